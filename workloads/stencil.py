@@ -1,0 +1,114 @@
+"""7-point stencils of the synthetic workloads, in the solver's input layout.
+
+Layout: ``coef[7, nz, ny, nx]`` float64 with slot order
+``C, W(i-1), E(i+1), S(j-1), N(j+1), B(k-1), T(k+1)`` so that, for the natural
+index r = (k*ny + j)*nx + i,
+
+    (A u)_r = C u_r + W u_{r-1} + E u_{r+1} + S u_{r-nx} + N u_{r+nx}
+              + B u_{r-nx*ny} + T u_{r+nx*ny}.
+
+Entries that would reach outside the grid are zero.  Grouping the unknowns by
+plane k gives the block-tridiagonal matrix of Eq. (originalMatrix): D_k is the
+5-point operator of plane k, E_k = diag(B[k]) and F_k = diag(T[k]).
+
+Discretisation (the paper leaves the variable-coefficient scheme open):
+vertex-centred, h = 1/(n+1); the coefficient on the face between nodes r and s
+is the harmonic mean 2 k_r k_s / (k_r + k_s); a face to the Dirichlet boundary
+uses k_r; (A u)_r = h^-2 [ sum_s k_rs (u_r - u_s) + n_b(r) k_r u_r ].
+Convection is first-order upwind; Helmholtz is -Lap_h - (omega / c)^2.
+"""
+import numpy as np
+
+from . import fields
+
+SLOT_NAMES = ("C", "W", "E", "S", "N", "B", "T")
+# (slot of the lower neighbour, slot of the upper neighbour, array axis) for x, y, z
+_DIRS = ((1, 2, 2), (3, 4, 1), (5, 6, 0))
+
+
+def _shift_lower(a, axis):
+    """Value of the lower neighbour along ``axis`` (NaN where outside)."""
+    out = np.full_like(a, np.nan)
+    sl_dst = [slice(None)] * 3
+    sl_src = [slice(None)] * 3
+    sl_dst[axis] = slice(1, None)
+    sl_src[axis] = slice(None, -1)
+    out[tuple(sl_dst)] = a[tuple(sl_src)]
+    return out
+
+
+def _shift_upper(a, axis):
+    out = np.full_like(a, np.nan)
+    sl_dst = [slice(None)] * 3
+    sl_src = [slice(None)] * 3
+    sl_dst[axis] = slice(None, -1)
+    sl_src[axis] = slice(1, None)
+    out[tuple(sl_dst)] = a[tuple(sl_src)]
+    return out
+
+
+def diffusion_coef(kappa):
+    """Stencil of -div(kappa grad u) with harmonic-mean face coefficients."""
+    kappa = np.asarray(kappa, dtype=np.float64)
+    nz, ny, nx = kappa.shape
+    hs = {2: fields.grid_h(nx), 1: fields.grid_h(ny), 0: fields.grid_h(nz)}
+    coef = np.zeros((7,) + kappa.shape)
+    for lo, up, ax in _DIRS:
+        ih2 = 1.0 / hs[ax] ** 2
+        for slot, nb in ((lo, _shift_lower(kappa, ax)), (up, _shift_upper(kappa, ax))):
+            inside = ~np.isnan(nb)
+            kf = np.where(inside, 2.0 * kappa * np.where(inside, nb, 1.0)
+                          / (kappa + np.where(inside, nb, 1.0)), kappa)
+            coef[0] += ih2 * kf
+            coef[slot] = np.where(inside, -ih2 * kf, 0.0)
+    return coef
+
+
+def add_upwind_convection(coef, b):
+    """Add b . grad u, first-order upwind; ``b`` has shape (3, nz, ny, nx) in (x, y, z) order."""
+    coef = coef.copy()
+    nz, ny, nx = coef.shape[1:]
+    hs = {2: fields.grid_h(nx), 1: fields.grid_h(ny), 0: fields.grid_h(nz)}
+    for comp, (lo, up, ax) in enumerate(_DIRS):
+        bd = b[comp]
+        pos = np.maximum(bd, 0.0) / hs[ax]
+        neg = np.minimum(bd, 0.0) / hs[ax]
+        coef[0] += pos - neg
+        lower_inside = ~np.isnan(_shift_lower(np.zeros_like(bd), ax))
+        upper_inside = ~np.isnan(_shift_upper(np.zeros_like(bd), ax))
+        coef[lo] += np.where(lower_inside, -pos, 0.0)
+        coef[up] += np.where(upper_inside, neg, 0.0)
+    return coef
+
+
+def helmholtz_coef(c, omega):
+    """Stencil of -Lap_h u - (omega / c)^2 u (indefinite for large omega)."""
+    coef = diffusion_coef(np.ones_like(c, dtype=np.float64))
+    coef[0] -= (omega / c) ** 2
+    return coef
+
+
+PROBLEMS = ("poisson", "convdiff", "helmholtz", "laplace")
+
+
+def problem(kind, n, seed=None):
+    """Coefficient array of a named workload on an n^3 grid.
+
+    ``poisson``: -div(kappa grad u), kappa lognormal (seed 0 unless given).
+    ``convdiff``: the same diffusion plus divergence-free upwind convection at
+    cell Peclet <= 1 (velocity seed 2).  ``helmholtz``: -Lap u - (omega/c)^2 u
+    with c = 1 + 0.3 * smoothed noise (seed 2), 10 points per wavelength.
+    ``laplace``: kappa = 1 (the constant-coefficient special case).
+    """
+    if kind == "laplace":
+        return diffusion_coef(np.ones((n, n, n)))
+    if kind == "helmholtz":
+        c = fields.helmholtz_speed(n, seed=fields.SEEDS["speed"] if seed is None else seed)
+        return helmholtz_coef(c, fields.helmholtz_omega(n))
+    kappa = fields.lognormal_kappa(n, seed=fields.SEEDS["kappa"] if seed is None else seed)
+    coef = diffusion_coef(kappa)
+    if kind == "poisson":
+        return coef
+    if kind == "convdiff":
+        return add_upwind_convection(coef, fields.divergence_free_velocity(kappa))
+    raise ValueError(f"unknown problem {kind!r}")
