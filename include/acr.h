@@ -1,0 +1,177 @@
+/*
+ * acr.h - accelerated cyclic reduction (ACR) on one MI355X (gfx950).
+ *
+ * Solves A u = f for the block-tridiagonal matrices of Eq. (originalMatrix)
+ * of Chavez et al., "Accelerated Cyclic Reduction" (Parallel Computing 2017):
+ * n_z plane blocks of size M = nx * ny coming from a 7-point stencil on an
+ * nx x ny x nz grid.  The factorisation is the red/black block cyclic
+ * reduction of Section 2.2 (Eq. elim, Algorithm 1) with every plane block held
+ * as a weak-admissibility hierarchical (HODLR) matrix truncated at a relative
+ * tolerance (Section 3.1); the solve is the forward reduction of the
+ * right-hand side and the back-substitution of Eq. all_backSubs / Algorithm 2.
+ *
+ * Conventions for every entry point:
+ *  - C linkage; no function throws; a failing call returns a status code and
+ *    leaves its outputs unspecified (handles are never partially created).
+ *  - Device pointers are HIP device addresses on the current device; sizes
+ *    are element counts.  Matrices are column-major.
+ *  - One handle may be used by one host thread at a time.  Calls are ordered
+ *    on the stream passed in; acr_factor synchronises that stream before it
+ *    returns, the solve calls do not (outputs are ready when the stream is).
+ */
+#ifndef ACR_H
+#define ACR_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct acr_factor_s* acr_handle_t;
+
+typedef enum {
+  ACR_SUCCESS = 0,
+  ACR_ERROR_INVALID_VALUE = 1,  /* bad option, null pointer, non-zero out-of-grid stencil entry */
+  ACR_ERROR_OUT_OF_MEMORY = 2,  /* device allocation (or the allocator callback) failed        */
+  ACR_ERROR_HIP = 3,            /* a HIP runtime call failed                                   */
+  ACR_ERROR_SINGULAR = 4,       /* zero / non-finite pivot in a leaf or capacitance inverse,  */
+                                /* or non-finite stencil values                               */
+  ACR_ERROR_RANK_CAPACITY = 5,  /* a truncated rank exceeded options.max_rank                  */
+  ACR_ERROR_NOT_CONVERGED = 6,  /* acr_solve_refined reached maxit above tol                   */
+  ACR_ERROR_NOT_SUPPORTED = 7
+} acr_status_t;
+
+typedef enum {
+  ACR_PREC_FP64 = 0,  /* factors stored and applied in FP64                              */
+  ACR_PREC_FP32 = 1   /* factors in FP32 (QR / products FP32, Jacobi SVD sweeps FP64)   */
+} acr_precision_t;
+
+typedef struct {
+  int32_t nx, ny, nplanes;   /* grid; M = nx * ny unknowns per plane, N = M * nplanes          */
+  double eps;                /* relative truncation tolerance per block, >= 0; 0 = exact      */
+  int32_t leaf;              /* maximum points per leaf cluster of the planar bisection, >= 1 */
+  int32_t max_rank;          /* cap on any truncated rank, 0 = none (exceeding it -> error)   */
+  int32_t precision;         /* acr_precision_t                                                */
+  double inner_eps_ratio;    /* accumulators inside one operation use eps * ratio; 0 -> 0.1   */
+  /* optional device allocator (e.g. a framework's caching allocator); both NULL -> hipMalloc */
+  void* (*alloc)(size_t bytes, void* ctx, hipStream_t stream);
+  void (*release)(void* ptr, void* ctx, hipStream_t stream);
+  void* alloc_ctx;
+} acr_options_t;
+
+/* Fills defaults: eps 1e-6, leaf 64, FP64, no rank cap, no allocator. Grid fields 0. */
+void acr_options_default(acr_options_t* opt);
+
+/*
+ * Factorisation (Algorithm 1 with the block-wise approximation of its first
+ * step).  coef: DEVICE, FP64, layout coef[7][nplanes][ny][nx], slot order
+ * {C, W(i-1), E(i+1), S(j-1), N(j+1), B(k-1), T(k+1)}:
+ *   (A u)_r = C u_r + W u_{r-1} + E u_{r+1} + S u_{r-nx} + N u_{r+nx}
+ *             + B u_{r-M} + T u_{r+M},   r = (k*ny + j)*nx + i.
+ * D_k is the 5-point part of plane k, E_k = diag(B[k]), F_k = diag(T[k]).
+ * Entries reaching outside the grid must be 0.  coef is read during the call
+ * only; the handle keeps its own FP64 copy for residuals.  On success *out is
+ * a new handle owning all factor memory; on failure *out is NULL.
+ */
+acr_status_t acr_factor(const acr_options_t* opt, const double* coef, hipStream_t stream,
+                        acr_handle_t* out);
+
+/*
+ * x = M^{-1} b, M the truncated factorisation (forward reduction of b by
+ * Eq. elim, then Eq. all_backSubs).  b, x: DEVICE, FP64, N x nrhs column-major
+ * with leading dimensions ldb, ldx >= N, natural ordering r as above; x may
+ * alias b.  Stream-ordered; the launch sequence is captured in a HIP graph on
+ * the first call for each nrhs and replayed afterwards.
+ */
+acr_status_t acr_solve(acr_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+                       hipStream_t stream);
+
+/*
+ * x = M^{-T} b with the same factors: the cyclic reduction of A^T, whose level
+ * blocks are (D_j^T, F_{j-1}^T, E_{j+1}^T), applied with transposed blocks.
+ * Exactly the transpose of the operator acr_solve applies (up to rounding).
+ */
+acr_status_t acr_solve_transpose(acr_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                                 int64_t ldx, hipStream_t stream);
+
+/* Releases the handle and all its memory after synchronising its last stream. NULL-safe. */
+void acr_free(acr_handle_t h);
+
+typedef struct {
+  int32_t levels;            /* cyclic-reduction levels q                                  */
+  int32_t depth;             /* HODLR depth L of every plane block                         */
+  int32_t max_rank;          /* largest stored rank                                        */
+  double avg_rank;           /* mean rank over stored off-diagonal blocks                  */
+  double factor_bytes;       /* bytes of the stored factors (G, E, F of every level)       */
+  double factor_seconds;     /* wall time of acr_factor                                    */
+  double solve_bytes;        /* algorithmic bytes one acr_solve with nrhs = 1 moves         */
+  double flops_gemm, flops_qr, flops_svd, flops_inverse;  /* launched work in acr_factor */
+  int64_t launches;          /* kernel launches issued by acr_factor                       */
+  int32_t level_max_rank[32];
+  double level_avg_rank[32];
+} acr_stats_t;
+
+acr_status_t acr_get_stats(acr_handle_t h, acr_stats_t* st);
+
+typedef struct {
+  int32_t method;      /* 0: iterative refinement x += M^{-1} r; 1: right-preconditioned GMRES */
+  int32_t restart;     /* GMRES restart length (default 30)                                  */
+  int32_t maxit;       /* maximum preconditioner applications (default 200)                  */
+  double tol;          /* stop when ||b - A x||_2 / ||b||_2 <= tol (FP64 residual)           */
+  int32_t transpose;   /* 1: solve A^T x = b with M^{-T} as preconditioner                   */
+} acr_refine_options_t;
+
+typedef struct {
+  int32_t iterations;  /* preconditioner applications                                        */
+  int32_t converged;
+  double relres;       /* final true FP64 relative residual                                  */
+  double relres0;      /* relative residual of the first preconditioned solve               */
+} acr_refine_result_t;
+
+/*
+ * FP64 refined solve of A x = b (or A^T x = b) for one right-hand side, the
+ * factorisation used as preconditioner (Section 5: a low-accuracy factorisation
+ * combined with an iteration).  b, x: DEVICE FP64 length N (x must not alias b).
+ * The residual uses the handle's FP64 stencil.  history (host, optional) gets
+ * up to history_len relative residual estimates.  Synchronises the stream.
+ * Returns ACR_ERROR_NOT_CONVERGED (with x = last iterate) when maxit is hit.
+ */
+acr_status_t acr_solve_refined(acr_handle_t h, const acr_refine_options_t* ro, const double* b, double* x,
+                               hipStream_t stream, acr_refine_result_t* res, double* history,
+                               int32_t history_len);
+
+/* r = b - A x (or b - A^T x) in FP64 with the handle's stencil; DEVICE vectors of length N. */
+acr_status_t acr_residual(acr_handle_t h, const double* x, const double* b, double* r, int32_t transpose,
+                          hipStream_t stream);
+
+/*
+ * Stencil of -div(kappa grad u) on the unit cube, vertex-centred, h = 1/(n+1)
+ * per axis, face coefficient = harmonic mean of the two nodal kappa, boundary
+ * faces weighted by the nodal kappa (the variable-coefficient model problem of
+ * Section 2.2.1).  kappa: DEVICE FP64 [nz][ny][nx]; coef: DEVICE FP64, layout
+ * as in acr_factor.  Stream-ordered.
+ */
+acr_status_t acr_assemble_diffusion(int32_t nx, int32_t ny, int32_t nz, const double* kappa, double* coef,
+                                    hipStream_t stream);
+
+/*
+ * Gradient of a scalar L with respect to the nodal kappa of
+ * acr_assemble_diffusion, given the state u (A u = f) and the adjoint lam
+ * (A^T lam = dL/du): grad_c = -lam^T (dA/dkappa_c) u.  All DEVICE FP64 length
+ * N.  Stream-ordered.
+ */
+acr_status_t acr_kappa_gradient(int32_t nx, int32_t ny, int32_t nz, const double* kappa, const double* u,
+                                const double* lam, double* grad, hipStream_t stream);
+
+const char* acr_status_string(acr_status_t s);
+
+/* Text of the last failure on the calling host thread ("" if none); valid until the next call. */
+const char* acr_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ACR_H */

@@ -1,0 +1,813 @@
+// Accelerated cyclic reduction: factorisation driver, solves and the C ABI.
+//
+// Factorisation (Algorithm 1 and Eq. elim): the plane blocks are converted to
+// HODLR form (the block-wise approximation of the algorithm's first step), then
+// for every level the eliminated planes (even positions) are inverted,
+// X = G E and Y = G F are formed, and every kept plane receives
+//   E+ = -E X_{j-1},  D+ = D - E Y_{j-1} - F X_{j+1},  F+ = -F Y_{j+1},
+// each product and sum truncated.  Every HODLR operation is batched over all
+// planes of the level.
+//
+// Solve (Eq. elim last line, Eq. all_backSubs, Algorithm 2): forward
+// reduction of the right-hand sides level by level, the last plane, then the
+// back-substitution.  The launch sequence of a solve is recorded once per
+// (nrhs, transpose) with persistent task arrays, captured into a HIP graph and
+// replayed.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+
+#include "../../include/acr.h"
+#include "hodlr.h"
+#include "stencil.h"
+
+namespace acr {
+
+namespace {
+
+struct Plan {
+  std::vector<std::function<void(hipStream_t)>> launches;
+  Arena mem;
+  void* W = nullptr;    // permuted right-hand sides / reduced right-hand sides
+  void* Ub = nullptr;   // solution per plane, cluster order
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int nrhs = 0;
+  bool trans = false;
+};
+
+struct FactorBase {
+  virtual ~FactorBase() = default;
+  virtual void solve(int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, bool trans,
+                     hipStream_t s) = 0;
+  virtual void stats(acr_stats_t* st) = 0;
+  Grid grid{};
+  Exec ex;
+  double* coef = nullptr;   // FP64 stencil copy
+  Arena persist;            // factors, stencil copy, plans' small data
+  Arena refine_mem;         // Krylov workspace of acr_solve_refined
+  int refine_cap = -1;
+  hipStream_t last_stream = nullptr;
+};
+
+template <class T> struct Level {
+  std::vector<int> alive;
+  std::vector<HMat<T>> G, E, F;
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <class T> struct FactorT : FactorBase {
+  Tree tr;
+  Trunc tc;
+  std::vector<Level<T>> lev;
+  HMat<T> Glast;
+  int last = 0;
+  Arena fac, lvl[2], levtmp, work, tmp;
+  int* d_perm = nullptr;
+  std::vector<std::unique_ptr<Plan>> plans;
+  double t_factor = 0;
+  bool use_graph = true;
+
+  void destroy_all() {
+    for (auto& p : plans) {
+      if (p->exec) (void)hipGraphExecDestroy(p->exec);
+      if (p->graph) (void)hipGraphDestroy(p->graph);
+      p->mem.free_all();
+    }
+    plans.clear();
+    fac.free_all();
+    lvl[0].free_all();
+    lvl[1].free_all();
+    levtmp.free_all();
+    work.free_all();
+    tmp.free_all();
+    refine_mem.free_all();
+    persist.free_all();
+  }
+  ~FactorT() override {
+    destroy_all();
+    ex.destroy();
+  }
+
+  // ---------------------------------------------------------- level 0
+  // D_k: dense leaves from the 5-point plane stencil; each off-diagonal block
+  // is the exact coupling across one cut, a scaled partial permutation whose
+  // singular values are the coupling magnitudes, so its truncation keeps the
+  // couplings with |a| > eps * max |a| of that block.
+  void convert(std::vector<HMat<T>>& D, std::vector<HMat<T>>& E, std::vector<HMat<T>>& F) {
+    const int M = tr.M, L = tr.L, nz = grid.nz, nx = tr.nx, ny = tr.ny;
+    std::vector<int> iperm(M);
+    for (int p = 0; p < M; ++p) iperm[tr.perm[p]] = p;
+    std::vector<std::vector<int>> seg_of(L + 1, std::vector<int>(M));
+    for (int d = 0; d <= L; ++d)
+      for (int s = 0; s < (1 << d); ++s)
+        for (int p = tr.off[d][s]; p < tr.off[d][s] + tr.sz[d][s]; ++p) seg_of[d][p] = s;
+    std::vector<LeafEnt> le;
+    std::vector<std::vector<CutEnt>> cut(tr.nblk());
+    const int nbr[4][3] = {{1, -1, 0}, {2, 1, 0}, {3, 0, -1}, {4, 0, 1}};
+    for (int a = 0; a < M; ++a) {
+      const int nat = tr.perm[a], i = nat % nx, j = nat / nx;
+      const int la = seg_of[L][a], lo = tr.off[L][la], ln = tr.sz[L][la];
+      le.push_back(LeafEnt{la, a - lo, a - lo, ln, 0, nat});
+      for (auto& nb : nbr) {
+        const int ii = i + nb[1], jj = j + nb[2];
+        if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
+        const int b = iperm[jj * nx + ii];
+        if (seg_of[L][b] == la) {
+          le.push_back(LeafEnt{la, a - lo, b - lo, ln, nb[0], nat});
+          continue;
+        }
+        int d = 0;
+        while (seg_of[d + 1][a] == seg_of[d + 1][b]) ++d;
+        const int s = seg_of[d + 1][a];
+        cut[Tree::bid(d, s)].push_back(CutEnt{a - tr.off[d + 1][s], b - tr.off[d + 1][s ^ 1], nb[0], nat});
+      }
+    }
+    std::vector<CutEnt> ents;
+    std::vector<int> first(tr.nblk() + 1, 0), rows(tr.nblk()), cols(tr.nblk());
+    for (int d = 0; d < L; ++d)
+      for (int s = 0; s < (2 << d); ++s) {
+        const int b = Tree::bid(d, s);
+        rows[b] = tr.sz[d + 1][s];
+        cols[b] = tr.sz[d + 1][s ^ 1];
+      }
+    for (int b = 0; b < tr.nblk(); ++b) {
+      first[b] = (int)ents.size();
+      ents.insert(ents.end(), cut[b].begin(), cut[b].end());
+    }
+    first[tr.nblk()] = (int)ents.size();
+    const int nleaf = 1 << L, nblk = tr.nblk();
+    D.assign(nz, HMat<T>{});
+    std::vector<T*> lp((size_t)nz * nleaf);
+    std::vector<CopyTask> zero;
+    for (int k = 0; k < nz; ++k) {
+      hodlr_alloc_leaves(tr, D[k], lvl[0]);
+      for (int s = 0; s < nleaf; ++s) {
+        lp[(size_t)k * nleaf + s] = D[k].leaf[s];
+        const int n = tr.sz[L][s];
+        CopyTask c{};
+        c.dst = D[k].leaf[s]; c.ldd = n; c.m = n; c.n = n; c.alpha = 0.0;
+        zero.push_back(c);
+      }
+    }
+    ex.copy<T>(zero);
+    zero.clear();
+    const LeafEnt* d_le = ex.upload(le);
+    T* const* d_lp = ex.upload(lp);
+    const int nle = (int)le.size();
+    const double* cf = coef;
+    Grid g = grid;
+    ex.submit([=](hipStream_t s) { launch_conv_leaves<T>(g, cf, d_le, nle, d_lp, nleaf, s); });
+    if (nblk > 0) {
+      const CutEnt* d_ce = ents.empty() ? nullptr : ex.upload(ents);
+      const int* d_first = ex.upload(first);
+      const int* d_rows = ex.upload(rows);
+      const int* d_cols = ex.upload(cols);
+      int* d_rank = tmp.get_n<int>((size_t)nz * nblk);
+      const double eps = tc.eps;
+      ex.submit([=](hipStream_t s) { launch_cut_rank(g, cf, d_ce, d_first, nblk, eps, d_rank, s); });
+      std::vector<int> rk((size_t)nz * nblk);
+      hip_check(hipMemcpyAsync(rk.data(), d_rank, rk.size() * sizeof(int), hipMemcpyDeviceToHost, ex.stream),
+                "hipMemcpyAsync(cut ranks)");
+      ex.sync();
+      std::vector<T*> up((size_t)nz * nblk, nullptr), vp((size_t)nz * nblk, nullptr);
+      for (int k = 0; k < nz; ++k)
+        for (int b = 0; b < nblk; ++b) {
+          const int r = rk[(size_t)k * nblk + b];
+          if (tc.max_rank > 0 && r > tc.max_rank) throw Failure(ST_RANK, "level-0 cut rank exceeds max_rank");
+          LR<T>& blk = D[k].blk[b];
+          blk.k = r;
+          if (r == 0) continue;
+          blk.U = lvl[0].get_n<T>((size_t)rows[b] * r);
+          blk.V = lvl[0].get_n<T>((size_t)cols[b] * r);
+          up[(size_t)k * nblk + b] = blk.U;
+          vp[(size_t)k * nblk + b] = blk.V;
+          CopyTask c{};
+          c.dst = blk.U; c.ldd = rows[b]; c.m = rows[b]; c.n = r;
+          zero.push_back(c);
+          c.dst = blk.V; c.ldd = cols[b]; c.m = cols[b];
+          zero.push_back(c);
+        }
+      ex.copy<T>(zero);
+      T* const* d_up = ex.upload(up);
+      T* const* d_vp = ex.upload(vp);
+      ex.submit([=](hipStream_t s) {
+        launch_cut_fill<T>(g, cf, d_ce, d_first, nblk, eps, d_up, d_vp, d_rows, d_cols, s);
+      });
+    }
+    E.assign(nz, HMat<T>{});
+    F.assign(nz, HMat<T>{});
+    T* eb = fac.get_n<T>((size_t)nz * M);
+    T* fb = fac.get_n<T>((size_t)nz * M);
+    const int* dp = d_perm;
+    ex.submit([=](hipStream_t s) {
+      launch_diag<T>(g, cf, 5, dp, eb, s);
+      launch_diag<T>(g, cf, 6, dp, fb, s);
+    });
+    for (int k = 0; k < nz; ++k) {
+      if (k > 0) { E[k].kind = HMat<T>::DIAG; E[k].diag = eb + (size_t)k * M; }
+      if (k + 1 < nz) { F[k].kind = HMat<T>::DIAG; F[k].diag = fb + (size_t)k * M; }
+    }
+  }
+
+  // ---------------------------------------------------------- factor
+  void factor() {
+    const double t0 = now_s();
+    std::vector<HMat<T>> D, E, F;
+    convert(D, E, F);
+    std::vector<int> alive(grid.nz);
+    for (int k = 0; k < grid.nz; ++k) alive[k] = k;
+    int cur = 0;
+    while (alive.size() > 1) {
+      const int m = (int)alive.size();
+      Level<T> L;
+      L.alive = alive;
+      L.E = E;
+      L.F = F;
+      L.G.assign(m, HMat<T>{});
+      // inverses of the eliminated planes
+      std::vector<const HMat<T>*> dv;
+      std::vector<HMat<T>*> gv;
+      for (int q = 0; q < m; q += 2) {
+        dv.push_back(&D[q]);
+        gv.push_back(&L.G[q]);
+      }
+      hodlr_inverse<T>(ex, tr, dv, gv, tc, fac, work, tmp);
+      // X = G E, Y = G F
+      std::vector<HMat<T>> X(m), Y(m);
+      std::vector<ProdJob<T>> pj;
+      for (int q = 0; q < m; q += 2) {
+        if (!E[q].absent()) pj.push_back(ProdJob<T>{&L.G[q], &E[q], &X[q], 1.0});
+        if (!F[q].absent()) pj.push_back(ProdJob<T>{&L.G[q], &F[q], &Y[q], 1.0});
+      }
+      hodlr_product<T>(ex, tr, pj, tc, levtmp, work, tmp);
+      // kept planes
+      const int mk = m / 2;
+      std::vector<HMat<T>> nE(mk), nF(mk), nD(mk), P1(mk), P2(mk);
+      // E+ and F+ are stored for the solve; P1 = E Y and P2 = F X only feed D+
+      std::vector<ProdJob<T>> keep, temp;
+      for (int q = 1; q < m; q += 2) {
+        const int o = q / 2;
+        if (!X[q - 1].absent()) keep.push_back(ProdJob<T>{&E[q], &X[q - 1], &nE[o], -1.0});
+        if (!Y[q - 1].absent()) temp.push_back(ProdJob<T>{&E[q], &Y[q - 1], &P1[o], 1.0});
+        if (q + 1 < m) {
+          if (!Y[q + 1].absent()) keep.push_back(ProdJob<T>{&F[q], &Y[q + 1], &nF[o], -1.0});
+          if (!X[q + 1].absent()) temp.push_back(ProdJob<T>{&F[q], &X[q + 1], &P2[o], 1.0});
+        }
+      }
+      hodlr_product<T>(ex, tr, keep, tc, fac, work, tmp);
+      hodlr_product<T>(ex, tr, temp, tc, levtmp, work, tmp);
+      std::vector<SumJob<T>> sj;
+      for (int o = 0; o < mk; ++o) {
+        SumJob<T> s;
+        s.terms.push_back({&D[2 * o + 1], 1.0});
+        if (!P1[o].absent()) s.terms.push_back({&P1[o], -1.0});
+        if (!P2[o].absent()) s.terms.push_back({&P2[o], -1.0});
+        s.C = &nD[o];
+        sj.push_back(s);
+      }
+      const int nxt = cur ^ 1;
+      lvl[nxt].reset();
+      hodlr_sum<T>(ex, tr, sj, tc, lvl[nxt], tmp);
+      lev.push_back(std::move(L));
+      levtmp.reset();
+      std::vector<int> na;
+      for (int q = 1; q < m; q += 2) na.push_back(alive[q]);
+      alive = na;
+      D = std::move(nD);
+      E = std::move(nE);
+      F = std::move(nF);
+      cur = nxt;
+    }
+    last = alive[0];
+    {
+      std::vector<const HMat<T>*> dv{&D[0]};
+      std::vector<HMat<T>*> gv{&Glast};
+      hodlr_inverse<T>(ex, tr, dv, gv, tc, fac, work, tmp);
+    }
+    int fl[NFLAGS];
+    ex.read_flags(fl);
+    lvl[0].free_all();
+    lvl[1].free_all();
+    levtmp.free_all();
+    work.free_all();
+    tmp.free_all();
+    if (fl[FLAG_SINGULAR]) throw Failure(ST_SINGULAR, "zero or non-finite pivot in a block inverse");
+    if (fl[FLAG_RANK]) throw Failure(ST_RANK, "truncated rank exceeds max_rank");
+    t_factor = now_s() - t0;
+  }
+
+  // ---------------------------------------------------------- solve plans
+  Plan* plan_for(int nrhs, bool trans) {
+    for (auto& p : plans)
+      if (p->nrhs == nrhs && p->trans == trans) return p.get();
+    auto pl = std::make_unique<Plan>();
+    pl->nrhs = nrhs;
+    pl->trans = trans;
+    pl->mem.init(&ex, size_t(64) << 20);
+    const int M = tr.M, nz = grid.nz, c = nrhs;
+    const size_t pane = (size_t)M * c;
+    T* W = pl->mem.get_n<T>(pane * nz);
+    T* Ub = pl->mem.get_n<T>(pane * nz);
+    T* Gb = pl->mem.get_n<T>(pane * ((nz + 1) / 2));
+    pl->W = W;
+    pl->Ub = Ub;
+    ex.rec = &pl->launches;
+    ex.rec_arena = &pl->mem;
+    try {
+      auto Wp = [&](int plane) { return W + pane * plane; };
+      auto Up = [&](int plane) { return Ub + pane * plane; };
+      auto Gp = [&](int q) { return Gb + pane * (q / 2); };
+      for (auto& L : lev) {
+        const int m = (int)L.alive.size();
+        std::vector<MVJob<T>> jg, je, jf;
+        for (int q = 0; q < m; q += 2) jg.push_back(MVJob<T>{&L.G[q], nullptr, Wp(L.alive[q]), M, Gp(q), M, c, 1.0, 0.0});
+        for (int q = 1; q < m; q += 2) {
+          const HMat<T>* left = trans ? &L.F[q - 1] : &L.E[q];
+          je.push_back(MVJob<T>{left, nullptr, Gp(q - 1), M, Wp(L.alive[q]), M, c, -1.0, 1.0});
+          if (q + 1 < m) {
+            const HMat<T>* right = trans ? &L.E[q + 1] : &L.F[q];
+            jf.push_back(MVJob<T>{right, nullptr, Gp(q + 1), M, Wp(L.alive[q]), M, c, -1.0, 1.0});
+          }
+        }
+        hodlr_multivec<T>(ex, tr, jg, trans, 0, pl->mem);
+        hodlr_multivec<T>(ex, tr, je, trans, 0, pl->mem);
+        hodlr_multivec<T>(ex, tr, jf, trans, 0, pl->mem);
+      }
+      {
+        std::vector<MVJob<T>> j1{MVJob<T>{&Glast, nullptr, Wp(last), M, Up(last), M, c, 1.0, 0.0}};
+        hodlr_multivec<T>(ex, tr, j1, trans, 0, pl->mem);
+      }
+      for (int li = (int)lev.size() - 1; li >= 0; --li) {
+        auto& L = lev[li];
+        const int m = (int)L.alive.size();
+        std::vector<CopyTask> cp;
+        std::vector<MVJob<T>> je, jf, jg;
+        for (int q = 0; q < m; q += 2) {
+          CopyTask t{};
+          t.src = Wp(L.alive[q]); t.dst = Gp(q); t.lds = M; t.ldd = M; t.m = M; t.n = c; t.alpha = 1.0;
+          cp.push_back(t);
+          if (q - 1 >= 0) {
+            const HMat<T>* left = trans ? &L.F[q - 1] : &L.E[q];
+            je.push_back(MVJob<T>{left, nullptr, Up(L.alive[q - 1]), M, Gp(q), M, c, -1.0, 1.0});
+          }
+          if (q + 1 < m) {
+            const HMat<T>* right = trans ? &L.E[q + 1] : &L.F[q];
+            jf.push_back(MVJob<T>{right, nullptr, Up(L.alive[q + 1]), M, Gp(q), M, c, -1.0, 1.0});
+          }
+          jg.push_back(MVJob<T>{&L.G[q], nullptr, Gp(q), M, Up(L.alive[q]), M, c, 1.0, 0.0});
+        }
+        ex.copy<T>(cp);
+        hodlr_multivec<T>(ex, tr, je, trans, 0, pl->mem);
+        hodlr_multivec<T>(ex, tr, jf, trans, 0, pl->mem);
+        hodlr_multivec<T>(ex, tr, jg, trans, 0, pl->mem);
+      }
+    } catch (...) {
+      ex.rec = nullptr;
+      ex.rec_arena = nullptr;
+      throw;
+    }
+    ex.rec = nullptr;
+    ex.rec_arena = nullptr;
+    plans.push_back(std::move(pl));
+    return plans.back().get();
+  }
+
+  void run_plan(Plan* pl, hipStream_t s) {
+    if (use_graph && !pl->exec && !pl->graph) {
+      bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        for (auto& f : pl->launches) f(s);
+        ok = hipStreamEndCapture(s, &pl->graph) == hipSuccess && pl->graph;
+        if (ok) ok = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) == hipSuccess;
+      }
+      if (!ok) {
+        (void)hipGetLastError();
+        if (pl->graph) (void)hipGraphDestroy(pl->graph);
+        pl->graph = nullptr;
+        pl->exec = nullptr;
+        use_graph = false;
+      }
+    }
+    if (pl->exec) {
+      hip_check(hipGraphLaunch(pl->exec, s), "hipGraphLaunch");
+    } else {
+      for (auto& f : pl->launches) f(s);
+      hip_check(hipGetLastError(), "solve launch");
+    }
+  }
+
+  void solve(int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, bool trans, hipStream_t s) override {
+    ex.stream = s;
+    Plan* pl = plan_for(nrhs, trans);
+    launch_perm_in<T>(grid, nrhs, b, ldb, d_perm, static_cast<T*>(pl->W), s);
+    hip_check(hipGetLastError(), "perm_in");
+    run_plan(pl, s);
+    launch_perm_out<T>(grid, nrhs, static_cast<const T*>(pl->Ub), d_perm, x, ldx, s);
+    hip_check(hipGetLastError(), "perm_out");
+    last_stream = s;
+  }
+
+  // ---------------------------------------------------------- statistics
+  void stats(acr_stats_t* st) override {
+    std::memset(st, 0, sizeof(*st));
+    st->levels = (int)lev.size();
+    st->depth = tr.L;
+    double words = 0, solve_words = 0, rsum = 0, rcnt = 0;
+    auto acc = [&](const HMat<T>& H, int li, double reads) {
+      if (H.absent()) return;
+      const double w = (double)H.words(tr);
+      words += w;
+      solve_words += reads * w;
+      if (H.kind != HMat<T>::HODLR) return;
+      for (auto& b : H.blk) {
+        st->max_rank = std::max(st->max_rank, b.k);
+        if (li < 32) st->level_max_rank[li] = std::max(st->level_max_rank[li], b.k);
+        rsum += b.k;
+        rcnt += 1;
+      }
+    };
+    std::vector<double> lsum(33, 0.0), lcnt(33, 0.0);
+    for (int li = 0; li < (int)lev.size(); ++li) {
+      const auto& L = lev[li];
+      const int m = (int)L.alive.size();
+      const double r0 = rsum, c0 = rcnt;
+      for (int q = 0; q < m; ++q) {
+        if (q % 2 == 0) acc(L.G[q], li, 2.0);
+        acc(L.E[q], li, 1.0);
+        acc(L.F[q], li, 1.0);
+      }
+      if (li < 32) st->level_avg_rank[li] = rcnt > c0 ? (rsum - r0) / (rcnt - c0) : 0.0;
+    }
+    acc(Glast, (int)lev.size(), 1.0);
+    st->avg_rank = rcnt > 0 ? rsum / rcnt : 0.0;
+    st->factor_bytes = words * sizeof(T);
+    // vectors: every multivec reads its input and updates its output once per level
+    solve_words += 6.0 * (double)grid.N();
+    st->solve_bytes = solve_words * sizeof(T);
+    st->factor_seconds = t_factor;
+    st->flops_gemm = ex.flops_gemm;
+    st->flops_qr = ex.flops_qr;
+    st->flops_svd = ex.flops_svd;
+    st->flops_inverse = ex.flops_inv;
+    st->launches = ex.launches;
+  }
+};
+
+acr_status_t to_status(int s) { return static_cast<acr_status_t>(s); }
+
+template <class T>
+FactorBase* make_factor(const acr_options_t* o, const double* coef_in, hipStream_t s) {
+  auto f = std::make_unique<FactorT<T>>();
+  Allocator al;
+  al.alloc = o->alloc;
+  al.release = o->release;
+  al.ctx = o->alloc_ctx;
+  f->ex.init(s, al);
+  f->grid = Grid{o->nx, o->ny, o->nplanes};
+  f->persist.init(&f->ex, size_t(32) << 20);
+  f->refine_mem.init(&f->ex, size_t(64) << 20);
+  const size_t big = size_t(512) << 20;
+  f->fac.init(&f->ex, big);
+  f->lvl[0].init(&f->ex, big);
+  f->lvl[1].init(&f->ex, big);
+  f->levtmp.init(&f->ex, big);
+  f->work.init(&f->ex, big);
+  f->tmp.init(&f->ex, big);
+  if (!f->tr.build(o->nx, o->ny, o->leaf)) throw Failure(ST_INVALID, "leaf size forces a split of a single point");
+  f->tc.eps = o->eps;
+  f->tc.eps_inner = o->eps * (o->inner_eps_ratio > 0 ? o->inner_eps_ratio : 0.1);
+  f->tc.max_rank = o->max_rank;
+  const char* ng = std::getenv("ACR_NO_GRAPH");
+  f->use_graph = !(ng && ng[0] == '1');
+  const int64_t N = f->grid.N();
+  f->coef = f->persist.template get_n<double>(7 * (size_t)N);
+  hip_check(hipMemcpyAsync(f->coef, coef_in, 7 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s),
+            "hipMemcpyAsync(coef)");
+  f->d_perm = f->persist.template get_n<int>(f->tr.M);
+  hip_check(hipMemcpyAsync(f->d_perm, f->tr.perm.data(), f->tr.M * sizeof(int), hipMemcpyHostToDevice, s),
+            "hipMemcpyAsync(perm)");
+  launch_validate(f->grid, f->coef, f->ex.d_flags, s);
+  int fl[NFLAGS];
+  f->ex.read_flags(fl);
+  if (fl[FLAG_INVALID]) throw Failure(ST_INVALID, "stencil entry reaching outside the grid is non-zero");
+  if (fl[FLAG_NONFINITE]) throw Failure(ST_SINGULAR, "non-finite stencil value");
+  f->factor();
+  f->last_stream = s;
+  return f.release();
+}
+
+thread_local std::string g_last_error;
+
+// ---------------------------------------------------------------- refinement
+struct Krylov {
+  FactorBase& f;
+  hipStream_t s;
+  int64_t N;
+  int nblk;
+  double* part;
+  double* dres;
+  double* zero;
+  double host_dot(const double* x, const double* y) {
+    launch_multidot(N, 1, x, N, y, part, nblk, s);
+    launch_reduce_parts(1, part, nblk, dres, s);
+    double v = 0;
+    hip_check(hipMemcpyAsync(&v, dres, sizeof(double), hipMemcpyDeviceToHost, s), "hipMemcpyAsync(dot)");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return v;
+  }
+  void residual(const double* x, const double* b, double* r, int trans) {
+    launch_residual(f.grid, f.coef, x, b, r, trans, s);
+  }
+  void precond(const double* r, double* z, bool trans) { f.solve(1, r, N, z, N, trans, s); }
+};
+
+int refine(FactorBase& f, const acr_refine_options_t& ro, const double* b, double* x, hipStream_t s,
+           acr_refine_result_t* res, double* hist, int hlen) {
+  const int64_t N = f.grid.N();
+  const int m = ro.method == 1 ? std::max(1, ro.restart > 0 ? ro.restart : 30) : 1;
+  const int maxit = ro.maxit > 0 ? ro.maxit : 200;
+  const bool tr = ro.transpose != 0;
+  const int nblk = 512;
+  if (f.refine_cap != m) {
+    f.refine_mem.reset();
+    f.refine_cap = m;
+  }
+  f.refine_mem.reset();
+  double* V = f.refine_mem.get_n<double>((size_t)(m + 1) * N);
+  double* Z = f.refine_mem.get_n<double>((size_t)m * N);
+  double* r = f.refine_mem.get_n<double>(N);
+  double* w = f.refine_mem.get_n<double>(N);
+  double* zero = f.refine_mem.get_n<double>(N);
+  double* part = f.refine_mem.get_n<double>((size_t)(m + 2) * nblk);
+  double* dh = f.refine_mem.get_n<double>(2 * (m + 2) + 2);
+  Krylov K{f, s, N, nblk, part, dh + 2 * (m + 2), zero};
+  launch_axpby(N, 0.0, zero, 0.0, zero, s);
+  const double bn = std::sqrt(K.host_dot(b, b));
+  int it = 0, nh = 0;
+  auto log = [&](double v) { if (hist && nh < hlen) hist[nh++] = v; };
+  if (bn == 0.0) {
+    launch_axpby(N, 0.0, zero, 0.0, x, s);
+    hip_check(hipStreamSynchronize(s), "sync");
+    if (res) *res = acr_refine_result_t{0, 1, 0.0, 0.0};
+    return ST_SUCCESS;
+  }
+  // x0 = M^{-1} b
+  K.precond(b, x, tr);
+  ++it;
+  K.residual(x, b, r, tr);
+  double rel = std::sqrt(K.host_dot(r, r)) / bn;
+  const double rel0 = rel;
+  log(rel);
+  if (ro.method != 1) {
+    while (rel > ro.tol && it < maxit) {
+      K.precond(r, w, tr);
+      ++it;
+      launch_axpby(N, 1.0, w, 1.0, x, s);
+      K.residual(x, b, r, tr);
+      rel = std::sqrt(K.host_dot(r, r)) / bn;
+      log(rel);
+      if (!std::isfinite(rel)) break;
+    }
+  } else {
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hb(2 * (m + 1) + 1);
+    while (rel > ro.tol && it < maxit) {
+      const double beta = rel * bn;
+      launch_axpby(N, 1.0 / beta, r, 0.0, V, s);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int jd = 0;
+      double est = rel;
+      for (int j = 0; j < m && it < maxit; ++j) {
+        double* vj = V + (size_t)j * N;
+        double* zj = Z + (size_t)j * N;
+        K.precond(vj, zj, tr);
+        ++it;
+        // w = A z_j  (residual of 0 gives -A z)
+        K.residual(zj, zero, w, tr);
+        launch_axpby(N, -1.0, w, 0.0, w, s);
+        // classical Gram-Schmidt, twice
+        launch_multidot(N, j + 1, V, N, w, part, nblk, s);
+        launch_reduce_parts(j + 1, part, nblk, dh, s);
+        launch_gemv_sub(N, j + 1, V, N, dh, w, s);
+        launch_multidot(N, j + 1, V, N, w, part, nblk, s);
+        launch_reduce_parts(j + 1, part, nblk, dh + (m + 1), s);
+        launch_gemv_sub(N, j + 1, V, N, dh + (m + 1), w, s);
+        launch_multidot(N, 1, w, N, w, part, nblk, s);
+        launch_reduce_parts(1, part, nblk, dh + 2 * (m + 1), s);
+        hip_check(hipMemcpyAsync(hb.data(), dh, hb.size() * sizeof(double), hipMemcpyDeviceToHost, s),
+                  "hipMemcpyAsync(hessenberg)");
+        hip_check(hipStreamSynchronize(s), "sync");
+        double* hc = &H[(size_t)j * (m + 1)];
+        for (int i = 0; i <= j; ++i) hc[i] = hb[i] + hb[(m + 1) + i];
+        const double hn = std::sqrt(std::max(hb[2 * (m + 1)], 0.0));
+        hc[j + 1] = hn;
+        if (hn > 0.0) launch_axpby(N, 1.0 / hn, w, 0.0, V + (size_t)(j + 1) * N, s);
+        for (int i = 0; i < j; ++i) {
+          const double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
+          hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+          hc[i] = t;
+        }
+        const double den = std::hypot(hc[j], hc[j + 1]);
+        cs[j] = den > 0 ? hc[j] / den : 1.0;
+        sn[j] = den > 0 ? hc[j + 1] / den : 0.0;
+        hc[j] = den;
+        hc[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        jd = j + 1;
+        est = std::fabs(g[j + 1]) / bn;
+        log(est);
+        if (est <= ro.tol || hn == 0.0) break;
+      }
+      // y = H^{-1} g (upper triangular), x += Z y
+      std::vector<double> y(jd);
+      for (int i = jd - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int l = i + 1; l < jd; ++l) t -= H[(size_t)l * (m + 1) + i] * y[l];
+        y[i] = t / H[(size_t)i * (m + 1) + i];
+      }
+      for (auto& v : y) v = -v;
+      hip_check(hipMemcpyAsync(dh, y.data(), jd * sizeof(double), hipMemcpyHostToDevice, s), "hipMemcpyAsync(y)");
+      launch_gemv_sub(N, jd, Z, N, dh, x, s);
+      K.residual(x, b, r, tr);
+      rel = std::sqrt(K.host_dot(r, r)) / bn;
+      if (!std::isfinite(rel)) break;
+    }
+  }
+  hip_check(hipStreamSynchronize(s), "sync");
+  if (res) {
+    res->iterations = it;
+    res->converged = rel <= ro.tol ? 1 : 0;
+    res->relres = rel;
+    res->relres0 = rel0;
+  }
+  return rel <= ro.tol ? ST_SUCCESS : ST_NOT_CONVERGED;
+}
+
+}  // namespace
+}  // namespace acr
+
+struct acr_factor_s {
+  acr::FactorBase* impl;
+};
+
+using namespace acr;
+
+namespace {
+
+template <class F> acr_status_t guarded(F&& fn) {
+  try {
+    return fn();
+  } catch (const Failure& e) {
+    g_last_error = e.what();
+    return to_status(e.status);
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return ACR_ERROR_OUT_OF_MEMORY;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return ACR_ERROR_HIP;
+  }
+}
+
+bool valid_opts(const acr_options_t* o) {
+  if (!o) return false;
+  if (o->nx < 1 || o->ny < 1 || o->nplanes < 1 || o->leaf < 1) return false;
+  if (!(o->eps >= 0.0) || !std::isfinite(o->eps)) return false;
+  if (o->max_rank < 0) return false;
+  if (o->precision != ACR_PREC_FP64 && o->precision != ACR_PREC_FP32) return false;
+  if ((o->alloc == nullptr) != (o->release == nullptr)) return false;
+  if (!(o->inner_eps_ratio >= 0.0)) return false;
+  if ((int64_t)o->nx * o->ny > (int64_t)1 << 28) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void acr_options_default(acr_options_t* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->eps = 1e-6;
+  o->leaf = 64;
+  o->precision = ACR_PREC_FP64;
+  o->inner_eps_ratio = 0.1;
+}
+
+acr_status_t acr_factor(const acr_options_t* opt, const double* coef, hipStream_t stream, acr_handle_t* out) {
+  if (out) *out = nullptr;
+  if (!out || !coef || !valid_opts(opt)) return ACR_ERROR_INVALID_VALUE;
+  return guarded([&]() -> acr_status_t {
+    FactorBase* f = opt->precision == ACR_PREC_FP32 ? make_factor<float>(opt, coef, stream)
+                                                     : make_factor<double>(opt, coef, stream);
+    *out = new acr_factor_s{f};
+    return ACR_SUCCESS;
+  });
+}
+
+acr_status_t acr_solve(acr_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+                       hipStream_t stream) {
+  if (!h || !h->impl || nrhs < 0 || (nrhs > 0 && (!b || !x))) return ACR_ERROR_INVALID_VALUE;
+  const int64_t N = h->impl->grid.N();
+  if (nrhs > 0 && (ldb < N || ldx < N)) return ACR_ERROR_INVALID_VALUE;
+  if (nrhs == 0) return ACR_SUCCESS;
+  return guarded([&]() -> acr_status_t {
+    h->impl->solve(nrhs, b, ldb, x, ldx, false, stream);
+    return ACR_SUCCESS;
+  });
+}
+
+acr_status_t acr_solve_transpose(acr_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                                 int64_t ldx, hipStream_t stream) {
+  if (!h || !h->impl || nrhs < 0 || (nrhs > 0 && (!b || !x))) return ACR_ERROR_INVALID_VALUE;
+  const int64_t N = h->impl->grid.N();
+  if (nrhs > 0 && (ldb < N || ldx < N)) return ACR_ERROR_INVALID_VALUE;
+  if (nrhs == 0) return ACR_SUCCESS;
+  return guarded([&]() -> acr_status_t {
+    h->impl->solve(nrhs, b, ldb, x, ldx, true, stream);
+    return ACR_SUCCESS;
+  });
+}
+
+void acr_free(acr_handle_t h) {
+  if (!h) return;
+  if (h->impl) {
+    if (h->impl->last_stream) (void)hipStreamSynchronize(h->impl->last_stream);
+    delete h->impl;
+  }
+  delete h;
+}
+
+acr_status_t acr_get_stats(acr_handle_t h, acr_stats_t* st) {
+  if (!h || !h->impl || !st) return ACR_ERROR_INVALID_VALUE;
+  return guarded([&]() -> acr_status_t {
+    h->impl->stats(st);
+    return ACR_SUCCESS;
+  });
+}
+
+acr_status_t acr_residual(acr_handle_t h, const double* x, const double* b, double* r, int32_t transpose,
+                          hipStream_t stream) {
+  if (!h || !h->impl || !x || !b || !r) return ACR_ERROR_INVALID_VALUE;
+  return guarded([&]() -> acr_status_t {
+    launch_residual(h->impl->grid, h->impl->coef, x, b, r, transpose, stream);
+    hip_check(hipGetLastError(), "residual");
+    return ACR_SUCCESS;
+  });
+}
+
+acr_status_t acr_assemble_diffusion(int32_t nx, int32_t ny, int32_t nz, const double* kappa, double* coef,
+                                    hipStream_t stream) {
+  if (nx < 1 || ny < 1 || nz < 1 || !kappa || !coef) return ACR_ERROR_INVALID_VALUE;
+  return guarded([&]() -> acr_status_t {
+    launch_assemble(Grid{nx, ny, nz}, kappa, coef, stream);
+    hip_check(hipGetLastError(), "assemble");
+    return ACR_SUCCESS;
+  });
+}
+
+acr_status_t acr_kappa_gradient(int32_t nx, int32_t ny, int32_t nz, const double* kappa, const double* u,
+                                const double* lam, double* grad, hipStream_t stream) {
+  if (nx < 1 || ny < 1 || nz < 1 || !kappa || !u || !lam || !grad) return ACR_ERROR_INVALID_VALUE;
+  return guarded([&]() -> acr_status_t {
+    launch_kappa_grad(Grid{nx, ny, nz}, kappa, u, lam, grad, stream);
+    hip_check(hipGetLastError(), "kappa gradient");
+    return ACR_SUCCESS;
+  });
+}
+
+acr_status_t acr_solve_refined(acr_handle_t h, const acr_refine_options_t* ro, const double* b, double* x,
+                               hipStream_t stream, acr_refine_result_t* res, double* history,
+                               int32_t history_len) {
+  if (!h || !h->impl || !ro || !b || !x || b == x || !(ro->tol > 0.0) || ro->method < 0 || ro->method > 1)
+    return ACR_ERROR_INVALID_VALUE;
+  return guarded([&]() -> acr_status_t {
+    return to_status(refine(*h->impl, *ro, b, x, stream, res, history, history_len));
+  });
+}
+
+const char* acr_status_string(acr_status_t s) {
+  switch (s) {
+    case ACR_SUCCESS: return "success";
+    case ACR_ERROR_INVALID_VALUE: return "invalid value";
+    case ACR_ERROR_OUT_OF_MEMORY: return "out of device memory";
+    case ACR_ERROR_HIP: return "HIP runtime error";
+    case ACR_ERROR_SINGULAR: return "singular or non-finite block";
+    case ACR_ERROR_RANK_CAPACITY: return "rank exceeds max_rank";
+    case ACR_ERROR_NOT_CONVERGED: return "refinement did not converge";
+    case ACR_ERROR_NOT_SUPPORTED: return "not supported";
+  }
+  return "unknown status";
+}
+
+const char* acr_last_error_message(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,195 @@
+// Host-side structures of the library: cluster tree, device arenas, the
+// launch executor and the weak-admissibility (HODLR) matrix handles.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <functional>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kern.h"
+
+namespace acr {
+
+// Internal failure carried to the C boundary as a status code.
+struct Failure : std::runtime_error {
+  int status;
+  Failure(int s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+enum : int {
+  ST_SUCCESS = 0, ST_INVALID = 1, ST_OOM = 2, ST_HIP = 3, ST_SINGULAR = 4,
+  ST_RANK = 5, ST_NOT_CONVERGED = 6, ST_NOT_SUPPORTED = 7,
+};
+
+void hip_check(hipError_t e, const char* what);
+
+// Planar bisection cluster tree of an nx x ny plane (Sections 2.1.1, 3.1).
+// Split across the longer side (x on ties), first half ceil(side/2); the tree is
+// complete (every box of a depth is split while any box of that depth holds
+// more than `leaf` points); points are numbered leaf by leaf, row-major inside.
+struct Tree {
+  int nx = 0, ny = 0, M = 0, L = 0, leaf = 0, leaf_max = 0;
+  std::vector<std::vector<int>> off, sz;  // [depth][segment]
+  std::vector<int> perm;                   // cluster position -> j * nx + i
+  // Returns false when the rule would have to split a single point.
+  bool build(int nx_, int ny_, int leaf_);
+  int nblk() const { return (1 << (L + 1)) - 2; }
+  static int bid(int d, int s) { return (1 << (d + 1)) - 2 + s; }
+};
+
+struct Allocator {
+  void* (*alloc)(size_t bytes, void* ctx, hipStream_t s) = nullptr;
+  void (*release)(void* p, void* ctx, hipStream_t s) = nullptr;
+  void* ctx = nullptr;
+};
+
+class Exec;
+
+// Chunked bump allocator of device memory with stack-like marks.
+class Arena {
+ public:
+  Arena() = default;
+  void init(Exec* ex, size_t chunk) { ex_ = ex; chunk_ = chunk; }
+  void* get(size_t bytes);
+  template <class T> T* get_n(size_t n) { return static_cast<T*>(get(n * sizeof(T))); }
+  struct Mark { size_t ci, off; };
+  Mark mark() const { return {ci_, off_}; }
+  void release(Mark m) { ci_ = m.ci; off_ = m.off; }
+  void reset() { ci_ = 0; off_ = 0; }
+  void free_all();
+  size_t used() const;
+  size_t reserved() const;
+ private:
+  Exec* ex_ = nullptr;
+  size_t chunk_ = 0;
+  std::vector<std::pair<char*, size_t>> chunks_;
+  size_t ci_ = 0, off_ = 0;
+};
+
+// Launch executor: uploads task arrays and launches, or records the launches
+// of a solve into a replayable list (captured into a HIP graph by the caller).
+class Exec {
+ public:
+  hipStream_t stream = nullptr;
+  Allocator al;
+  int* d_flags = nullptr;
+  int* h_flags = nullptr;
+  std::vector<std::function<void(hipStream_t)>>* rec = nullptr;
+  Arena* rec_arena = nullptr;
+
+  void init(hipStream_t s, const Allocator& a);
+  void destroy();
+  void* dev_alloc(size_t bytes);
+  void dev_free(void* p);
+  void sync();
+  // Device copy of a host array: the staging ring (immediate mode) or the
+  // recording arena (recorded solves keep their task arrays for replay).
+  const void* upload_bytes(const void* src, size_t bytes);
+  template <class Task> const Task* upload(const std::vector<Task>& v) {
+    return static_cast<const Task*>(upload_bytes(v.data(), v.size() * sizeof(Task)));
+  }
+  void submit(std::function<void(hipStream_t)> f);
+  void read_flags(int out[NFLAGS]);
+  void clear_flags();
+
+  template <class T> void gemm(const std::vector<GemmTask>& t);
+  template <class T> void copy(const std::vector<CopyTask>& t);
+  template <class T> void inverse(const std::vector<InvTask>& t);
+  template <class T> void qr(const std::vector<QrTask>& t);
+  template <class T> void svd(const std::vector<SvdTask>& t, double eps);
+  template <class T> void applyq(const std::vector<ApplyQTask>& t);
+
+  // Host-side bounds check of every task against the live device allocations
+  // (enabled with ACR_CHECK=1): a task that would touch memory outside one
+  // allocation raises before anything is launched.
+  bool checking = false;
+  void check_range(const void* p, size_t bytes, const char* what) const;
+
+  // counters of launched algorithmic work (flops), by kernel class
+  double flops_gemm = 0, flops_qr = 0, flops_svd = 0, flops_inv = 0;
+  long launches = 0;
+
+ private:
+  std::vector<void*> oversized_;
+  char* h_ring_ = nullptr;
+  char* d_ring_ = nullptr;
+  size_t ring_bytes_ = 0, ring_off_ = 0;
+};
+
+// A low-rank block U V^T: U is rows x k, V is cols x k, both column-major.
+template <class T> struct LR {
+  T* U = nullptr;
+  T* V = nullptr;
+  int k = 0;
+};
+
+// Plane block: absent, diagonal, or HODLR (dense leaves + one low-rank block
+// per off-diagonal position; block (d, s) has rows seg(d+1, s) and columns
+// seg(d+1, s^1)).
+template <class T> struct HMat {
+  enum Kind { ABSENT = 0, DIAG = 1, HODLR = 2 };
+  int kind = ABSENT;
+  T* diag = nullptr;
+  std::vector<T*> leaf;
+  std::vector<LR<T>> blk;
+  bool absent() const { return kind == ABSENT; }
+  int max_rank() const {
+    int m = 0;
+    for (auto& b : blk) m = b.k > m ? b.k : m;
+    return m;
+  }
+  size_t words(const Tree& tr) const;
+};
+
+// Truncation controls shared by all hierarchical operations.
+struct Trunc {
+  double eps = 0;         // stored blocks: keep sigma_i > eps * sigma_1
+  double eps_inner = 0;   // internal accumulators of one operation
+  int max_rank = 0;       // 0 = unlimited
+};
+
+// ---- hierarchical operations (batched over planes) ----
+template <class T> struct MVJob {
+  const HMat<T>* H;
+  const std::vector<std::vector<LR<T>>>* corr;  // optional diagonal terms per depth
+  const T* X;
+  int64_t ldx;
+  T* Y;
+  int64_t ldy;
+  int c;
+  double alpha, beta;  // beta must be 0 or 1
+};
+
+template <class T> struct ProdJob {
+  const HMat<T>* A;
+  const HMat<T>* B;
+  HMat<T>* C;
+  double alpha;
+};
+
+template <class T> struct SumJob {
+  std::vector<std::pair<const HMat<T>*, double>> terms;
+  HMat<T>* C;
+};
+
+template <class T>
+void hodlr_multivec(Exec& ex, const Tree& tr, const std::vector<MVJob<T>>& jobs, bool trans, int dmin,
+                    Arena& scratch);
+// `out` receives the result blocks; `work` holds intermediates for the duration
+// of the call and `tmp` per-depth temporaries (both are rewound on return).
+template <class T>
+void hodlr_inverse(Exec& ex, const Tree& tr, const std::vector<const HMat<T>*>& D,
+                   const std::vector<HMat<T>*>& G, const Trunc& tc, Arena& out, Arena& work, Arena& tmp);
+template <class T>
+void hodlr_product(Exec& ex, const Tree& tr, const std::vector<ProdJob<T>>& jobs, const Trunc& tc,
+                   Arena& out, Arena& work, Arena& tmp);
+template <class T>
+void hodlr_sum(Exec& ex, const Tree& tr, const std::vector<SumJob<T>>& jobs, const Trunc& tc, Arena& out,
+               Arena& tmp);
+template <class T>
+void hodlr_alloc_leaves(const Tree& tr, HMat<T>& H, Arena& out);
+
+}  // namespace acr

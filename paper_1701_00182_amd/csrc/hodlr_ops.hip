@@ -1,0 +1,736 @@
+// Hierarchical-matrix arithmetic on weak-admissibility (HODLR) plane blocks,
+// batched over all planes of a cyclic-reduction level.
+//
+// The polymorphic operations of Eq. elim (A *_H B, A +_H B, A^{-H}, A *_H b)
+// are realised as "exact structured result, then one truncation per produced
+// block": every off-diagonal block of a result is first written as a stacked
+// low-rank sum [U1 U2 ...][V1 V2 ...]^T that represents it exactly, then
+// compressed by Householder QR of both stacks, a one-sided Jacobi SVD of the
+// small core and truncation at the relative tolerance (Section 3.1: the
+// accuracy is imposed on every block compression and every arithmetic
+// operation).  Contributions that reach a block from its ancestors (diagonal
+// low-rank terms) are accumulated top-down per segment and truncated at a
+// tighter inner tolerance.
+#include <algorithm>
+
+#include "hodlr.h"
+
+namespace acr {
+
+namespace {
+
+template <class T>
+GemmTask gt(const T* A, int64_t lda, int ta, const T* B, int64_t ldb, int tb, T* C, int64_t ldc, int m, int n,
+            int k, double alpha, double beta) {
+  GemmTask g;
+  g.A = A; g.B = B; g.C = C;
+  g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+  g.m = m; g.n = n; g.k = k;
+  g.ta = ta; g.tb = tb;
+  g.alpha = alpha; g.beta = beta;
+  return g;
+}
+
+template <class T>
+CopyTask ctk(const T* src, int64_t lds, T* dst, int64_t ldd, int m, int n, double alpha, int acc,
+             const T* rs = nullptr, const T* cs = nullptr) {
+  CopyTask c;
+  c.src = src; c.dst = dst; c.rs = rs; c.cs = cs;
+  c.lds = lds; c.ldd = ldd;
+  c.m = m; c.n = n;
+  c.accumulate = acc;
+  c.alpha = alpha;
+  return c;
+}
+
+template <class T> struct CJob {
+  T* Us;   // m x r stack (destroyed)
+  T* Vs;   // n x r stack (destroyed)
+  int m, n, r;
+  LR<T>* out;
+};
+
+// Truncated recompression of stacked low-rank sums (see file comment).
+template <class T>
+void compress(Exec& ex, std::vector<CJob<T>>& jobs, double eps, int max_rank, Arena& out, Arena& tmp) {
+  std::vector<CJob<T>*> live;
+  for (auto& j : jobs) {
+    if (j.r == 0 || j.m == 0 || j.n == 0) {
+      *j.out = LR<T>{};
+    } else {
+      live.push_back(&j);
+    }
+  }
+  if (live.empty()) return;
+  const auto mk = tmp.mark();
+  const int nj = (int)live.size();
+  std::vector<QrTask> qt;
+  std::vector<SvdTask> st;
+  int* d_rank = tmp.get_n<int>(nj);
+  qt.reserve(2 * nj);
+  st.reserve(nj);
+  std::vector<T*> tau_u(nj), tau_v(nj);
+  std::vector<double*> Cw(nj), Yw(nj);
+  for (int i = 0; i < nj; ++i) {
+    const CJob<T>& j = *live[i];
+    const int p = std::min(j.m, j.r), q = std::min(j.n, j.r);
+    tau_u[i] = tmp.get_n<T>(p);
+    tau_v[i] = tmp.get_n<T>(q);
+    Cw[i] = tmp.get_n<double>(2 * (size_t)p * q);
+    Yw[i] = tmp.get_n<double>(2 * (size_t)q * q);
+    double* sig = tmp.get_n<double>(q);
+    qt.push_back(QrTask{j.Us, tau_u[i], j.m, j.m, j.r});
+    qt.push_back(QrTask{j.Vs, tau_v[i], j.n, j.n, j.r});
+    SvdTask s;
+    s.Ru = j.Us; s.Rv = j.Vs; s.ldu = j.m; s.ldv = j.n;
+    s.p = p; s.q = q; s.r = j.r;
+    s.C = Cw[i]; s.Y = Yw[i]; s.sig = sig;
+    s.rank_out = d_rank + i;
+    s.max_rank = max_rank;
+    st.push_back(s);
+  }
+  ex.qr<T>(qt);
+  ex.svd<T>(st, eps);
+  std::vector<int> ranks(nj);
+  hip_check(hipMemcpyAsync(ranks.data(), d_rank, nj * sizeof(int), hipMemcpyDeviceToHost, ex.stream),
+            "hipMemcpyAsync(ranks)");
+  ex.sync();
+  std::vector<ApplyQTask> at;
+  at.reserve(2 * nj);
+  for (int i = 0; i < nj; ++i) {
+    CJob<T>& j = *live[i];
+    const int p = std::min(j.m, j.r), q = std::min(j.n, j.r);
+    const int k = ranks[i];
+    LR<T> o;
+    o.k = k;
+    if (k > 0) {
+      o.U = out.get_n<T>((size_t)j.m * k);
+      o.V = out.get_n<T>((size_t)j.n * k);
+      ApplyQTask a;
+      a.Aq = j.Us; a.tau = tau_u[i]; a.Z = Cw[i] + (size_t)p * q; a.out = o.U;
+      a.lda = j.m; a.ldz = p; a.ldo = j.m; a.m = j.m; a.p = p; a.k = k;
+      at.push_back(a);
+      ApplyQTask b;
+      b.Aq = j.Vs; b.tau = tau_v[i]; b.Z = Yw[i] + (size_t)q * q; b.out = o.V;
+      b.lda = j.n; b.ldz = q; b.ldo = j.n; b.m = j.n; b.p = q; b.k = k;
+      at.push_back(b);
+    }
+    *j.out = o;
+  }
+  ex.applyq<T>(at);
+  tmp.release(mk);
+}
+
+inline int nseg(int d) { return 1 << d; }
+
+}  // namespace
+
+template <class T> void hodlr_alloc_leaves(const Tree& tr, HMat<T>& H, Arena& out) {
+  H.kind = HMat<T>::HODLR;
+  H.diag = nullptr;
+  H.leaf.assign(nseg(tr.L), nullptr);
+  for (int s = 0; s < nseg(tr.L); ++s) H.leaf[s] = out.get_n<T>((size_t)tr.sz[tr.L][s] * tr.sz[tr.L][s]);
+  H.blk.assign(tr.nblk(), LR<T>{});
+}
+
+// Y = alpha op(H_{>=dmin}) X + beta Y for every job, where H_{>=dmin} keeps the
+// leaves and the blocks of depth >= dmin (the block diagonal of H at depth
+// dmin), plus each job's optional diagonal low-rank terms corr[d][t] on the
+// segments of depth d + 1 (d >= dmin).
+template <class T>
+void hodlr_multivec(Exec& ex, const Tree& tr, const std::vector<MVJob<T>>& jobs, bool trans, int dmin,
+                    Arena& scratch) {
+  const int L = tr.L;
+  size_t tot = 0;
+  for (auto& j : jobs) {
+    if (j.H->kind != HMat<T>::HODLR) continue;
+    for (int d = dmin; d < L; ++d)
+      for (int s = 0; s < nseg(d + 1); ++s) tot += (size_t)j.H->blk[Tree::bid(d, s)].k * j.c;
+    if (j.corr)
+      for (int d = dmin; d < (int)j.corr->size(); ++d)
+        for (auto& c : (*j.corr)[d]) tot += (size_t)c.k * j.c;
+  }
+  T* buf = scratch.get_n<T>(std::max<size_t>(tot, 1));
+  // per job: pointer to the t of each block / correction
+  std::vector<std::vector<T*>> tb(jobs.size());
+  std::vector<std::vector<std::vector<T*>>> tcr(jobs.size());  // [job][depth][segment]
+  std::vector<GemmTask> inner;
+  size_t pos = 0;
+  for (size_t ji = 0; ji < jobs.size(); ++ji) {
+    const auto& j = jobs[ji];
+    if (j.H->kind != HMat<T>::HODLR) continue;
+    tb[ji].assign(tr.nblk(), nullptr);
+    for (int d = dmin; d < L; ++d)
+      for (int s = 0; s < nseg(d + 1); ++s) {
+        const LR<T>& b = j.H->blk[Tree::bid(d, s)];
+        if (b.k == 0) continue;
+        T* t = buf + pos;
+        pos += (size_t)b.k * j.c;
+        tb[ji][Tree::bid(d, s)] = t;
+        const int ro = tr.off[d + 1][s], rn = tr.sz[d + 1][s];
+        const int co = tr.off[d + 1][s ^ 1], cn = tr.sz[d + 1][s ^ 1];
+        if (!trans)
+          inner.push_back(gt<T>(b.V, cn, 1, j.X + co, j.ldx, 0, t, b.k, b.k, j.c, cn, 1.0, 0.0));
+        else
+          inner.push_back(gt<T>(b.U, rn, 1, j.X + ro, j.ldx, 0, t, b.k, b.k, j.c, rn, 1.0, 0.0));
+      }
+    if (j.corr) {
+      tcr[ji].assign(j.corr->size(), {});
+      for (int d = dmin; d < (int)j.corr->size(); ++d)
+        for (int s = 0; s < (int)(*j.corr)[d].size(); ++s) {
+          const LR<T>& c = (*j.corr)[d][s];
+          T* t = nullptr;
+          if (c.k > 0) {
+            t = buf + pos;
+            pos += (size_t)c.k * j.c;
+            const int so = tr.off[d + 1][s], sn = tr.sz[d + 1][s];
+            inner.push_back(gt<T>(trans ? c.U : c.V, sn, 1, j.X + so, j.ldx, 0, t, c.k, c.k, j.c, sn, 1.0, 0.0));
+          }
+          tcr[ji][d].push_back(t);
+        }
+    }
+  }
+  ex.gemm<T>(inner);
+  std::vector<GemmTask> lv;
+  std::vector<CopyTask> dg;
+  for (const auto& j : jobs) {
+    if (j.H->kind == HMat<T>::DIAG) {
+      dg.push_back(ctk<T>(j.X, j.ldx, j.Y, j.ldy, tr.M, j.c, j.alpha, j.beta != 0.0, j.H->diag));
+    } else if (j.H->kind == HMat<T>::ABSENT) {
+      if (j.beta == 0.0) dg.push_back(ctk<T>(nullptr, 0, j.Y, j.ldy, tr.M, j.c, 0.0, 0));
+    } else {
+      for (int s = 0; s < nseg(L); ++s) {
+        const int o = tr.off[L][s], n = tr.sz[L][s];
+        lv.push_back(gt<T>(j.H->leaf[s], n, trans ? 1 : 0, j.X + o, j.ldx, 0, j.Y + o, j.ldy, n, j.c, n, j.alpha,
+                           j.beta));
+      }
+    }
+  }
+  ex.gemm<T>(lv);
+  ex.copy<T>(dg);
+  for (int d = dmin; d < L; ++d) {
+    std::vector<GemmTask> ap, apc;
+    for (size_t ji = 0; ji < jobs.size(); ++ji) {
+      const auto& j = jobs[ji];
+      if (j.H->kind != HMat<T>::HODLR) continue;
+      for (int s = 0; s < nseg(d + 1); ++s) {
+        const LR<T>& b = j.H->blk[Tree::bid(d, s)];
+        if (b.k == 0) continue;
+        const T* t = tb[ji][Tree::bid(d, s)];
+        const int ro = tr.off[d + 1][s], rn = tr.sz[d + 1][s];
+        const int co = tr.off[d + 1][s ^ 1], cn = tr.sz[d + 1][s ^ 1];
+        if (!trans)
+          ap.push_back(gt<T>(b.U, rn, 0, t, b.k, 0, j.Y + ro, j.ldy, rn, j.c, b.k, j.alpha, 1.0));
+        else
+          ap.push_back(gt<T>(b.V, cn, 0, t, b.k, 0, j.Y + co, j.ldy, cn, j.c, b.k, j.alpha, 1.0));
+      }
+      if (j.corr && d < (int)j.corr->size()) {
+        for (int s = 0; s < (int)(*j.corr)[d].size(); ++s) {
+          const LR<T>& c = (*j.corr)[d][s];
+          if (c.k == 0) continue;
+          const int so = tr.off[d + 1][s], sn = tr.sz[d + 1][s];
+          apc.push_back(gt<T>(trans ? c.V : c.U, sn, 0, tcr[ji][d][s], c.k, 0, j.Y + so, j.ldy, sn, j.c, c.k, j.alpha,
+                              1.0));
+        }
+      }
+    }
+    ex.gemm<T>(ap);
+    ex.gemm<T>(apc);
+  }
+}
+
+// ---------------------------------------------------------------- inverse
+//
+// Bottom-up block inversion.  With B_{d+1} the block diagonal of D at depth
+// d + 1 and O_d the off-diagonal blocks of depth d, each node satisfies
+//   inv(B + U W^T) = inv(B) - inv(B) U (I + W^T inv(B) U)^{-1} W^T inv(B)
+// (Sherman-Morrison-Woodbury), which yields per node the two new off-diagonal
+// blocks and one low-rank correction on each child.  The corrections are
+// pushed down into the deeper blocks and the leaves at the end.
+template <class T>
+void hodlr_inverse(Exec& ex, const Tree& tr, const std::vector<const HMat<T>*>& D,
+                   const std::vector<HMat<T>*>& G, const Trunc& tc, Arena& out, Arena& work, Arena& tmp) {
+  const int L = tr.L, M = tr.M;
+  const int np = (int)D.size();
+  const auto wmark = work.mark();
+  // leaves
+  {
+    std::vector<CopyTask> cp;
+    std::vector<InvTask> iv;
+    for (int p = 0; p < np; ++p) {
+      hodlr_alloc_leaves(tr, *G[p], out);
+      for (int s = 0; s < nseg(L); ++s) {
+        const int n = tr.sz[L][s];
+        cp.push_back(ctk<T>(D[p]->leaf[s], n, G[p]->leaf[s], n, n, n, 1.0, 0));
+        iv.push_back(InvTask{G[p]->leaf[s], n, n, 0});
+      }
+    }
+    ex.copy<T>(cp);
+    ex.inverse<T>(iv);
+  }
+  // state: off-diagonal blocks g (by block id) and corrections c[d][t]
+  std::vector<std::vector<LR<T>>> g(np, std::vector<LR<T>>(tr.nblk()));
+  std::vector<std::vector<std::vector<LR<T>>>> corr(np);
+  for (int p = 0; p < np; ++p) {
+    corr[p].assign(std::max(L - 1, 0), {});
+    for (int d = 0; d + 1 < L; ++d) corr[p][d].assign(nseg(d + 1), LR<T>{});
+  }
+  std::vector<HMat<T>> cur(np);
+  for (int p = 0; p < np; ++p) {
+    cur[p].kind = HMat<T>::HODLR;
+    cur[p].leaf = G[p]->leaf;
+    cur[p].blk.assign(tr.nblk(), LR<T>{});
+  }
+  for (int d = L - 1; d >= 0; --d) {
+    const auto tm = tmp.mark();
+    // flat bases of depth d: Xu rows of s <- U_{d,s}; Xv rows of t <- V_{d,t^1}
+    std::vector<int> K(np, 0);
+    std::vector<T*> Xu(np), Xv(np), P(np), Q(np);
+    std::vector<CopyTask> cp;
+    std::vector<MVJob<T>> mv, mvt;
+    for (int p = 0; p < np; ++p) {
+      for (int s = 0; s < nseg(d + 1); ++s) K[p] = std::max(K[p], D[p]->blk[Tree::bid(d, s)].k);
+      if (K[p] == 0) continue;
+      Xu[p] = tmp.get_n<T>((size_t)M * K[p]);
+      Xv[p] = tmp.get_n<T>((size_t)M * K[p]);
+      P[p] = tmp.get_n<T>((size_t)M * K[p]);
+      Q[p] = tmp.get_n<T>((size_t)M * K[p]);
+      cp.push_back(ctk<T>(nullptr, 0, Xu[p], M, M, K[p], 0.0, 0));
+      cp.push_back(ctk<T>(nullptr, 0, Xv[p], M, M, K[p], 0.0, 0));
+    }
+    ex.copy<T>(cp);
+    cp.clear();
+    for (int p = 0; p < np; ++p) {
+      if (K[p] == 0) continue;
+      for (int s = 0; s < nseg(d + 1); ++s) {
+        const LR<T>& b = D[p]->blk[Tree::bid(d, s)];
+        if (b.k == 0) continue;
+        const int ro = tr.off[d + 1][s], rn = tr.sz[d + 1][s];
+        const int co = tr.off[d + 1][s ^ 1], cn = tr.sz[d + 1][s ^ 1];
+        cp.push_back(ctk<T>(b.U, rn, Xu[p] + ro, M, rn, b.k, 1.0, 0));
+        cp.push_back(ctk<T>(b.V, cn, Xv[p] + co, M, cn, b.k, 1.0, 0));
+      }
+      mv.push_back(MVJob<T>{&cur[p], &corr[p], Xu[p], M, P[p], M, K[p], 1.0, 0.0});
+      mvt.push_back(MVJob<T>{&cur[p], &corr[p], Xv[p], M, Q[p], M, K[p], 1.0, 0.0});
+    }
+    ex.copy<T>(cp);
+    hodlr_multivec<T>(ex, tr, mv, false, d + 1, tmp);
+    hodlr_multivec<T>(ex, tr, mvt, true, d + 1, tmp);
+    // capacitance matrices per node
+    struct Node { int p, b, k12, k21; T* K; };
+    std::vector<Node> nodes;
+    std::vector<CopyTask> eye;
+    std::vector<GemmTask> kg;
+    std::vector<InvTask> kinv;
+    for (int p = 0; p < np; ++p) {
+      if (K[p] == 0) continue;
+      for (int b = 0; b < nseg(d); ++b) {
+        const int s1 = 2 * b, s2 = 2 * b + 1;
+        const LR<T>& B12 = D[p]->blk[Tree::bid(d, s1)];
+        const LR<T>& B21 = D[p]->blk[Tree::bid(d, s2)];
+        const int k12 = B12.k, k21 = B21.k, kk = k12 + k21;
+        if (kk == 0) continue;
+        T* Km = tmp.get_n<T>((size_t)kk * kk);
+        nodes.push_back(Node{p, b, k12, k21, Km});
+        eye.push_back(ctk<T>(nullptr, 0, Km, kk, kk, kk, 1.0, 0));
+        const int o1 = tr.off[d + 1][s1], n1 = tr.sz[d + 1][s1];
+        const int o2 = tr.off[d + 1][s2], n2 = tr.sz[d + 1][s2];
+        if (k12 && k21) {
+          kg.push_back(gt<T>(B12.V, n2, 1, P[p] + o2, M, 0, Km + (size_t)k12 * kk, kk, k12, k21, n2, 1.0, 0.0));
+          kg.push_back(gt<T>(B21.V, n1, 1, P[p] + o1, M, 0, Km + k12, kk, k21, k12, n1, 1.0, 0.0));
+        }
+        kinv.push_back(InvTask{Km, kk, kk, 0});
+      }
+    }
+    ex.copy<T>(eye);
+    ex.gemm<T>(kg);
+    ex.inverse<T>(kinv);
+    // stacks of the new off-diagonal blocks and of the child corrections
+    std::vector<CJob<T>> gj, cj;
+    std::vector<GemmTask> sg;
+    std::vector<CopyTask> sc;
+    std::vector<GemmTask> leafupd;
+    for (const Node& nd : nodes) {
+      const int p = nd.p, s1 = 2 * nd.b, s2 = s1 + 1, k12 = nd.k12, k21 = nd.k21, kk = k12 + k21;
+      const int o1 = tr.off[d + 1][s1], n1 = tr.sz[d + 1][s1];
+      const int o2 = tr.off[d + 1][s2], n2 = tr.sz[d + 1][s2];
+      T* Km = nd.K;
+      // block (d, s1) = -P1 K11 Q2^T ; block (d, s2) = -P2 K22 Q1^T
+      if (k12) {
+        T* Us = tmp.get_n<T>((size_t)n1 * k12);
+        T* Vs = tmp.get_n<T>((size_t)n2 * k12);
+        sg.push_back(gt<T>(P[p] + o1, M, 0, Km, kk, 0, Us, n1, n1, k12, k12, -1.0, 0.0));
+        sc.push_back(ctk<T>(Q[p] + o2, M, Vs, n2, n2, k12, 1.0, 0));
+        gj.push_back(CJob<T>{Us, Vs, n1, n2, k12, &g[p][Tree::bid(d, s1)]});
+      }
+      if (k21) {
+        T* Us = tmp.get_n<T>((size_t)n2 * k21);
+        T* Vs = tmp.get_n<T>((size_t)n1 * k21);
+        sg.push_back(gt<T>(P[p] + o2, M, 0, Km + k12 + (size_t)k12 * kk, kk, 0, Us, n2, n2, k21, k21, -1.0, 0.0));
+        sc.push_back(ctk<T>(Q[p] + o1, M, Vs, n1, n1, k21, 1.0, 0));
+        gj.push_back(CJob<T>{Us, Vs, n2, n1, k21, &g[p][Tree::bid(d, s2)]});
+      }
+      // corrections: on s1: -P1 K12 Q1^T (rank k21); on s2: -P2 K21 Q2^T (rank k12)
+      if (k12 && k21) {
+        T* U1 = tmp.get_n<T>((size_t)n1 * k21);
+        T* V1 = tmp.get_n<T>((size_t)n1 * k21);
+        sg.push_back(gt<T>(P[p] + o1, M, 0, Km + (size_t)k12 * kk, kk, 0, U1, n1, n1, k21, k12, -1.0, 0.0));
+        sc.push_back(ctk<T>(Q[p] + o1, M, V1, n1, n1, k21, 1.0, 0));
+        T* U2 = tmp.get_n<T>((size_t)n2 * k12);
+        T* V2 = tmp.get_n<T>((size_t)n2 * k12);
+        sg.push_back(gt<T>(P[p] + o2, M, 0, Km + k12, kk, 0, U2, n2, n2, k12, k21, -1.0, 0.0));
+        sc.push_back(ctk<T>(Q[p] + o2, M, V2, n2, n2, k12, 1.0, 0));
+        if (d == L - 1) {
+          // children are leaves: add the corrections to the dense inverses directly
+          leafupd.push_back(gt<T>(U1, n1, 0, V1, n1, 1, G[p]->leaf[s1], n1, n1, n1, k21, 1.0, 1.0));
+          leafupd.push_back(gt<T>(U2, n2, 0, V2, n2, 1, G[p]->leaf[s2], n2, n2, n2, k12, 1.0, 1.0));
+        } else {
+          cj.push_back(CJob<T>{U1, V1, n1, n1, k21, &corr[p][d][s1]});
+          cj.push_back(CJob<T>{U2, V2, n2, n2, k12, &corr[p][d][s2]});
+        }
+      }
+    }
+    ex.gemm<T>(sg);
+    ex.copy<T>(sc);
+    ex.gemm<T>(leafupd);
+    // depth-0 blocks are final; deeper ones are intermediate until the push-down
+    compress<T>(ex, gj, d == 0 ? tc.eps : tc.eps_inner, d == 0 ? tc.max_rank : 0, d == 0 ? out : work, tmp);
+    compress<T>(ex, cj, tc.eps_inner, 0, work, tmp);
+    for (int p = 0; p < np; ++p)
+      for (int s = 0; s < nseg(d + 1); ++s) cur[p].blk[Tree::bid(d, s)] = g[p][Tree::bid(d, s)];
+    tmp.release(tm);
+  }
+  for (int p = 0; p < np; ++p)
+    for (int s = 0; s < (L > 0 ? 2 : 0); ++s) G[p]->blk[Tree::bid(0, s)] = g[p][Tree::bid(0, s)];
+  // push-down of the corrections: acc on segments of depth d (from corrections
+  // of depths < d) joins the blocks of depth d and the next accumulator
+  std::vector<std::vector<LR<T>>> acc(np);
+  for (int p = 0; p < np; ++p)
+    if (L >= 2) acc[p] = corr[p][0];
+  for (int d = 1; d < L; ++d) {
+    const auto tm = tmp.mark();
+    std::vector<CJob<T>> bj, aj;
+    std::vector<CopyTask> sc;
+    std::vector<GemmTask> leafupd;
+    std::vector<std::vector<LR<T>>> nacc(np);
+    for (int p = 0; p < np; ++p) {
+      if (d + 1 < L) nacc[p].assign(nseg(d + 1), LR<T>{});
+      for (int s = 0; s < nseg(d + 1); ++s) {
+        const int par = s >> 1;
+        const LR<T>& a = acc[p][par];
+        const LR<T>& gb = g[p][Tree::bid(d, s)];
+        const int ro = tr.off[d + 1][s] - tr.off[d][par], rn = tr.sz[d + 1][s];
+        const int co = tr.off[d + 1][s ^ 1] - tr.off[d][par], cn = tr.sz[d + 1][s ^ 1];
+        const int pn = tr.sz[d][par];
+        // final block (d, s)
+        const int r = gb.k + a.k;
+        if (r > 0) {
+          T* Us = tmp.get_n<T>((size_t)rn * r);
+          T* Vs = tmp.get_n<T>((size_t)cn * r);
+          if (gb.k) {
+            sc.push_back(ctk<T>(gb.U, rn, Us, rn, rn, gb.k, 1.0, 0));
+            sc.push_back(ctk<T>(gb.V, cn, Vs, cn, cn, gb.k, 1.0, 0));
+          }
+          if (a.k) {
+            sc.push_back(ctk<T>(a.U + ro, pn, Us + (size_t)rn * gb.k, rn, rn, a.k, 1.0, 0));
+            sc.push_back(ctk<T>(a.V + co, pn, Vs + (size_t)cn * gb.k, cn, cn, a.k, 1.0, 0));
+          }
+          bj.push_back(CJob<T>{Us, Vs, rn, cn, r, &G[p]->blk[Tree::bid(d, s)]});
+        } else {
+          G[p]->blk[Tree::bid(d, s)] = LR<T>{};
+        }
+        if (d + 1 < L) {
+          const LR<T>& c = corr[p][d][s];
+          const int ra = c.k + a.k;
+          if (ra > 0) {
+            T* Us = tmp.get_n<T>((size_t)rn * ra);
+            T* Vs = tmp.get_n<T>((size_t)rn * ra);
+            if (c.k) {
+              sc.push_back(ctk<T>(c.U, rn, Us, rn, rn, c.k, 1.0, 0));
+              sc.push_back(ctk<T>(c.V, rn, Vs, rn, rn, c.k, 1.0, 0));
+            }
+            if (a.k) {
+              sc.push_back(ctk<T>(a.U + ro, pn, Us + (size_t)rn * c.k, rn, rn, a.k, 1.0, 0));
+              sc.push_back(ctk<T>(a.V + ro, pn, Vs + (size_t)rn * c.k, rn, rn, a.k, 1.0, 0));
+            }
+            aj.push_back(CJob<T>{Us, Vs, rn, rn, ra, &nacc[p][s]});
+          }
+        } else if (a.k) {
+          leafupd.push_back(gt<T>(a.U + ro, pn, 0, a.V + ro, pn, 1, G[p]->leaf[s], rn, rn, rn, a.k, 1.0, 1.0));
+        }
+      }
+    }
+    ex.copy<T>(sc);
+    ex.gemm<T>(leafupd);
+    compress<T>(ex, bj, tc.eps, tc.max_rank, out, tmp);
+    compress<T>(ex, aj, tc.eps_inner, 0, work, tmp);
+    // the new accumulators live in `work`, so only the stacks are released
+    tmp.release(tm);
+    if (d + 1 < L) acc = std::move(nacc);
+  }
+  work.release(wmark);
+}
+
+// ---------------------------------------------------------------- product
+//
+// C = alpha A B.  With A, B in HODLR form, the block (d, s) of the product is
+//   A[s,s] U^B_{d,s} V^B_{d,s}^T + U^A_{d,s} (B[s',s']^T V^A_{d,s})^T
+//   + (terms from the ancestors' off-diagonal blocks),
+// where the ancestor of depth d0 contributes on each child segment t the
+// diagonal term U^A_{d0,t} (V^A_{d0,t}^T U^B_{d0,t'}) V^B_{d0,t'}^T.  A
+// diagonal factor (the level-0 couplings) scales rows or columns instead.
+template <class T>
+void hodlr_product(Exec& ex, const Tree& tr, const std::vector<ProdJob<T>>& jobs, const Trunc& tc,
+                   Arena& out, Arena& work, Arena& tmp) {
+  const int L = tr.L, M = tr.M;
+  const auto wmark = work.mark();
+  std::vector<const ProdJob<T>*> gen, dia;
+  for (auto& j : jobs) {
+    if (j.A->absent() || j.B->absent()) {
+      *j.C = HMat<T>{};
+      continue;
+    }
+    if (j.A->kind == HMat<T>::DIAG && j.B->kind == HMat<T>::DIAG)
+      throw Failure(ST_NOT_SUPPORTED, "product of two diagonal blocks");
+    (j.A->kind == HMat<T>::DIAG || j.B->kind == HMat<T>::DIAG ? dia : gen).push_back(&j);
+  }
+  // -- diagonal factor: scaled copy, then truncation of every block
+  if (!dia.empty()) {
+    const auto tm = tmp.mark();
+    std::vector<CopyTask> cp;
+    std::vector<CJob<T>> cj;
+    for (const auto* j : dia) {
+      const bool left = j->A->kind == HMat<T>::DIAG;
+      const HMat<T>& H = left ? *j->B : *j->A;
+      const T* dv = left ? j->A->diag : j->B->diag;
+      hodlr_alloc_leaves(tr, *j->C, out);
+      for (int s = 0; s < nseg(L); ++s) {
+        const int o = tr.off[L][s], n = tr.sz[L][s];
+        cp.push_back(ctk<T>(H.leaf[s], n, j->C->leaf[s], n, n, n, j->alpha, 0, left ? dv + o : nullptr,
+                            left ? nullptr : dv + o));
+      }
+      for (int d = 0; d < L; ++d)
+        for (int s = 0; s < nseg(d + 1); ++s) {
+          const LR<T>& b = H.blk[Tree::bid(d, s)];
+          if (b.k == 0) continue;
+          const int ro = tr.off[d + 1][s], rn = tr.sz[d + 1][s];
+          const int co = tr.off[d + 1][s ^ 1], cn = tr.sz[d + 1][s ^ 1];
+          T* Us = tmp.get_n<T>((size_t)rn * b.k);
+          T* Vs = tmp.get_n<T>((size_t)cn * b.k);
+          cp.push_back(ctk<T>(b.U, rn, Us, rn, rn, b.k, j->alpha, 0, left ? dv + ro : nullptr));
+          cp.push_back(ctk<T>(b.V, cn, Vs, cn, cn, b.k, 1.0, 0, left ? nullptr : dv + co));
+          cj.push_back(CJob<T>{Us, Vs, rn, cn, b.k, &j->C->blk[Tree::bid(d, s)]});
+        }
+    }
+    ex.copy<T>(cp);
+    compress<T>(ex, cj, tc.eps, tc.max_rank, out, tmp);
+    tmp.release(tm);
+  }
+  if (gen.empty()) {
+    work.release(wmark);
+    return;
+  }
+  const int nj = (int)gen.size();
+  // leaves: C_l = alpha A_l B_l
+  {
+    std::vector<GemmTask> lg;
+    for (const auto* j : gen) {
+      hodlr_alloc_leaves(tr, *j->C, out);
+      for (int s = 0; s < nseg(L); ++s) {
+        const int n = tr.sz[L][s];
+        lg.push_back(gt<T>(j->A->leaf[s], n, 0, j->B->leaf[s], n, 0, j->C->leaf[s], n, n, n, n, j->alpha, 0.0));
+      }
+    }
+    ex.gemm<T>(lg);
+  }
+  std::vector<std::vector<LR<T>>> acc(nj);  // accumulators on segments of depth d
+  for (int d = 0; d < L; ++d) {
+    const auto tm = tmp.mark();
+    std::vector<int> Kb(nj, 0), Ka(nj, 0);
+    std::vector<T*> Xu(nj, nullptr), Xv(nj, nullptr), PU(nj, nullptr), QV(nj, nullptr);
+    std::vector<CopyTask> cp;
+    for (int i = 0; i < nj; ++i) {
+      for (int s = 0; s < nseg(d + 1); ++s) {
+        Kb[i] = std::max(Kb[i], gen[i]->B->blk[Tree::bid(d, s)].k);
+        Ka[i] = std::max(Ka[i], gen[i]->A->blk[Tree::bid(d, s)].k);
+      }
+      if (Kb[i]) {
+        Xu[i] = tmp.get_n<T>((size_t)M * Kb[i]);
+        PU[i] = tmp.get_n<T>((size_t)M * Kb[i]);
+        cp.push_back(ctk<T>(nullptr, 0, Xu[i], M, M, Kb[i], 0.0, 0));
+      }
+      if (Ka[i]) {
+        Xv[i] = tmp.get_n<T>((size_t)M * Ka[i]);
+        QV[i] = tmp.get_n<T>((size_t)M * Ka[i]);
+        cp.push_back(ctk<T>(nullptr, 0, Xv[i], M, M, Ka[i], 0.0, 0));
+      }
+    }
+    ex.copy<T>(cp);
+    cp.clear();
+    std::vector<MVJob<T>> mu, mvv;
+    for (int i = 0; i < nj; ++i) {
+      for (int s = 0; s < nseg(d + 1); ++s) {
+        const LR<T>& bb = gen[i]->B->blk[Tree::bid(d, s)];
+        const LR<T>& ab = gen[i]->A->blk[Tree::bid(d, s)];
+        const int ro = tr.off[d + 1][s], rn = tr.sz[d + 1][s];
+        const int co = tr.off[d + 1][s ^ 1], cn = tr.sz[d + 1][s ^ 1];
+        if (bb.k) cp.push_back(ctk<T>(bb.U, rn, Xu[i] + ro, M, rn, bb.k, 1.0, 0));
+        if (ab.k) cp.push_back(ctk<T>(ab.V, cn, Xv[i] + co, M, cn, ab.k, 1.0, 0));
+      }
+      if (Kb[i]) mu.push_back(MVJob<T>{gen[i]->A, nullptr, Xu[i], M, PU[i], M, Kb[i], 1.0, 0.0});
+      if (Ka[i]) mvv.push_back(MVJob<T>{gen[i]->B, nullptr, Xv[i], M, QV[i], M, Ka[i], 1.0, 0.0});
+    }
+    ex.copy<T>(cp);
+    hodlr_multivec<T>(ex, tr, mu, false, d + 1, tmp);
+    hodlr_multivec<T>(ex, tr, mvv, true, d + 1, tmp);
+    // own stacks (+ accumulator of the parent segment) of the blocks of depth d,
+    // and diagonal terms of depth d on the child segments
+    std::vector<CJob<T>> bj, aj;
+    std::vector<CopyTask> sc;
+    std::vector<GemmTask> wg, zg, leafupd;
+    std::vector<std::vector<LR<T>>> nacc(nj);
+    for (int i = 0; i < nj; ++i) {
+      const ProdJob<T>& j = *gen[i];
+      if (d + 1 < L) nacc[i].assign(nseg(d + 1), LR<T>{});
+      for (int s = 0; s < nseg(d + 1); ++s) {
+        const LR<T>& bb = j.B->blk[Tree::bid(d, s)];
+        const LR<T>& ab = j.A->blk[Tree::bid(d, s)];
+        const int ro = tr.off[d + 1][s], rn = tr.sz[d + 1][s];
+        const int co = tr.off[d + 1][s ^ 1], cn = tr.sz[d + 1][s ^ 1];
+        LR<T> a{};
+        int pro = 0, pco = 0, pn = 0;
+        if (d > 0) {
+          const int par = s >> 1;
+          a = acc[i][par];
+          pro = tr.off[d + 1][s] - tr.off[d][par];
+          pco = tr.off[d + 1][s ^ 1] - tr.off[d][par];
+          pn = tr.sz[d][par];
+        }
+        const int r = bb.k + ab.k + a.k;
+        if (r > 0) {
+          T* Us = tmp.get_n<T>((size_t)rn * r);
+          T* Vs = tmp.get_n<T>((size_t)cn * r);
+          int c0 = 0;
+          if (bb.k) {
+            sc.push_back(ctk<T>(PU[i] + ro, M, Us, rn, rn, bb.k, j.alpha, 0));
+            sc.push_back(ctk<T>(bb.V, cn, Vs, cn, cn, bb.k, 1.0, 0));
+            c0 += bb.k;
+          }
+          if (ab.k) {
+            sc.push_back(ctk<T>(ab.U, rn, Us + (size_t)rn * c0, rn, rn, ab.k, j.alpha, 0));
+            sc.push_back(ctk<T>(QV[i] + co, M, Vs + (size_t)cn * c0, cn, cn, ab.k, 1.0, 0));
+            c0 += ab.k;
+          }
+          if (a.k) {
+            sc.push_back(ctk<T>(a.U + pro, pn, Us + (size_t)rn * c0, rn, rn, a.k, 1.0, 0));
+            sc.push_back(ctk<T>(a.V + pco, pn, Vs + (size_t)cn * c0, cn, cn, a.k, 1.0, 0));
+          }
+          bj.push_back(CJob<T>{Us, Vs, rn, cn, r, &j.C->blk[Tree::bid(d, s)]});
+        } else {
+          j.C->blk[Tree::bid(d, s)] = LR<T>{};
+        }
+        // diagonal term on segment s: U^A_{d,s} (V^A_{d,s}^T U^B_{d,s^1}) V^B_{d,s^1}^T
+        const LR<T>& bs = j.B->blk[Tree::bid(d, s ^ 1)];
+        const int kz = (ab.k && bs.k) ? bs.k : 0;
+        const int ra = kz + a.k;
+        if (ra == 0) continue;
+        T* Zu = tmp.get_n<T>((size_t)rn * ra);
+        T* Zv = tmp.get_n<T>((size_t)rn * ra);
+        if (kz) {
+          T* W = tmp.get_n<T>((size_t)ab.k * kz);
+          wg.push_back(gt<T>(ab.V, cn, 1, bs.U, cn, 0, W, ab.k, ab.k, kz, cn, 1.0, 0.0));
+          zg.push_back(gt<T>(ab.U, rn, 0, W, ab.k, 0, Zu, rn, rn, kz, ab.k, j.alpha, 0.0));
+          sc.push_back(ctk<T>(bs.V, rn, Zv, rn, rn, kz, 1.0, 0));
+        }
+        if (a.k) {
+          sc.push_back(ctk<T>(a.U + pro, pn, Zu + (size_t)rn * kz, rn, rn, a.k, 1.0, 0));
+          sc.push_back(ctk<T>(a.V + pro, pn, Zv + (size_t)rn * kz, rn, rn, a.k, 1.0, 0));
+        }
+        if (d + 1 < L)
+          aj.push_back(CJob<T>{Zu, Zv, rn, rn, ra, &nacc[i][s]});
+        else
+          leafupd.push_back(gt<T>(Zu, rn, 0, Zv, rn, 1, j.C->leaf[s], rn, rn, rn, ra, 1.0, 1.0));
+      }
+    }
+    ex.gemm<T>(wg);
+    ex.gemm<T>(zg);
+    ex.copy<T>(sc);
+    ex.gemm<T>(leafupd);
+    compress<T>(ex, bj, tc.eps, tc.max_rank, out, tmp);
+    compress<T>(ex, aj, tc.eps_inner, 0, work, tmp);
+    tmp.release(tm);
+    if (d + 1 < L) acc = std::move(nacc);
+  }
+  work.release(wmark);
+}
+
+// ---------------------------------------------------------------- sum
+template <class T>
+void hodlr_sum(Exec& ex, const Tree& tr, const std::vector<SumJob<T>>& jobs, const Trunc& tc, Arena& out,
+               Arena& tmp) {
+  const int L = tr.L;
+  const auto tm = tmp.mark();
+  // leaves: the first present term is copied, every further term is added in
+  // a launch of its own (tasks of one launch must not share a destination)
+  std::vector<CopyTask> cp;
+  std::vector<std::vector<CopyTask>> ca;
+  std::vector<CJob<T>> cj;
+  for (const auto& j : jobs) {
+    hodlr_alloc_leaves(tr, *j.C, out);
+    int nth = 0;
+    for (const auto& term : j.terms) {
+      const HMat<T>* H = term.first;
+      if (H->absent()) continue;
+      if (H->kind != HMat<T>::HODLR) throw Failure(ST_NOT_SUPPORTED, "sum of a diagonal block");
+      if (nth > 0 && (int)ca.size() < nth) ca.resize(nth);
+      for (int s = 0; s < nseg(L); ++s) {
+        const int n = tr.sz[L][s];
+        const CopyTask t = ctk<T>(H->leaf[s], n, j.C->leaf[s], n, n, n, term.second, nth > 0 ? 1 : 0);
+        if (nth == 0) cp.push_back(t); else ca[nth - 1].push_back(t);
+      }
+      ++nth;
+    }
+    if (nth == 0) throw Failure(ST_INVALID, "empty sum");
+    for (int d = 0; d < L; ++d)
+      for (int s = 0; s < nseg(d + 1); ++s) {
+        int r = 0;
+        for (const auto& term : j.terms)
+          if (!term.first->absent()) r += term.first->blk[Tree::bid(d, s)].k;
+        const int rn = tr.sz[d + 1][s], cn = tr.sz[d + 1][s ^ 1];
+        if (r == 0) {
+          j.C->blk[Tree::bid(d, s)] = LR<T>{};
+          continue;
+        }
+        T* Us = tmp.get_n<T>((size_t)rn * r);
+        T* Vs = tmp.get_n<T>((size_t)cn * r);
+        int c0 = 0;
+        for (const auto& term : j.terms) {
+          if (term.first->absent()) continue;
+          const LR<T>& b = term.first->blk[Tree::bid(d, s)];
+          if (!b.k) continue;
+          cp.push_back(ctk<T>(b.U, rn, Us + (size_t)rn * c0, rn, rn, b.k, term.second, 0));
+          cp.push_back(ctk<T>(b.V, cn, Vs + (size_t)cn * c0, cn, cn, b.k, 1.0, 0));
+          c0 += b.k;
+        }
+        cj.push_back(CJob<T>{Us, Vs, rn, cn, r, &j.C->blk[Tree::bid(d, s)]});
+      }
+  }
+  ex.copy<T>(cp);
+  for (auto& a : ca) ex.copy<T>(a);
+  compress<T>(ex, cj, tc.eps, tc.max_rank, out, tmp);
+  tmp.release(tm);
+}
+
+#define ACR_OPS_INST(T)                                                                                        \
+  template void hodlr_alloc_leaves<T>(const Tree&, HMat<T>&, Arena&);                                           \
+  template void hodlr_multivec<T>(Exec&, const Tree&, const std::vector<MVJob<T>>&, bool, int, Arena&);         \
+  template void hodlr_inverse<T>(Exec&, const Tree&, const std::vector<const HMat<T>*>&,                        \
+                                 const std::vector<HMat<T>*>&, const Trunc&, Arena&, Arena&, Arena&);           \
+  template void hodlr_product<T>(Exec&, const Tree&, const std::vector<ProdJob<T>>&, const Trunc&, Arena&,      \
+                                 Arena&, Arena&);                                                               \
+  template void hodlr_sum<T>(Exec&, const Tree&, const std::vector<SumJob<T>>&, const Trunc&, Arena&, Arena&);
+ACR_OPS_INST(float)
+ACR_OPS_INST(double)
+#undef ACR_OPS_INST
+
+}  // namespace acr

@@ -1,0 +1,382 @@
+// Cluster tree, device arenas and the launch executor.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "hodlr.h"
+
+namespace acr {
+
+void hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  if (e == hipErrorOutOfMemory) throw Failure(ST_OOM, std::string(what) + ": out of device memory");
+  throw Failure(ST_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- tree
+namespace {
+struct Box { int x0, x1, y0, y1; };
+inline int box_size(const Box& b) { return (b.x1 - b.x0) * (b.y1 - b.y0); }
+}  // namespace
+
+bool Tree::build(int nx_, int ny_, int leaf_) {
+  nx = nx_; ny = ny_; leaf = leaf_; M = nx * ny;
+  std::vector<std::vector<Box>> levels{{Box{0, nx, 0, ny}}};
+  for (;;) {
+    const auto& cur = levels.back();
+    int mx = 0;
+    for (auto& b : cur) mx = std::max(mx, box_size(b));
+    if (mx <= leaf) break;
+    std::vector<Box> nxt;
+    nxt.reserve(cur.size() * 2);
+    for (auto& b : cur) {
+      if (box_size(b) < 2) return false;
+      const int w = b.x1 - b.x0, h = b.y1 - b.y0;
+      if (w >= h) {
+        const int xm = b.x0 + (w + 1) / 2;
+        nxt.push_back({b.x0, xm, b.y0, b.y1});
+        nxt.push_back({xm, b.x1, b.y0, b.y1});
+      } else {
+        const int ym = b.y0 + (h + 1) / 2;
+        nxt.push_back({b.x0, b.x1, b.y0, ym});
+        nxt.push_back({b.x0, b.x1, ym, b.y1});
+      }
+    }
+    levels.push_back(std::move(nxt));
+  }
+  L = (int)levels.size() - 1;
+  off.assign(L + 1, {});
+  sz.assign(L + 1, {});
+  for (int d = 0; d <= L; ++d) {
+    int o = 0;
+    for (auto& b : levels[d]) {
+      off[d].push_back(o);
+      sz[d].push_back(box_size(b));
+      o += box_size(b);
+    }
+  }
+  perm.clear();
+  leaf_max = 0;
+  for (auto& b : levels[L]) {
+    leaf_max = std::max(leaf_max, box_size(b));
+    for (int j = b.y0; j < b.y1; ++j)
+      for (int i = b.x0; i < b.x1; ++i) perm.push_back(j * nx + i);
+  }
+  return true;
+}
+
+template <class T> size_t HMat<T>::words(const Tree& tr) const {
+  if (kind == DIAG) return tr.M;
+  if (kind != HODLR) return 0;
+  size_t w = 0;
+  for (int s = 0; s < (1 << tr.L); ++s) w += (size_t)tr.sz[tr.L][s] * tr.sz[tr.L][s];
+  for (int d = 0; d < tr.L; ++d)
+    for (int s = 0; s < (2 << d); ++s) {
+      const auto& b = blk[Tree::bid(d, s)];
+      w += (size_t)b.k * (tr.sz[d + 1][s] + tr.sz[d + 1][s ^ 1]);
+    }
+  return w;
+}
+template struct HMat<float>;
+template struct HMat<double>;
+
+// ---------------------------------------------------------------- arena
+void* Arena::get(size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  while (ci_ < chunks_.size()) {
+    if (off_ + bytes <= chunks_[ci_].second) {
+      void* p = chunks_[ci_].first + off_;
+      off_ += bytes;
+      return p;
+    }
+    ++ci_;
+    off_ = 0;
+  }
+  const size_t csz = std::max(chunk_, bytes);
+  char* p = static_cast<char*>(ex_->dev_alloc(csz));
+  chunks_.push_back({p, csz});
+  ci_ = chunks_.size() - 1;
+  off_ = bytes;
+  return p;
+}
+
+void Arena::free_all() {
+  for (auto& c : chunks_) ex_->dev_free(c.first);
+  chunks_.clear();
+  ci_ = off_ = 0;
+}
+
+size_t Arena::used() const {
+  size_t u = 0;
+  for (size_t i = 0; i < ci_ && i < chunks_.size(); ++i) u += chunks_[i].second;
+  return u + off_;
+}
+
+size_t Arena::reserved() const {
+  size_t u = 0;
+  for (auto& c : chunks_) u += c.second;
+  return u;
+}
+
+// ---------------------------------------------------------------- exec
+namespace {
+std::mutex g_reg_mu;
+std::map<uintptr_t, size_t>& registry() {
+  static std::map<uintptr_t, size_t> r;
+  return r;
+}
+void reg_add(void* p, size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_reg_mu);
+  registry()[(uintptr_t)p] = bytes;
+}
+void reg_del(void* p) {
+  std::lock_guard<std::mutex> lk(g_reg_mu);
+  registry().erase((uintptr_t)p);
+}
+}  // namespace
+
+void Exec::check_range(const void* p, size_t bytes, const char* what) const {
+  if (!checking || bytes == 0) return;
+  std::lock_guard<std::mutex> lk(g_reg_mu);
+  auto& r = registry();
+  const uintptr_t a = (uintptr_t)p;
+  auto it = r.upper_bound(a);
+  if (p == nullptr || it == r.begin()) throw Failure(ST_HIP, std::string("bounds check: unknown pointer in ") + what);
+  --it;
+  if (a + bytes > it->first + it->second)
+    throw Failure(ST_HIP, std::string("bounds check: access past allocation end in ") + what);
+}
+
+namespace {
+inline size_t ext(int rows, int cols, int64_t ld) {
+  if (rows <= 0 || cols <= 0) return 0;
+  return (size_t)(cols - 1) * (size_t)ld + (size_t)rows;
+}
+}  // namespace
+
+void Exec::init(hipStream_t s, const Allocator& a) {
+  const char* ck = std::getenv("ACR_CHECK");
+  checking = ck && ck[0] == '1';
+  stream = s;
+  al = a;
+  ring_bytes_ = size_t(64) << 20;
+  hip_check(hipHostMalloc((void**)&h_ring_, ring_bytes_, hipHostMallocDefault), "hipHostMalloc(ring)");
+  d_ring_ = static_cast<char*>(dev_alloc(ring_bytes_));
+  d_flags = static_cast<int*>(dev_alloc(NFLAGS * sizeof(int)));
+  hip_check(hipHostMalloc((void**)&h_flags, NFLAGS * sizeof(int), hipHostMallocDefault), "hipHostMalloc(flags)");
+  clear_flags();
+}
+
+void Exec::destroy() {
+  (void)hipDeviceSynchronize();
+  if (h_ring_) (void)hipHostFree(h_ring_);
+  if (h_flags) (void)hipHostFree(h_flags);
+  if (d_ring_) dev_free(d_ring_);
+  if (d_flags) dev_free(d_flags);
+  h_ring_ = nullptr; h_flags = nullptr; d_ring_ = nullptr; d_flags = nullptr;
+}
+
+void* Exec::dev_alloc(size_t bytes) {
+  void* p = nullptr;
+  if (al.alloc) {
+    p = al.alloc(bytes, al.ctx, stream);
+    if (!p) throw Failure(ST_OOM, "allocator callback returned NULL");
+  } else {
+    hip_check(hipMalloc(&p, bytes), "hipMalloc");
+  }
+  reg_add(p, bytes);
+  return p;
+}
+
+void Exec::dev_free(void* p) {
+  if (!p) return;
+  reg_del(p);
+  if (al.release) {
+    al.release(p, al.ctx, stream);
+    return;
+  }
+  (void)hipFree(p);  // hipFree waits for the device to finish with the memory
+}
+
+void Exec::sync() { hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+
+const void* Exec::upload_bytes(const void* src, size_t bytes) {
+  if (bytes == 0) return nullptr;
+  if (rec_arena) {
+    void* d = rec_arena->get(bytes);
+    hip_check(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(plan tasks)");
+    return d;
+  }
+  const size_t b = (bytes + 255) & ~size_t(255);
+  if (b > ring_bytes_) {
+    // oversized batch: a dedicated buffer released at the next sync point
+    sync();
+    void* d = dev_alloc(b);
+    hip_check(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(tasks)");
+    oversized_.push_back(d);
+    return d;
+  }
+  if (ring_off_ + b > ring_bytes_) {
+    sync();  // every earlier launch that read the ring has completed
+    ring_off_ = 0;
+    for (void* p : oversized_) dev_free(p);
+    oversized_.clear();
+  }
+  std::memcpy(h_ring_ + ring_off_, src, bytes);
+  hip_check(hipMemcpyAsync(d_ring_ + ring_off_, h_ring_ + ring_off_, bytes, hipMemcpyHostToDevice, stream),
+            "hipMemcpyAsync(tasks)");
+  const void* d = d_ring_ + ring_off_;
+  ring_off_ += b;
+  return d;
+}
+
+void Exec::submit(std::function<void(hipStream_t)> f) {
+  ++launches;
+  if (rec) {
+    rec->push_back(f);
+    return;
+  }
+  f(stream);
+  hip_check(hipGetLastError(), "kernel launch");
+}
+
+void Exec::clear_flags() {
+  hip_check(hipMemsetAsync(d_flags, 0, NFLAGS * sizeof(int), stream), "hipMemsetAsync(flags)");
+}
+
+void Exec::read_flags(int out[NFLAGS]) {
+  hip_check(hipMemcpyAsync(h_flags, d_flags, NFLAGS * sizeof(int), hipMemcpyDeviceToHost, stream),
+            "hipMemcpyAsync(flags)");
+  sync();
+  for (int i = 0; i < NFLAGS; ++i) out[i] = h_flags[i];
+}
+
+template <class T> void Exec::gemm(const std::vector<GemmTask>& t) {
+  if (t.empty()) return;
+  if (checking)
+    for (auto& x : t) {
+      if (x.m < 0 || x.n < 0 || x.k < 0) throw Failure(ST_HIP, "bounds check: negative gemm size");
+      const size_t e = sizeof(T);
+      check_range(x.A, e * (x.ta ? ext(x.k, x.m, x.lda) : ext(x.m, x.k, x.lda)), "gemm A");
+      check_range(x.B, e * (x.tb ? ext(x.n, x.k, x.ldb) : ext(x.k, x.n, x.ldb)), "gemm B");
+      check_range(x.C, e * ext(x.m, x.n, x.ldc), "gemm C");
+      if ((x.ta ? x.lda < x.k : x.lda < x.m) && x.m * x.k > 0) throw Failure(ST_HIP, "bounds check: gemm lda");
+      if ((x.tb ? x.ldb < x.n : x.ldb < x.k) && x.n * x.k > 0) throw Failure(ST_HIP, "bounds check: gemm ldb");
+      if (x.ldc < x.m && x.m * x.n > 0) throw Failure(ST_HIP, "bounds check: gemm ldc");
+    }
+  std::vector<int> first(t.size()), tile_task;
+  int nt = 0;
+  for (size_t i = 0; i < t.size(); ++i) {
+    first[i] = nt;
+    const int tiles = ((t[i].m + 63) / 64) * ((t[i].n + 63) / 64);
+    for (int j = 0; j < tiles; ++j) tile_task.push_back((int)i);
+    nt += tiles;
+    flops_gemm += 2.0 * t[i].m * t[i].n * t[i].k;
+  }
+  if (nt == 0) return;
+  const GemmTask* dt = upload(t);
+  const int* dtt = upload(tile_task);
+  const int* dft = upload(first);
+  submit([=](hipStream_t s) { launch_gemm<T>(dt, dtt, dft, nt, s); });
+}
+
+template <class T> void Exec::copy(const std::vector<CopyTask>& t) {
+  if (t.empty()) return;
+  if (checking)
+    for (auto& x : t) {
+      const size_t e = sizeof(T);
+      if (x.src) check_range(x.src, e * ext(x.m, x.n, x.lds), "copy src");
+      check_range(x.dst, e * ext(x.m, x.n, x.ldd), "copy dst");
+      if (x.rs) check_range(x.rs, e * x.m, "copy rs");
+      if (x.cs) check_range(x.cs, e * x.n, "copy cs");
+      if (x.ldd < x.m || (x.src && x.lds < x.m)) throw Failure(ST_HIP, "bounds check: copy ld");
+    }
+  const CopyTask* dt = upload(t);
+  const int n = (int)t.size();
+  submit([=](hipStream_t s) { launch_copy<T>(dt, n, s); });
+}
+
+template <class T> void Exec::inverse(const std::vector<InvTask>& t) {
+  if (t.empty()) return;
+  if (checking)
+    for (auto& x : t) {
+      check_range(x.A, sizeof(T) * ext(x.s, x.s, x.lda), "inverse");
+      if (x.lda < x.s) throw Failure(ST_HIP, "bounds check: inverse ld");
+    }
+  int mx = 0;
+  for (auto& x : t) {
+    mx = std::max(mx, x.s);
+    flops_inv += 2.0 * x.s * x.s * (double)x.s;
+  }
+  const InvTask* dt = upload(t);
+  const int n = (int)t.size();
+  int* fl = d_flags;
+  submit([=](hipStream_t s) { launch_inverse<T>(dt, n, mx, fl, s); });
+}
+
+template <class T> void Exec::qr(const std::vector<QrTask>& t) {
+  if (t.empty()) return;
+  if (checking)
+    for (auto& x : t) {
+      check_range(x.A, sizeof(T) * ext(x.m, x.r, x.lda), "qr panel");
+      check_range(x.tau, sizeof(T) * std::min(x.m, x.r), "qr tau");
+      if (x.lda < x.m) throw Failure(ST_HIP, "bounds check: qr ld");
+    }
+  for (auto& x : t) {
+    const double m = x.m, r = std::min(x.m, x.r);
+    flops_qr += 2.0 * m * x.r * r - 2.0 / 3.0 * r * r * r;
+  }
+  const QrTask* dt = upload(t);
+  const int n = (int)t.size();
+  submit([=](hipStream_t s) { launch_qr<T>(dt, n, s); });
+}
+
+template <class T> void Exec::svd(const std::vector<SvdTask>& t, double eps) {
+  if (t.empty()) return;
+  if (checking)
+    for (auto& x : t) {
+      check_range(x.Ru, sizeof(T) * ext(x.p, x.r, x.ldu), "svd Ru");
+      check_range(x.Rv, sizeof(T) * ext(x.q, x.r, x.ldv), "svd Rv");
+      check_range(x.C, sizeof(double) * 2 * (size_t)x.p * x.q, "svd C");
+      check_range(x.Y, sizeof(double) * 2 * (size_t)x.q * x.q, "svd Y");
+      check_range(x.sig, sizeof(double) * x.q, "svd sig");
+      check_range(x.rank_out, sizeof(int), "svd rank");
+      if (x.ldu < x.p || x.ldv < x.q) throw Failure(ST_HIP, "bounds check: svd ld");
+    }
+  for (auto& x : t) flops_svd += 9.0 * x.q * x.q * (double)std::max(x.p, 1) * 6.0;
+  const SvdTask* dt = upload(t);
+  const int n = (int)t.size();
+  int* fl = d_flags;
+  submit([=](hipStream_t s) { launch_svd<T>(dt, n, eps, fl, s); });
+}
+
+template <class T> void Exec::applyq(const std::vector<ApplyQTask>& t) {
+  if (t.empty()) return;
+  if (checking)
+    for (auto& x : t) {
+      check_range(x.Aq, sizeof(T) * ext(x.m, x.p, x.lda), "applyq reflectors");
+      check_range(x.tau, sizeof(T) * x.p, "applyq tau");
+      check_range(x.Z, sizeof(double) * ext(x.p, x.k, x.ldz), "applyq Z");
+      check_range(x.out, sizeof(T) * ext(x.m, x.k, x.ldo), "applyq out");
+      if (x.p > x.m || x.ldo < x.m || x.lda < x.m) throw Failure(ST_HIP, "bounds check: applyq shape");
+    }
+  for (auto& x : t) flops_qr += 4.0 * x.m * x.p * (double)x.k;
+  const ApplyQTask* dt = upload(t);
+  const int n = (int)t.size();
+  submit([=](hipStream_t s) { launch_applyq<T>(dt, n, s); });
+}
+
+#define ACR_EXEC_INST(T)                                              \
+  template void Exec::gemm<T>(const std::vector<GemmTask>&);          \
+  template void Exec::copy<T>(const std::vector<CopyTask>&);          \
+  template void Exec::inverse<T>(const std::vector<InvTask>&);        \
+  template void Exec::qr<T>(const std::vector<QrTask>&);              \
+  template void Exec::svd<T>(const std::vector<SvdTask>&, double);    \
+  template void Exec::applyq<T>(const std::vector<ApplyQTask>&);
+ACR_EXEC_INST(float)
+ACR_EXEC_INST(double)
+
+}  // namespace acr
