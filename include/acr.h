@@ -55,7 +55,7 @@ typedef struct {
   int32_t leaf;              /* maximum points per leaf cluster of the planar bisection, >= 1 */
   int32_t max_rank;          /* cap on any truncated rank, 0 = none (exceeding it -> error)   */
   int32_t precision;         /* acr_precision_t                                                */
-  double inner_eps_ratio;    /* accumulators inside one operation use eps * ratio; 0 -> 0.1   */
+  double inner_eps_ratio;    /* accumulators inside one operation use eps * ratio; 0 -> 1     */
   /* optional device allocator (e.g. a framework's caching allocator); both NULL -> hipMalloc */
   void* (*alloc)(size_t bytes, void* ctx, hipStream_t stream);
   void (*release)(void* ptr, void* ctx, hipStream_t stream);

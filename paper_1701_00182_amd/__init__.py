@@ -127,7 +127,7 @@ def _rhs_view(b, N):
 class Factor:
     """ACR factorisation of a 7-point operator given as coef[7, nz, ny, nx] (FP64, CUDA)."""
 
-    def __init__(self, coef, eps=1e-6, leaf=64, precision="fp64", max_rank=0, inner_eps_ratio=0.1):
+    def __init__(self, coef, eps=1e-6, leaf=64, precision="fp64", max_rank=0, inner_eps_ratio=1.0):
         L = lib()
         if coef.dim() != 4 or coef.shape[0] != 7:
             raise ValueError("coef must be shaped (7, nz, ny, nx)")

@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 
@@ -238,6 +239,7 @@ template <class T> struct FactorT : FactorBase {
         dv.push_back(&D[q]);
         gv.push_back(&L.G[q]);
       }
+      ex.trace_tag = "inverse";
       hodlr_inverse<T>(ex, tr, dv, gv, tc, fac, work, tmp);
       // X = G E, Y = G F
       std::vector<HMat<T>> X(m), Y(m);
@@ -246,6 +248,7 @@ template <class T> struct FactorT : FactorBase {
         if (!E[q].absent()) pj.push_back(ProdJob<T>{&L.G[q], &E[q], &X[q], 1.0});
         if (!F[q].absent()) pj.push_back(ProdJob<T>{&L.G[q], &F[q], &Y[q], 1.0});
       }
+      ex.trace_tag = "GE-GF";
       hodlr_product<T>(ex, tr, pj, tc, levtmp, work, tmp);
       // kept planes
       const int mk = m / 2;
@@ -261,7 +264,9 @@ template <class T> struct FactorT : FactorBase {
           if (!X[q + 1].absent()) temp.push_back(ProdJob<T>{&F[q], &X[q + 1], &P2[o], 1.0});
         }
       }
+      ex.trace_tag = "E+F+";
       hodlr_product<T>(ex, tr, keep, tc, fac, work, tmp);
+      ex.trace_tag = "EY-FX";
       hodlr_product<T>(ex, tr, temp, tc, levtmp, work, tmp);
       std::vector<SumJob<T>> sj;
       for (int o = 0; o < mk; ++o) {
@@ -274,7 +279,9 @@ template <class T> struct FactorT : FactorBase {
       }
       const int nxt = cur ^ 1;
       lvl[nxt].reset();
+      ex.trace_tag = "D+";
       hodlr_sum<T>(ex, tr, sj, tc, lvl[nxt], tmp);
+      if (ex.trace) std::fprintf(stderr, "[acr] level %zu done\n", lev.size());
       lev.push_back(std::move(L));
       levtmp.reset();
       std::vector<int> na;
@@ -482,7 +489,7 @@ FactorBase* make_factor(const acr_options_t* o, const double* coef_in, hipStream
   f->tmp.init(&f->ex, big);
   if (!f->tr.build(o->nx, o->ny, o->leaf)) throw Failure(ST_INVALID, "leaf size forces a split of a single point");
   f->tc.eps = o->eps;
-  f->tc.eps_inner = o->eps * (o->inner_eps_ratio > 0 ? o->inner_eps_ratio : 0.1);
+  f->tc.eps_inner = o->eps * (o->inner_eps_ratio > 0 ? o->inner_eps_ratio : 1.0);
   f->tc.max_rank = o->max_rank;
   const char* ng = std::getenv("ACR_NO_GRAPH");
   f->use_graph = !(ng && ng[0] == '1');
@@ -699,7 +706,7 @@ void acr_options_default(acr_options_t* o) {
   o->eps = 1e-6;
   o->leaf = 64;
   o->precision = ACR_PREC_FP64;
-  o->inner_eps_ratio = 0.1;
+  o->inner_eps_ratio = 1.0;
 }
 
 acr_status_t acr_factor(const acr_options_t* opt, const double* coef, hipStream_t stream, acr_handle_t* out) {

@@ -99,13 +99,21 @@ class Exec {
   template <class T> void copy(const std::vector<CopyTask>& t);
   template <class T> void inverse(const std::vector<InvTask>& t);
   template <class T> void qr(const std::vector<QrTask>& t);
-  template <class T> void svd(const std::vector<SvdTask>& t, double eps);
+  // d_tvals: device array of the tasks' t_out values (contiguous, in task order)
+  template <class T> void svd(std::vector<SvdTask>& t, double eps, int* d_tvals);
   template <class T> void applyq(const std::vector<ApplyQTask>& t);
+  template <class T> void gram(const std::vector<GramTask>& t);
+  void pchol(const std::vector<PcholTask>& t, double tol);
+  void materialize_r(const std::vector<PcholTask>& t);
+  template <class T> void wtilde(const std::vector<WtTask>& t);
 
   // Host-side bounds check of every task against the live device allocations
   // (enabled with ACR_CHECK=1): a task that would touch memory outside one
   // allocation raises before anything is launched.
   bool checking = false;
+  bool trace = false;          // ACR_TRACE=1: one line per compression batch on stderr
+  bool gram_ok = true;         // ACR_GRAM=0 forces Householder compression everywhere
+  const char* trace_tag = "";
   void check_range(const void* p, size_t bytes, const char* what) const;
 
   // counters of launched algorithmic work (flops), by kernel class

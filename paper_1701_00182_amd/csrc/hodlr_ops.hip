@@ -12,6 +12,7 @@
 // low-rank terms) are accumulated top-down per segment and truncated at a
 // tighter inner tolerance.
 #include <algorithm>
+#include <cstdio>
 
 #include "hodlr.h"
 
@@ -50,23 +51,17 @@ template <class T> struct CJob {
   LR<T>* out;
 };
 
-// Truncated recompression of stacked low-rank sums (see file comment).
+// Householder path: QR of both stacks, Jacobi SVD of the core, Q [Z; 0].
 template <class T>
-void compress(Exec& ex, std::vector<CJob<T>>& jobs, double eps, int max_rank, Arena& out, Arena& tmp) {
-  std::vector<CJob<T>*> live;
-  for (auto& j : jobs) {
-    if (j.r == 0 || j.m == 0 || j.n == 0) {
-      *j.out = LR<T>{};
-    } else {
-      live.push_back(&j);
-    }
-  }
+void compress_householder(Exec& ex, std::vector<CJob<T>*>& live, double eps, int max_rank, Arena& out,
+                          Arena& tmp) {
   if (live.empty()) return;
   const auto mk = tmp.mark();
   const int nj = (int)live.size();
   std::vector<QrTask> qt;
   std::vector<SvdTask> st;
   int* d_rank = tmp.get_n<int>(nj);
+  int* d_tv = tmp.get_n<int>(nj);
   qt.reserve(2 * nj);
   st.reserve(nj);
   std::vector<T*> tau_u(nj), tau_v(nj);
@@ -81,16 +76,20 @@ void compress(Exec& ex, std::vector<CJob<T>>& jobs, double eps, int max_rank, Ar
     double* sig = tmp.get_n<double>(q);
     qt.push_back(QrTask{j.Us, tau_u[i], j.m, j.m, j.r});
     qt.push_back(QrTask{j.Vs, tau_v[i], j.n, j.n, j.r});
-    SvdTask s;
+    SvdTask s{};
     s.Ru = j.Us; s.Rv = j.Vs; s.ldu = j.m; s.ldv = j.n;
     s.p = p; s.q = q; s.r = j.r;
     s.C = Cw[i]; s.Y = Yw[i]; s.sig = sig;
     s.rank_out = d_rank + i;
     s.max_rank = max_rank;
+    s.mode = 0;
+    s.perm = tmp.get_n<int>(q);
+    s.t_out = d_tv + i;
+    s.tmp = tmp.get_n<double>(j.r);
     st.push_back(s);
   }
   ex.qr<T>(qt);
-  ex.svd<T>(st, eps);
+  ex.svd<T>(st, eps, d_tv);
   std::vector<int> ranks(nj);
   hip_check(hipMemcpyAsync(ranks.data(), d_rank, nj * sizeof(int), hipMemcpyDeviceToHost, ex.stream),
             "hipMemcpyAsync(ranks)");
@@ -119,6 +118,153 @@ void compress(Exec& ex, std::vector<CJob<T>>& jobs, double eps, int max_rank, Ar
   }
   ex.applyq<T>(at);
   tmp.release(mk);
+}
+
+// Gram path for stacks too large for one workgroup (see gram.hip).
+template <class T>
+void compress_gram(Exec& ex, std::vector<CJob<T>*>& live, double eps, int max_rank, Arena& out, Arena& tmp) {
+  if (live.empty()) return;
+  const auto mk = tmp.mark();
+  const int nj = (int)live.size();
+  // directions of a stack below tau * its largest column norm are dropped: their
+  // contribution to the block is below tau * ||U|| ||V||, far under eps * sigma_1
+  const double tau = std::min(1e-6, 0.01 * eps);
+  std::vector<GramTask> gt_;
+  std::vector<PcholTask> pc;
+  int* d_r1 = tmp.get_n<int>(2 * nj);
+  auto chunk_rows = [](int m) { return std::max(256, ((m + 7) / 8 + 31) / 32 * 32); };
+  for (int i = 0; i < nj; ++i) {
+    const CJob<T>& j = *live[i];
+    for (int side = 0; side < 2; ++side) {
+      const int m = side ? j.n : j.m, r = j.r;
+      GramTask g{};
+      g.A = side ? j.Vs : j.Us;
+      g.lda = m;
+      g.m = m;
+      g.r = r;
+      g.rows_per_chunk = chunk_rows(m);
+      const int nch = (m + g.rows_per_chunk - 1) / g.rows_per_chunk;
+      g.part = tmp.get_n<double>((size_t)nch * r * r);
+      g.G = tmp.get_n<double>((size_t)r * r);
+      gt_.push_back(g);
+      PcholTask p{};
+      p.G = g.G;
+      p.L = tmp.get_n<double>((size_t)r * r);
+      p.perm = tmp.get_n<int>(r);
+      p.d = tmp.get_n<double>(r);
+      p.rank_out = d_r1 + 2 * i + side;
+      p.r = r;
+      pc.push_back(p);
+    }
+  }
+  ex.gram<T>(gt_);
+  ex.pchol(pc, tau * tau);
+  std::vector<int> r1(2 * nj);
+  hip_check(hipMemcpyAsync(r1.data(), d_r1, r1.size() * sizeof(int), hipMemcpyDeviceToHost, ex.stream),
+            "hipMemcpyAsync(gram ranks)");
+  ex.sync();
+  std::vector<PcholTask> mat;
+  std::vector<SvdTask> st;
+  std::vector<int> idx;
+  int* d_rank = tmp.get_n<int>(nj);
+  int* d_tv = tmp.get_n<int>(nj);
+  std::vector<double*> Cw(nj, nullptr), Yw(nj, nullptr);
+  for (int i = 0; i < nj; ++i) {
+    PcholTask& pu = pc[2 * i];
+    PcholTask& pv = pc[2 * i + 1];
+    pu.r1 = r1[2 * i];
+    pv.r1 = r1[2 * i + 1];
+    if (pu.r1 == 0 || pv.r1 == 0) continue;
+    pu.R = tmp.get_n<double>((size_t)pu.r1 * pu.r);
+    pv.R = tmp.get_n<double>((size_t)pv.r1 * pv.r);
+    mat.push_back(pu);
+    mat.push_back(pv);
+    const int p = pu.r1, q = pv.r1;
+    Cw[i] = tmp.get_n<double>(2 * (size_t)p * q);
+    Yw[i] = tmp.get_n<double>(2 * (size_t)q * q);
+    SvdTask s{};
+    s.Ru = pu.R; s.Rv = pv.R; s.ldu = p; s.ldv = q;
+    s.p = p; s.q = q; s.r = live[i]->r;
+    s.C = Cw[i]; s.Y = Yw[i]; s.sig = tmp.get_n<double>(q);
+    s.rank_out = d_rank + i;
+    s.max_rank = max_rank;
+    s.mode = 1;
+    s.perm = tmp.get_n<int>(q);
+    s.t_out = d_tv + st.size();
+    s.tmp = tmp.get_n<double>(live[i]->r);
+    st.push_back(s);
+    idx.push_back(i);
+  }
+  ex.materialize_r(mat);
+  ex.svd<T>(st, eps, d_tv);
+  std::vector<int> rk(nj, 0);
+  if (!st.empty()) {
+    hip_check(hipMemcpyAsync(rk.data(), d_rank, nj * sizeof(int), hipMemcpyDeviceToHost, ex.stream),
+              "hipMemcpyAsync(ranks)");
+    ex.sync();
+  }
+  std::vector<WtTask> wt;
+  std::vector<GemmTask> gg;
+  std::vector<T*> Wu(nj, nullptr), Wv(nj, nullptr);
+  std::vector<char> is_live(nj, 0);
+  for (int i : idx) is_live[i] = 1;
+  for (int i = 0; i < nj; ++i) {
+    CJob<T>& j = *live[i];
+    const int k = is_live[i] ? rk[i] : 0;
+    LR<T> o;
+    o.k = k;
+    if (k > 0) {
+      const PcholTask& pu = pc[2 * i];
+      const PcholTask& pv = pc[2 * i + 1];
+      const int p = pu.r1, q = pv.r1, r = j.r;
+      Wu[i] = tmp.get_n<T>((size_t)r * k);
+      Wv[i] = tmp.get_n<T>((size_t)r * k);
+      wt.push_back(WtTask{pu.L, pu.perm, Cw[i] + (size_t)p * q, p, Wu[i], r, p, k});
+      wt.push_back(WtTask{pv.L, pv.perm, Yw[i] + (size_t)q * q, q, Wv[i], r, q, k});
+      o.U = out.get_n<T>((size_t)j.m * k);
+      o.V = out.get_n<T>((size_t)j.n * k);
+      gg.push_back(gt<T>(j.Us, j.m, 0, Wu[i], r, 0, o.U, j.m, j.m, k, r, 1.0, 0.0));
+      gg.push_back(gt<T>(j.Vs, j.n, 0, Wv[i], r, 0, o.V, j.n, j.n, k, r, 1.0, 0.0));
+    }
+    *j.out = o;
+  }
+  ex.wtilde<T>(wt);
+  ex.gemm<T>(gg);
+  tmp.release(mk);
+}
+
+// Truncated recompression of stacked low-rank sums (see file comment): small
+// problems and exact mode use Householder QR; large ones the Gram path.
+template <class T>
+void compress(Exec& ex, std::vector<CJob<T>>& jobs, double eps, int max_rank, Arena& out, Arena& tmp) {
+  std::vector<CJob<T>*> hh, gr;
+  for (auto& j : jobs) {
+    if (j.r == 0 || j.m == 0 || j.n == 0) {
+      *j.out = LR<T>{};
+      continue;
+    }
+    const int p = std::min(j.m, j.r), q = std::min(j.n, j.r);
+    QrTask qu{nullptr, nullptr, j.m, j.m, j.r}, qv{nullptr, nullptr, j.n, j.n, j.r};
+    SvdTask sv{};
+    sv.p = p;
+    sv.q = q;
+    const bool fits = lds_bytes_qr(qu, sizeof(T)) <= kLdsBudget && lds_bytes_qr(qv, sizeof(T)) <= kLdsBudget &&
+                      lds_bytes_qrcp(sv) <= kLdsBudget;
+    (!fits && ex.gram_ok && eps >= 1e-4 ? gr : hh).push_back(&j);
+  }
+  if (ex.trace) {
+    int mm = 0, mr = 0;
+    double w = 0;
+    for (auto& j : jobs) {
+      mm = std::max(mm, std::max(j.m, j.n));
+      mr = std::max(mr, j.r);
+      w += (double)j.r * j.r * (j.m + j.n);
+    }
+    std::fprintf(stderr, "[acr] compress %s n=%zu hh=%zu gram=%zu max_m=%d max_r=%d work=%.3g\n", ex.trace_tag,
+                 jobs.size(), hh.size(), gr.size(), mm, mr, w);
+  }
+  compress_householder<T>(ex, hh, eps, max_rank, out, tmp);
+  compress_gram<T>(ex, gr, eps, max_rank, out, tmp);
 }
 
 inline int nseg(int d) { return 1 << d; }

@@ -51,18 +51,24 @@ struct QrTask {
   int m, r;
 };
 
-// Truncated SVD of the core Ru * Rv^T (p x q, p = min(mu, r), q = min(mv, r))
-// by one-sided Jacobi in FP64; writes Zu = X_k Sigma_k (p x k), Zv = Y_k (q x k)
+// Truncated SVD of the core C = Ru * Rv^T (p x q) in FP64: column-pivoted QR of
+// C, then one-sided Jacobi; writes Zu = X_k Sigma_k (p x k, at C + p*q, ld p) and
+// Zv = Y_k (q x k, at Y + q*q, ld q)
 struct SvdTask {
-  const void* Ru;   // panel holding R of the U stack (ld ldu)
-  const void* Rv;   // panel holding R of the V stack (ld ldv)
+  const void* Ru;   // R factor of the U stack (ld ldu)
+  const void* Rv;   // R factor of the V stack (ld ldv)
   int64_t ldu, ldv;
   int p, q, r;
-  double* C;        // p x q workspace (becomes X * Sigma)
-  double* Y;        // q x q workspace (right rotations)
+  double* C;        // 2 p q workspace
+  double* Y;        // 2 q q workspace
   double* sig;      // q workspace
+  int* perm;        // q workspace (column pivots)
+  int* t_out;       // numerical rank found by the pivoted QR
+  double* tmp;      // r workspace
   int* rank_out;
   int max_rank;     // 0 = unlimited
+  int mode;         // 0: Ru, Rv upper-trapezoidal panels in T; 1: full FP64 factors
+  int tc;           // host copy of *t_out (used to size the Jacobi stage)
 };
 
 // out (m x k) = Q * [Z; 0] with Q the product of the panel's reflectors
@@ -75,6 +81,39 @@ struct ApplyQTask {
   int m, p, k;
 };
 
+// S^T S of an m x r stack in FP64, from per-chunk partial sums reduced in order
+struct GramTask {
+  const void* A;
+  int64_t lda;
+  int m, r;
+  int rows_per_chunk;
+  double* part;   // nchunk x r x r
+  double* G;      // r x r
+};
+
+// Pivoted Cholesky G[perm, perm] ~= L L^T (L r x rank), then R (rank x r) in the
+// original column order
+struct PcholTask {
+  const double* G;
+  double* L;       // r x r workspace
+  int* perm;       // r
+  double* d;       // r workspace
+  int* rank_out;
+  int r;
+  int r1;          // rank (host fills it in before materialising R)
+  double* R;       // r1 x r
+};
+
+// W (r x k, precision T) = P1 L11^{-T} Z  (Z r1 x k FP64, overwritten)
+struct WtTask {
+  const double* L;
+  const int* perm;
+  double* Z;
+  int64_t ldz;
+  void* W;
+  int r, r1, k;
+};
+
 enum : int { FLAG_SINGULAR = 0, FLAG_RANK = 1, FLAG_NONFINITE = 2, FLAG_INVALID = 3, NFLAGS = 8 };
 
 template <class T> void launch_gemm(const GemmTask* d_tasks, const int* d_tile_task,
@@ -82,9 +121,21 @@ template <class T> void launch_gemm(const GemmTask* d_tasks, const int* d_tile_t
 template <class T> void launch_copy(const CopyTask* d_tasks, int ntasks, hipStream_t s);
 template <class T> void launch_inverse(const InvTask* d_tasks, int ntasks, int max_s,
                                        int* d_flags, hipStream_t s);
-template <class T> void launch_qr(const QrTask* d_tasks, int ntasks, hipStream_t s);
-template <class T> void launch_svd(const SvdTask* d_tasks, int ntasks, double eps,
-                                   int* d_flags, hipStream_t s);
-template <class T> void launch_applyq(const ApplyQTask* d_tasks, int ntasks, hipStream_t s);
+// LDS-resident variants; `lds` is the dynamic shared memory per workgroup
+template <class T> void launch_qr_lds(const QrTask* d_tasks, int ntasks, size_t lds, hipStream_t s);
+template <class T> void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, hipStream_t s);
+template <class T> void launch_jacobi(const SvdTask* d_tasks, int ntasks, double eps, int* d_flags, size_t lds,
+                                      hipStream_t s);
+template <class T> void launch_applyq_lds(const ApplyQTask* d_tasks, int ntasks, size_t lds, hipStream_t s);
+template <class T> void launch_gram(const GramTask* d_tasks, int ntasks, const int* d_tile_task,
+                                   const int* d_first_tile, int ntiles, hipStream_t s);
+void launch_pchol(const PcholTask* d_tasks, int ntasks, double tol, hipStream_t s);
+void launch_materialize_r(const PcholTask* d_tasks, int ntasks, hipStream_t s);
+template <class T> void launch_wtilde(const WtTask* d_tasks, int ntasks, hipStream_t s);
+constexpr size_t kLdsBudget = 156 * 1024;
+inline size_t lds_bytes_qr(const QrTask& t, size_t w) { return (size_t)t.m * t.r * w; }
+inline size_t lds_bytes_qrcp(const SvdTask& t) { return ((size_t)t.p * t.q + t.q) * 8 + (size_t)t.q * 4; }
+inline size_t lds_bytes_jacobi(const SvdTask& t) { return (size_t)t.q * t.tc * 8; }
+inline size_t lds_bytes_applyq(const ApplyQTask& t, size_t w) { return ((size_t)t.m * t.p + (size_t)t.m * t.k) * w; }
 
 }  // namespace acr

@@ -1,0 +1,176 @@
+// Householder QR of stacked bases and the reconstruction Q [Z; 0], in an
+// LDS-resident instantiation for panels that fit the 160 KB local data share of
+// a CDNA4 compute unit and a global-memory one otherwise.  Trailing columns are
+// processed concurrently by groups of G lanes that reduce with intra-group
+// shuffles, so one workgroup keeps its 256 lanes busy even on 64 x 64 panels.
+#include <cmath>
+
+#include "kern.h"
+
+namespace acr {
+
+namespace {
+
+__device__ inline double gsum(double v, int G) {
+  for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+
+__device__ inline double block_sum4(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  const double s = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return s;
+}
+
+// lanes per column group for a column length of m
+__device__ inline int lanes_for_rows(int m) {
+  int G = 4;
+  while (G < 64 && G * 4 < m) G <<= 1;
+  return G;
+}
+
+template <class T, bool LDS>
+__global__ __launch_bounds__(256) void k_qr_lds(const QrTask* __restrict__ tasks) {
+  extern __shared__ double smq[];
+  const QrTask t = tasks[blockIdx.x];
+  T* A = static_cast<T*>(t.A);
+  T* tau = static_cast<T*>(t.tau);
+  const int m = t.m, r = t.r;
+  T* a = LDS ? reinterpret_cast<T*>(smq) : A;
+  const int64_t la = LDS ? m : t.lda;
+  if (LDS)
+    for (int e = threadIdx.x; e < m * r; e += 256) a[e] = A[(e % m) + (int64_t)(e / m) * t.lda];
+  __shared__ double red[4];
+  __shared__ double sh_tau, sh_scale, sh_beta;
+  const int G = lanes_for_rows(m), groups = 256 / G;
+  const int gi = threadIdx.x / G, gl = threadIdx.x % G;
+  const int nref = m < r ? m : r;
+  __syncthreads();
+  for (int j = 0; j < nref; ++j) {
+    T* col = a + j * la;
+    double ps = 0.0;
+    for (int i = j + 1 + threadIdx.x; i < m; i += 256) {
+      const double v = (double)col[i];
+      ps += v * v;
+    }
+    const double sigma = block_sum4(ps, red);
+    if (threadIdx.x == 0) {
+      const double x0 = (double)col[j];
+      if (sigma == 0.0) {
+        sh_tau = 0.0;
+        sh_beta = x0;
+        sh_scale = 0.0;
+      } else {
+        const double nrm = sqrt(x0 * x0 + sigma);
+        const double beta = x0 >= 0.0 ? -nrm : nrm;
+        sh_tau = (beta - x0) / beta;
+        sh_scale = 1.0 / (x0 - beta);
+        sh_beta = beta;
+      }
+      tau[j] = T(sh_tau);
+    }
+    __syncthreads();
+    const double tj = sh_tau;
+    if (tj != 0.0) {
+      const T sc = T(sh_scale);
+      for (int i = j + 1 + threadIdx.x; i < m; i += 256) col[i] *= sc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) col[j] = T(sh_beta);
+    if (tj != 0.0) {
+      for (int c = j + 1 + gi; c < r; c += groups) {
+        T* ac = a + c * la;
+        double w = 0.0;
+        for (int i = j + gl; i < m; i += G) w += (i == j ? 1.0 : (double)col[i]) * (double)ac[i];
+        w = gsum(w, G) * tj;
+        for (int i = j + gl; i < m; i += G) ac[i] = T((double)ac[i] - w * (i == j ? 1.0 : (double)col[i]));
+      }
+    }
+    __syncthreads();
+  }
+  if (LDS)
+    for (int e = threadIdx.x; e < m * r; e += 256) A[(e % m) + (int64_t)(e / m) * t.lda] = a[e];
+}
+
+template <class T, bool LDS>
+__global__ __launch_bounds__(256) void k_applyq_lds(const ApplyQTask* __restrict__ tasks) {
+  extern __shared__ double sma[];
+  const ApplyQTask t = tasks[blockIdx.x];
+  const int m = t.m, p = t.p, k = t.k;
+  if (k == 0 || m == 0) return;
+  const T* Aq = static_cast<const T*>(t.Aq);
+  const T* tau = static_cast<const T*>(t.tau);
+  T* out = static_cast<T*>(t.out);
+  const T* v = LDS ? reinterpret_cast<T*>(sma) : Aq;
+  const int64_t lv = LDS ? m : t.lda;
+  T* o = LDS ? reinterpret_cast<T*>(sma) + m * p : out;
+  const int64_t lo = LDS ? m : t.ldo;
+  if (LDS)
+    for (int e = threadIdx.x; e < m * p; e += 256)
+      reinterpret_cast<T*>(sma)[e] = Aq[(e % m) + (int64_t)(e / m) * t.lda];
+  for (int e = threadIdx.x; e < m * k; e += 256) {
+    const int i = e % m, c = e / m;
+    o[i + c * lo] = i < p ? T(t.Z[i + (int64_t)c * t.ldz]) : T(0);
+  }
+  const int G = lanes_for_rows(m), groups = 256 / G;
+  const int gi = threadIdx.x / G, gl = threadIdx.x % G;
+  __syncthreads();
+  for (int j = p - 1; j >= 0; --j) {
+    const double tj = (double)tau[j];
+    if (tj == 0.0) continue;
+    const T* vj = v + j * lv;
+    for (int c = gi; c < k; c += groups) {
+      T* oc = o + c * lo;
+      double w = 0.0;
+      for (int i = j + gl; i < m; i += G) w += (i == j ? 1.0 : (double)vj[i]) * (double)oc[i];
+      w = gsum(w, G) * tj;
+      for (int i = j + gl; i < m; i += G) oc[i] = T((double)oc[i] - w * (i == j ? 1.0 : (double)vj[i]));
+    }
+    __syncthreads();
+  }
+  if (LDS)
+    for (int e = threadIdx.x; e < m * k; e += 256) out[(e % m) + (int64_t)(e / m) * t.ldo] = o[e];
+}
+
+template <class K> void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+}
+
+}  // namespace
+
+// lds == 0 selects the global-memory instantiation (same algorithm)
+template <class T> void launch_qr_lds(const QrTask* d_tasks, int ntasks, size_t lds, hipStream_t s) {
+  if (ntasks <= 0) return;
+  if (lds == 0) {
+    hipLaunchKernelGGL((k_qr_lds<T, false>), dim3(ntasks), dim3(256), 0, s, d_tasks);
+    return;
+  }
+  allow_lds(k_qr_lds<T, true>, lds);
+  hipLaunchKernelGGL((k_qr_lds<T, true>), dim3(ntasks), dim3(256), lds, s, d_tasks);
+}
+
+template <class T> void launch_applyq_lds(const ApplyQTask* d_tasks, int ntasks, size_t lds, hipStream_t s) {
+  if (ntasks <= 0) return;
+  if (lds == 0) {
+    hipLaunchKernelGGL((k_applyq_lds<T, false>), dim3(ntasks), dim3(256), 0, s, d_tasks);
+    return;
+  }
+  allow_lds(k_applyq_lds<T, true>, lds);
+  hipLaunchKernelGGL((k_applyq_lds<T, true>), dim3(ntasks), dim3(256), lds, s, d_tasks);
+}
+
+#define ACR_LDS_INST(T)                                                                           \
+  template void launch_qr_lds<T>(const QrTask*, int, size_t, hipStream_t);                        \
+  template void launch_applyq_lds<T>(const ApplyQTask*, int, size_t, hipStream_t);
+ACR_LDS_INST(float)
+ACR_LDS_INST(double)
+#undef ACR_LDS_INST
+
+}  // namespace acr

@@ -160,6 +160,10 @@ inline size_t ext(int rows, int cols, int64_t ld) {
 void Exec::init(hipStream_t s, const Allocator& a) {
   const char* ck = std::getenv("ACR_CHECK");
   checking = ck && ck[0] == '1';
+  const char* tr = std::getenv("ACR_TRACE");
+  trace = tr && tr[0] == '1';
+  const char* gm = std::getenv("ACR_GRAM");
+  gram_ok = !(gm && gm[0] == '0');
   stream = s;
   al = a;
   ring_bytes_ = size_t(64) << 20;
@@ -254,6 +258,29 @@ void Exec::read_flags(int out[NFLAGS]) {
   for (int i = 0; i < NFLAGS; ++i) out[i] = h_flags[i];
 }
 
+// Splits tasks by the local memory they need: one launch per size class of the
+// LDS-resident kernel (so small problems are not limited by the occupancy of
+// large ones), one launch of the global-memory kernel for the rest.
+template <class Task, class Need, class Launch>
+void bucketed(const std::vector<Task>& t, Need need, Launch launch) {
+  static const size_t cls[] = {16 * 1024, 32 * 1024, 64 * 1024, 96 * 1024, kLdsBudget};
+  std::vector<Task> b[6];
+  for (const Task& x : t) {
+    const size_t n = need(x);
+    int c = 5;
+    for (int i = 0; i < 5; ++i)
+      if (n <= cls[i]) { c = i; break; }
+    b[c].push_back(x);
+  }
+  for (int i = 0; i < 5; ++i)
+    if (!b[i].empty()) {
+      size_t mx = 0;
+      for (const Task& x : b[i]) mx = std::max(mx, need(x));
+      launch(b[i], std::max<size_t>(mx, 16));
+    }
+  if (!b[5].empty()) launch(b[5], 0);
+}
+
 template <class T> void Exec::gemm(const std::vector<GemmTask>& t) {
   if (t.empty()) return;
   if (checking)
@@ -329,28 +356,55 @@ template <class T> void Exec::qr(const std::vector<QrTask>& t) {
     const double m = x.m, r = std::min(x.m, x.r);
     flops_qr += 2.0 * m * x.r * r - 2.0 / 3.0 * r * r * r;
   }
-  const QrTask* dt = upload(t);
-  const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_qr<T>(dt, n, s); });
+  bucketed(t, [](const QrTask& x) { return lds_bytes_qr(x, sizeof(T)); },
+           [this](const std::vector<QrTask>& b, size_t lds) {
+             const QrTask* dt = upload(b);
+             const int n = (int)b.size();
+             if (lds) submit([=](hipStream_t s) { launch_qr_lds<T>(dt, n, lds, s); });
+             else submit([=](hipStream_t s) { launch_qr_lds<T>(dt, n, 0, s); });
+           });
 }
 
-template <class T> void Exec::svd(const std::vector<SvdTask>& t, double eps) {
+template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tvals) {
   if (t.empty()) return;
   if (checking)
     for (auto& x : t) {
-      check_range(x.Ru, sizeof(T) * ext(x.p, x.r, x.ldu), "svd Ru");
-      check_range(x.Rv, sizeof(T) * ext(x.q, x.r, x.ldv), "svd Rv");
+      const size_t rw = x.mode == 1 ? sizeof(double) : sizeof(T);
+      check_range(x.Ru, rw * ext(x.p, x.r, x.ldu), "svd Ru");
+      check_range(x.Rv, rw * ext(x.q, x.r, x.ldv), "svd Rv");
       check_range(x.C, sizeof(double) * 2 * (size_t)x.p * x.q, "svd C");
       check_range(x.Y, sizeof(double) * 2 * (size_t)x.q * x.q, "svd Y");
+      check_range(x.perm, sizeof(int) * x.q, "svd perm");
       check_range(x.sig, sizeof(double) * x.q, "svd sig");
+      check_range(x.tmp, sizeof(double) * x.r, "svd tmp");
+      check_range(x.t_out, sizeof(int), "svd t");
       check_range(x.rank_out, sizeof(int), "svd rank");
       if (x.ldu < x.p || x.ldv < x.q) throw Failure(ST_HIP, "bounds check: svd ld");
     }
-  for (auto& x : t) flops_svd += 9.0 * x.q * x.q * (double)std::max(x.p, 1) * 6.0;
-  const SvdTask* dt = upload(t);
-  const int n = (int)t.size();
+  const double delta = eps > 0.0 ? 0.01 * eps : 0.0;
+  for (auto& x : t) flops_svd += 4.0 * x.p * x.q * (double)std::min(x.p, x.q);
+  bucketed(t, [](const SvdTask& x) { return lds_bytes_qrcp(x); },
+           [this, delta](const std::vector<SvdTask>& b, size_t lds) {
+             const SvdTask* dt = upload(b);
+             const int n = (int)b.size();
+             submit([=](hipStream_t s) { launch_qrcp<T>(dt, n, delta, lds, s); });
+           });
+  // numerical ranks of the cores size the Jacobi stage
+  std::vector<int> tv(t.size());
+  hip_check(hipMemcpyAsync(tv.data(), d_tvals, tv.size() * sizeof(int), hipMemcpyDeviceToHost, stream),
+            "hipMemcpyAsync(core ranks)");
+  sync();
+  for (size_t i = 0; i < t.size(); ++i) {
+    t[i].tc = tv[i];
+    flops_svd += 6.0 * (double)t[i].q * tv[i] * tv[i] * 4.0;
+  }
   int* fl = d_flags;
-  submit([=](hipStream_t s) { launch_svd<T>(dt, n, eps, fl, s); });
+  bucketed(t, [](const SvdTask& x) { return lds_bytes_jacobi(x); },
+           [this, eps, fl](const std::vector<SvdTask>& b, size_t lds) {
+             const SvdTask* dt = upload(b);
+             const int n = (int)b.size();
+             submit([=](hipStream_t s) { launch_jacobi<T>(dt, n, eps, fl, lds, s); });
+           });
 }
 
 template <class T> void Exec::applyq(const std::vector<ApplyQTask>& t) {
@@ -364,9 +418,74 @@ template <class T> void Exec::applyq(const std::vector<ApplyQTask>& t) {
       if (x.p > x.m || x.ldo < x.m || x.lda < x.m) throw Failure(ST_HIP, "bounds check: applyq shape");
     }
   for (auto& x : t) flops_qr += 4.0 * x.m * x.p * (double)x.k;
-  const ApplyQTask* dt = upload(t);
+  bucketed(t, [](const ApplyQTask& x) { return lds_bytes_applyq(x, sizeof(T)); },
+           [this](const std::vector<ApplyQTask>& b, size_t lds) {
+             const ApplyQTask* dt = upload(b);
+             const int n = (int)b.size();
+             if (lds) submit([=](hipStream_t s) { launch_applyq_lds<T>(dt, n, lds, s); });
+             else submit([=](hipStream_t s) { launch_applyq_lds<T>(dt, n, 0, s); });
+           });
+}
+
+template <class T> void Exec::gram(const std::vector<GramTask>& t) {
+  if (t.empty()) return;
+  std::vector<int> first(t.size()), tile_task;
+  int nt = 0;
+  for (size_t i = 0; i < t.size(); ++i) {
+    const GramTask& x = t[i];
+    if (checking) {
+      check_range(x.A, sizeof(T) * ext(x.m, x.r, x.lda), "gram A");
+      const int nch = (x.m + x.rows_per_chunk - 1) / x.rows_per_chunk;
+      check_range(x.part, sizeof(double) * (size_t)nch * x.r * x.r, "gram part");
+      check_range(x.G, sizeof(double) * (size_t)x.r * x.r, "gram G");
+    }
+    first[i] = nt;
+    const int nb = (x.r + 31) / 32, nch = (x.m + x.rows_per_chunk - 1) / x.rows_per_chunk;
+    const int tiles = nch * nb * (nb + 1) / 2;
+    for (int j = 0; j < tiles; ++j) tile_task.push_back((int)i);
+    nt += tiles;
+    flops_qr += (double)x.m * x.r * x.r;
+  }
+  const GramTask* dt = upload(t);
+  const int* dtt = upload(tile_task);
+  const int* dft = upload(first);
   const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_applyq<T>(dt, n, s); });
+  submit([=](hipStream_t s) { launch_gram<T>(dt, n, dtt, dft, nt, s); });
+}
+
+void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
+  if (t.empty()) return;
+  for (auto& x : t) {
+    check_range(x.G, sizeof(double) * (size_t)x.r * x.r, "pchol G");
+    check_range(x.L, sizeof(double) * (size_t)x.r * x.r, "pchol L");
+    check_range(x.perm, sizeof(int) * x.r, "pchol perm");
+    check_range(x.d, sizeof(double) * x.r, "pchol d");
+    check_range(x.rank_out, sizeof(int), "pchol rank");
+    flops_qr += (double)x.r * x.r * x.r / 3.0;
+  }
+  const PcholTask* dt = upload(t);
+  const int n = (int)t.size();
+  submit([=](hipStream_t s) { launch_pchol(dt, n, tol, s); });
+}
+
+void Exec::materialize_r(const std::vector<PcholTask>& t) {
+  if (t.empty()) return;
+  for (auto& x : t) check_range(x.R, sizeof(double) * (size_t)x.r1 * x.r, "materialize R");
+  const PcholTask* dt = upload(t);
+  const int n = (int)t.size();
+  submit([=](hipStream_t s) { launch_materialize_r(dt, n, s); });
+}
+
+template <class T> void Exec::wtilde(const std::vector<WtTask>& t) {
+  if (t.empty()) return;
+  for (auto& x : t) {
+    check_range(x.W, sizeof(T) * (size_t)x.r * x.k, "wtilde W");
+    check_range(x.Z, sizeof(double) * ext(x.r1, x.k, x.ldz), "wtilde Z");
+    check_range(x.L, sizeof(double) * (size_t)x.r * x.r, "wtilde L");
+  }
+  const WtTask* dt = upload(t);
+  const int n = (int)t.size();
+  submit([=](hipStream_t s) { launch_wtilde<T>(dt, n, s); });
 }
 
 #define ACR_EXEC_INST(T)                                              \
@@ -374,8 +493,10 @@ template <class T> void Exec::applyq(const std::vector<ApplyQTask>& t) {
   template void Exec::copy<T>(const std::vector<CopyTask>&);          \
   template void Exec::inverse<T>(const std::vector<InvTask>&);        \
   template void Exec::qr<T>(const std::vector<QrTask>&);              \
-  template void Exec::svd<T>(const std::vector<SvdTask>&, double);    \
-  template void Exec::applyq<T>(const std::vector<ApplyQTask>&);
+  template void Exec::svd<T>(std::vector<SvdTask>&, double, int*);   \
+  template void Exec::applyq<T>(const std::vector<ApplyQTask>&);     \
+  template void Exec::gram<T>(const std::vector<GramTask>&);         \
+  template void Exec::wtilde<T>(const std::vector<WtTask>&);
 ACR_EXEC_INST(float)
 ACR_EXEC_INST(double)
 

@@ -111,3 +111,24 @@ def test_gmres_convdiff_fp32_eps1e2_to_1e10():
     A = operator_from_coef(coef)
     assert info["converged"] and float(relres(A, x.cpu().numpy(), f)) <= 1e-10
     fac.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gram_compression_matches_householder(prec, monkeypatch):
+    """Large blocks take the Gram compression path; it must agree with the
+    Householder path (forced with ACR_GRAM=0) to the truncation level."""
+    n, leaf, eps = 32, 32, 1e-3
+    coef = problem("convdiff", n)
+    f = rhs_normal(n ** 3)
+    A = operator_from_coef(coef)
+    monkeypatch.setenv("ACR_GRAM", "1")
+    fg = _gpu(coef, eps=eps, leaf=leaf, precision=prec)
+    xg = _solve(fg, f)
+    monkeypatch.setenv("ACR_GRAM", "0")
+    fh = _gpu(coef, eps=eps, leaf=leaf, precision=prec)
+    xh = _solve(fh, f)
+    assert float(relres(A, xg, f)) <= 5 * eps
+    assert float(relres(A, xh, f)) <= 5 * eps
+    assert np.linalg.norm(xg - xh) <= 20 * eps * np.linalg.norm(xh)
+    fg.free()
+    fh.free()
