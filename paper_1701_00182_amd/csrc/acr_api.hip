@@ -74,6 +74,8 @@ template <class T> struct FactorT : FactorBase {
   std::vector<std::unique_ptr<Plan>> plans;
   double t_factor = 0;
   bool use_graph = true;
+  bool fused_ok = true;   // ACR_FUSED_SOLVE=0 records the GEMM-based sweeps instead
+  static constexpr int kFusedMaxRhs = 4;
 
   void destroy_all() {
     for (auto& p : plans) {
@@ -310,6 +312,184 @@ template <class T> struct FactorT : FactorBase {
     t_factor = now_s() - t0;
   }
 
+  // ---------------------------------------------------------- fused sweeps
+  // Inner products t_b of every off-diagonal block of H (or H^T) against x.
+  void fused_inner(const HMat<T>& H, bool trans, const T* X, int c, Arena& mem, std::vector<InnerTask>& out,
+                   std::vector<const T*>& tptr) {
+    tptr.assign(tr.nblk(), nullptr);
+    if (H.kind != HMat<T>::HODLR) return;
+    const int M = tr.M;
+    for (int d = 0; d < tr.L; ++d)
+      for (int s = 0; s < (2 << d); ++s) {
+        const LR<T>& b = H.blk[Tree::bid(d, s)];
+        if (b.k == 0) continue;
+        T* t = mem.get_n<T>((size_t)b.k * c);
+        tptr[Tree::bid(d, s)] = t;
+        InnerTask it{};
+        if (!trans) {
+          it.V = b.V;
+          it.ldv = tr.sz[d + 1][s ^ 1];
+          it.rows = tr.sz[d + 1][s ^ 1];
+          it.x = X + tr.off[d + 1][s ^ 1];
+        } else {
+          it.V = b.U;
+          it.ldv = tr.sz[d + 1][s];
+          it.rows = tr.sz[d + 1][s];
+          it.x = X + tr.off[d + 1][s];
+        }
+        it.k = b.k;
+        it.ldx = M;
+        it.t = t;
+        it.c = c;
+        out.push_back(it);
+      }
+  }
+
+  // alpha * op(H) x on the rows of leaf l; false when H is absent
+  bool leaf_term(const HMat<T>& H, bool trans, double alpha, const T* X, const std::vector<const T*>& tptr, int l,
+                 LeafTerm& tm) {
+    if (H.absent()) return false;
+    const int L = tr.L, o = tr.off[L][l];
+    tm = LeafTerm{};
+    tm.x = X + o;
+    tm.ldx = tr.M;
+    tm.alpha = alpha;
+    tm.trans = trans ? 1 : 0;
+    if (H.kind == HMat<T>::DIAG) {
+      tm.diag = H.diag + o;
+      return true;
+    }
+    tm.leaf = H.leaf[l];
+    int nd = 0;
+    for (int d = 0; d < L; ++d) {
+      const int s = l >> (L - d - 1);           // ancestor segment at depth d + 1
+      const int b = Tree::bid(d, trans ? (s ^ 1) : s);
+      const LR<T>& blk = H.blk[b];
+      if (blk.k == 0) continue;
+      const int within = o - tr.off[d + 1][s];
+      tm.up[nd] = (trans ? blk.V : blk.U) + within;
+      tm.ldu[nd] = tr.sz[d + 1][s];
+      tm.kd[nd] = blk.k;
+      tm.tp[nd] = tptr[b];
+      ++nd;
+    }
+    tm.nd = nd;
+    return true;
+  }
+
+  void record_fused(Plan* pl, bool trans, T* W, T* Ub, T* Gb, int c) {
+    const int M = tr.M, nleaf = 1 << tr.L;
+    const size_t pane = (size_t)M * c;
+    auto Wp = [&](int plane) { return W + pane * plane; };
+    auto Up = [&](int plane) { return Ub + pane * plane; };
+    auto Gp = [&](int q) { return Gb + pane * (q / 2); };
+    Arena& mem = pl->mem;
+    auto leaf_task = [&](T* y, const T* yin, double beta) {
+      LeafTask lt{};
+      lt.y = y;
+      lt.yin = yin;
+      lt.ldy = M;
+      lt.c = c;
+      lt.beta = beta;
+      return lt;
+    };
+    for (auto& L : lev) {
+      const int m = (int)L.alive.size();
+      // g_e = G_e f_e
+      std::vector<InnerTask> in;
+      std::vector<std::vector<const T*>> tg(m);
+      for (int q = 0; q < m; q += 2) fused_inner(L.G[q], trans, Wp(L.alive[q]), c, mem, in, tg[q]);
+      ex.inner<T>(in);
+      std::vector<LeafTask> lt;
+      for (int q = 0; q < m; q += 2)
+        for (int l = 0; l < nleaf; ++l) {
+          LeafTask t = leaf_task(Gp(q) + tr.off[tr.L][l], nullptr, 0.0);
+          t.n = tr.sz[tr.L][l];
+          if (leaf_term(L.G[q], trans, 1.0, Wp(L.alive[q]), tg[q], l, t.term[0])) t.nterm = 1;
+          lt.push_back(t);
+        }
+      ex.apply_leaf<T>(lt);
+      // f_j -= E_j g_{j-1} + F_j g_{j+1}   (A^T: F_{j-1}^T and E_{j+1}^T)
+      in.clear();
+      std::vector<std::vector<const T*>> tl(m), trr(m);
+      for (int q = 1; q < m; q += 2) {
+        const HMat<T>& left = trans ? L.F[q - 1] : L.E[q];
+        fused_inner(left, trans, Gp(q - 1), c, mem, in, tl[q]);
+        if (q + 1 < m) fused_inner(trans ? L.E[q + 1] : L.F[q], trans, Gp(q + 1), c, mem, in, trr[q]);
+      }
+      ex.inner<T>(in);
+      lt.clear();
+      for (int q = 1; q < m; q += 2)
+        for (int l = 0; l < nleaf; ++l) {
+          T* y = Wp(L.alive[q]) + tr.off[tr.L][l];
+          LeafTask t = leaf_task(y, y, 1.0);
+          t.n = tr.sz[tr.L][l];
+          const HMat<T>& left = trans ? L.F[q - 1] : L.E[q];
+          if (leaf_term(left, trans, -1.0, Gp(q - 1), tl[q], l, t.term[t.nterm])) ++t.nterm;
+          if (q + 1 < m) {
+            const HMat<T>& right = trans ? L.E[q + 1] : L.F[q];
+            if (leaf_term(right, trans, -1.0, Gp(q + 1), trr[q], l, t.term[t.nterm])) ++t.nterm;
+          }
+          if (t.nterm) lt.push_back(t);
+        }
+      ex.apply_leaf<T>(lt);
+    }
+    {
+      std::vector<InnerTask> in;
+      std::vector<const T*> tg;
+      fused_inner(Glast, trans, Wp(last), c, mem, in, tg);
+      ex.inner<T>(in);
+      std::vector<LeafTask> lt;
+      for (int l = 0; l < nleaf; ++l) {
+        LeafTask t = leaf_task(Up(last) + tr.off[tr.L][l], nullptr, 0.0);
+        t.n = tr.sz[tr.L][l];
+        if (leaf_term(Glast, trans, 1.0, Wp(last), tg, l, t.term[0])) t.nterm = 1;
+        lt.push_back(t);
+      }
+      ex.apply_leaf<T>(lt);
+    }
+    for (int li = (int)lev.size() - 1; li >= 0; --li) {
+      auto& L = lev[li];
+      const int m = (int)L.alive.size();
+      // r_e = f_e - E_e u_{e-1} - F_e u_{e+1}   (A^T: F_{e-1}^T, E_{e+1}^T)
+      std::vector<InnerTask> in;
+      std::vector<std::vector<const T*>> tl(m), trr(m), tg(m);
+      for (int q = 0; q < m; q += 2) {
+        if (q - 1 >= 0) fused_inner(trans ? L.F[q - 1] : L.E[q], trans, Up(L.alive[q - 1]), c, mem, in, tl[q]);
+        if (q + 1 < m) fused_inner(trans ? L.E[q + 1] : L.F[q], trans, Up(L.alive[q + 1]), c, mem, in, trr[q]);
+      }
+      ex.inner<T>(in);
+      std::vector<LeafTask> lt;
+      for (int q = 0; q < m; q += 2)
+        for (int l = 0; l < nleaf; ++l) {
+          const int o = tr.off[tr.L][l];
+          LeafTask t = leaf_task(Gp(q) + o, Wp(L.alive[q]) + o, 1.0);
+          t.n = tr.sz[tr.L][l];
+          if (q - 1 >= 0 && leaf_term(trans ? L.F[q - 1] : L.E[q], trans, -1.0, Up(L.alive[q - 1]), tl[q], l,
+                                      t.term[t.nterm]))
+            ++t.nterm;
+          if (q + 1 < m && leaf_term(trans ? L.E[q + 1] : L.F[q], trans, -1.0, Up(L.alive[q + 1]), trr[q], l,
+                                     t.term[t.nterm]))
+            ++t.nterm;
+          lt.push_back(t);
+        }
+      ex.apply_leaf<T>(lt);
+      // u_e = G_e r_e
+      in.clear();
+      for (int q = 0; q < m; q += 2) fused_inner(L.G[q], trans, Gp(q), c, mem, in, tg[q]);
+      ex.inner<T>(in);
+      lt.clear();
+      for (int q = 0; q < m; q += 2)
+        for (int l = 0; l < nleaf; ++l) {
+          LeafTask t = leaf_task(Up(L.alive[q]) + tr.off[tr.L][l], nullptr, 0.0);
+          t.n = tr.sz[tr.L][l];
+          if (leaf_term(L.G[q], trans, 1.0, Gp(q), tg[q], l, t.term[0])) t.nterm = 1;
+          lt.push_back(t);
+        }
+      ex.apply_leaf<T>(lt);
+    }
+  }
+
   // ---------------------------------------------------------- solve plans
   Plan* plan_for(int nrhs, bool trans) {
     for (auto& p : plans)
@@ -327,7 +507,11 @@ template <class T> struct FactorT : FactorBase {
     pl->Ub = Ub;
     ex.rec = &pl->launches;
     ex.rec_arena = &pl->mem;
+    const bool fused = nrhs <= kFusedMaxRhs && tr.L <= kMaxDepth && fused_ok;
     try {
+      if (fused) {
+        record_fused(pl.get(), trans, W, Ub, Gb, nrhs);
+      } else {
       auto Wp = [&](int plane) { return W + pane * plane; };
       auto Up = [&](int plane) { return Ub + pane * plane; };
       auto Gp = [&](int q) { return Gb + pane * (q / 2); };
@@ -374,6 +558,7 @@ template <class T> struct FactorT : FactorBase {
         hodlr_multivec<T>(ex, tr, je, trans, 0, pl->mem);
         hodlr_multivec<T>(ex, tr, jf, trans, 0, pl->mem);
         hodlr_multivec<T>(ex, tr, jg, trans, 0, pl->mem);
+      }
       }
     } catch (...) {
       ex.rec = nullptr;
@@ -493,6 +678,8 @@ FactorBase* make_factor(const acr_options_t* o, const double* coef_in, hipStream
   f->tc.max_rank = o->max_rank;
   const char* ng = std::getenv("ACR_NO_GRAPH");
   f->use_graph = !(ng && ng[0] == '1');
+  const char* fs = std::getenv("ACR_FUSED_SOLVE");
+  f->fused_ok = !(fs && fs[0] == '0');
   const int64_t N = f->grid.N();
   f->coef = f->persist.template get_n<double>(7 * (size_t)N);
   hip_check(hipMemcpyAsync(f->coef, coef_in, 7 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s),

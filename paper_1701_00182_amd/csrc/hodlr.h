@@ -106,6 +106,8 @@ class Exec {
   void pchol(const std::vector<PcholTask>& t, double tol);
   void materialize_r(const std::vector<PcholTask>& t);
   template <class T> void wtilde(const std::vector<WtTask>& t);
+  template <class T> void inner(const std::vector<InnerTask>& t);
+  template <class T> void apply_leaf(const std::vector<LeafTask>& t);
 
   // Host-side bounds check of every task against the live device allocations
   // (enabled with ACR_CHECK=1): a task that would touch memory outside one

@@ -114,6 +114,45 @@ struct WtTask {
   int r, r1, k;
 };
 
+// t (k x c, ld k) = V^T x for one off-diagonal block (solve sweeps)
+struct InnerTask {
+  const void* V;
+  int64_t ldv;
+  int rows, k;
+  const void* x;
+  int64_t ldx;
+  void* t;
+  int c;
+};
+
+constexpr int kMaxDepth = 20;
+// alpha * H x restricted to one leaf's rows: dense leaf (or diagonal) times the
+// leaf part of x, plus the U-slices of the leaf's ancestors times their t
+struct LeafTerm {
+  const void* leaf;
+  const void* diag;
+  const void* x;
+  int64_t ldx;
+  int trans;
+  int nd;
+  double alpha;
+  const void* up[kMaxDepth];
+  const void* tp[kMaxDepth];
+  int64_t ldu[kMaxDepth];
+  int kd[kMaxDepth];
+};
+
+// y_leaf = beta * yin_leaf + sum of up to two terms
+struct LeafTask {
+  void* y;
+  const void* yin;
+  int64_t ldy;
+  int n, c;
+  double beta;
+  int nterm;
+  LeafTerm term[2];
+};
+
 enum : int { FLAG_SINGULAR = 0, FLAG_RANK = 1, FLAG_NONFINITE = 2, FLAG_INVALID = 3, NFLAGS = 8 };
 
 template <class T> void launch_gemm(const GemmTask* d_tasks, const int* d_tile_task,
@@ -132,6 +171,9 @@ template <class T> void launch_gram(const GramTask* d_tasks, int ntasks, const i
 void launch_pchol(const PcholTask* d_tasks, int ntasks, double tol, hipStream_t s);
 void launch_materialize_r(const PcholTask* d_tasks, int ntasks, hipStream_t s);
 template <class T> void launch_wtilde(const WtTask* d_tasks, int ntasks, hipStream_t s);
+template <class T> void launch_inner(const InnerTask* d_tasks, const int* d_wave_task, const int* d_first_wave,
+                                    int nwaves, hipStream_t s);
+template <class T> void launch_apply_leaf(const LeafTask* d_tasks, int ntasks, hipStream_t s);
 constexpr size_t kLdsBudget = 156 * 1024;
 inline size_t lds_bytes_qr(const QrTask& t, size_t w) { return (size_t)t.m * t.r * w; }
 inline size_t lds_bytes_qrcp(const SvdTask& t) { return ((size_t)t.p * t.q + t.q) * 8 + (size_t)t.q * 4; }

@@ -488,6 +488,49 @@ template <class T> void Exec::wtilde(const std::vector<WtTask>& t) {
   submit([=](hipStream_t s) { launch_wtilde<T>(dt, n, s); });
 }
 
+template <class T> void Exec::inner(const std::vector<InnerTask>& t) {
+  if (t.empty()) return;
+  std::vector<int> first(t.size()), wave_task;
+  int nw = 0;
+  for (size_t i = 0; i < t.size(); ++i) {
+    const InnerTask& x = t[i];
+    if (checking) {
+      check_range(x.V, sizeof(T) * ext(x.rows, x.k, x.ldv), "inner V");
+      check_range(x.x, sizeof(T) * ext(x.rows, x.c, x.ldx), "inner x");
+      check_range(x.t, sizeof(T) * (size_t)x.k * x.c, "inner t");
+    }
+    first[i] = nw;
+    for (int j = 0; j < x.k; ++j) wave_task.push_back((int)i);
+    nw += x.k;
+  }
+  const InnerTask* dt = upload(t);
+  const int* dwt = upload(wave_task);
+  const int* dfw = upload(first);
+  submit([=](hipStream_t s) { launch_inner<T>(dt, dwt, dfw, nw, s); });
+}
+
+template <class T> void Exec::apply_leaf(const std::vector<LeafTask>& t) {
+  if (t.empty()) return;
+  if (checking)
+    for (auto& x : t) {
+      check_range(x.y, sizeof(T) * ext(x.n, x.c, x.ldy), "leaf y");
+      if (x.yin) check_range(x.yin, sizeof(T) * ext(x.n, x.c, x.ldy), "leaf yin");
+      for (int q = 0; q < x.nterm; ++q) {
+        const LeafTerm& m = x.term[q];
+        check_range(m.x, sizeof(T) * ext(x.n, x.c, m.ldx), "leaf x");
+        if (m.diag) check_range(m.diag, sizeof(T) * x.n, "leaf diag");
+        else check_range(m.leaf, sizeof(T) * (size_t)x.n * x.n, "leaf matrix");
+        for (int d = 0; d < m.nd; ++d) {
+          check_range(m.up[d], sizeof(T) * ext(x.n, m.kd[d], m.ldu[d]), "leaf U slice");
+          check_range(m.tp[d], sizeof(T) * (size_t)m.kd[d] * x.c, "leaf t");
+        }
+      }
+    }
+  const LeafTask* dt = upload(t);
+  const int n = (int)t.size();
+  submit([=](hipStream_t s) { launch_apply_leaf<T>(dt, n, s); });
+}
+
 #define ACR_EXEC_INST(T)                                              \
   template void Exec::gemm<T>(const std::vector<GemmTask>&);          \
   template void Exec::copy<T>(const std::vector<CopyTask>&);          \
@@ -496,7 +539,9 @@ template <class T> void Exec::wtilde(const std::vector<WtTask>& t) {
   template void Exec::svd<T>(std::vector<SvdTask>&, double, int*);   \
   template void Exec::applyq<T>(const std::vector<ApplyQTask>&);     \
   template void Exec::gram<T>(const std::vector<GramTask>&);         \
-  template void Exec::wtilde<T>(const std::vector<WtTask>&);
+  template void Exec::wtilde<T>(const std::vector<WtTask>&);         \
+  template void Exec::inner<T>(const std::vector<InnerTask>&);       \
+  template void Exec::apply_leaf<T>(const std::vector<LeafTask>&);
 ACR_EXEC_INST(float)
 ACR_EXEC_INST(double)
 
