@@ -1004,4 +1004,10 @@ const char* acr_status_string(acr_status_t s) {
 
 const char* acr_last_error_message(void) { return g_last_error.c_str(); }
 
+void acr_set_kernel_timing(int32_t enable) { acr::timing_enable(enable != 0); }
+
+int32_t acr_get_kernel_times(acr_kernel_time_t* out, int32_t cap) {
+  return acr::timing_report(out, cap < 0 ? 0 : cap);
+}
+
 }  // extern "C"

@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/acr.h"
 #include "kern.h"
 
 namespace acr {
@@ -69,6 +70,21 @@ class Arena {
   size_t ci_ = 0, off_ = 0;
 };
 
+// Algorithmic work of one launch, for the per-kernel timing table: flops and
+// bytes counted from the task shapes (what the method must move or compute),
+// optionally completed from a device counter the kernel fills in.
+struct Work {
+  const char* cls = nullptr;
+  double flops = 0, bytes = 0;
+  unsigned long long* counter = nullptr;
+  double flops_per_count = 0, bytes_per_count = 0;
+};
+
+// Process-wide switch and table of per-kernel-class event timings.
+void timing_enable(bool on);
+bool timing_enabled();
+int timing_report(acr_kernel_time_t* out, int cap);
+
 // Launch executor: uploads task arrays and launches, or records the launches
 // of a solve into a replayable list (captured into a HIP graph by the caller).
 class Exec {
@@ -91,7 +107,9 @@ class Exec {
   template <class Task> const Task* upload(const std::vector<Task>& v) {
     return static_cast<const Task*>(upload_bytes(v.data(), v.size() * sizeof(Task)));
   }
-  void submit(std::function<void(hipStream_t)> f);
+  void submit(std::function<void(hipStream_t)> f, const Work& w = Work{});
+  unsigned long long* counter_slot();   // zeroed device counter for one launch
+  void resolve_timings();               // after the stream is idle
   void read_flags(int out[NFLAGS]);
   void clear_flags();
 
@@ -123,6 +141,11 @@ class Exec {
   long launches = 0;
 
  private:
+  struct Pending { hipEvent_t a, b; Work w; };
+  std::vector<Pending> pending_;
+  std::vector<hipEvent_t> event_pool_;
+  unsigned long long* d_counters_ = nullptr;
+  size_t counter_cursor_ = 0;
   std::vector<void*> oversized_;
   char* h_ring_ = nullptr;
   char* d_ring_ = nullptr;

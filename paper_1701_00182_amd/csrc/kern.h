@@ -69,6 +69,7 @@ struct SvdTask {
   int max_rank;     // 0 = unlimited
   int mode;         // 0: Ru, Rv upper-trapezoidal panels in T; 1: full FP64 factors
   int tc;           // host copy of *t_out (used to size the Jacobi stage)
+  unsigned long long* sweep_ctr;  // optional: += rows * pairs visited (timing table)
 };
 
 // out (m x k) = Q * [Z; 0] with Q the product of the panel's reflectors

@@ -121,6 +121,91 @@ size_t Arena::reserved() const {
   return u;
 }
 
+// ---------------------------------------------------------------- timing table
+namespace {
+std::mutex g_time_mu;
+bool g_timing = false;
+struct TimeAcc { long launches = 0; double ms = 0, flops = 0, bytes = 0; };
+std::map<std::string, TimeAcc>& time_table() {
+  static std::map<std::string, TimeAcc> t;
+  return t;
+}
+constexpr size_t kCounters = 1 << 16;
+}  // namespace
+
+void timing_enable(bool on) {
+  std::lock_guard<std::mutex> lk(g_time_mu);
+  if (on) time_table().clear();   // a new measurement starts; disabling keeps the table
+  g_timing = on;
+}
+bool timing_enabled() { return g_timing; }
+
+int timing_report(acr_kernel_time_t* out, int cap) {
+  std::lock_guard<std::mutex> lk(g_time_mu);
+  int n = 0;
+  for (auto& kv : time_table()) {
+    if (out && n < cap) {
+      acr_kernel_time_t& o = out[n];
+      std::memset(&o, 0, sizeof(o));
+      std::strncpy(o.name, kv.first.c_str(), sizeof(o.name) - 1);
+      o.launches = kv.second.launches;
+      o.total_ms = kv.second.ms;
+      o.flops = kv.second.flops;
+      o.bytes = kv.second.bytes;
+    }
+    ++n;
+  }
+  return n;
+}
+
+unsigned long long* Exec::counter_slot() {
+  if (!d_counters_) {
+    d_counters_ = static_cast<unsigned long long*>(dev_alloc(kCounters * sizeof(unsigned long long)));
+    hip_check(hipMemsetAsync(d_counters_, 0, kCounters * sizeof(unsigned long long), stream), "hipMemsetAsync(ctr)");
+  }
+  if (counter_cursor_ >= kCounters) {
+    sync();
+    hip_check(hipMemsetAsync(d_counters_, 0, kCounters * sizeof(unsigned long long), stream), "hipMemsetAsync(ctr)");
+    counter_cursor_ = 0;
+  }
+  return d_counters_ + counter_cursor_++;
+}
+
+void Exec::resolve_timings() {
+  if (pending_.empty()) return;
+  std::vector<unsigned long long> ctr;
+  if (d_counters_ && counter_cursor_ > 0) {
+    ctr.resize(counter_cursor_);
+    hip_check(hipMemcpy(ctr.data(), d_counters_, ctr.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost),
+              "hipMemcpy(counters)");
+  }
+  std::lock_guard<std::mutex> lk(g_time_mu);
+  for (auto& p : pending_) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p.a, p.b);
+    double fl = p.w.flops, by = p.w.bytes;
+    if (p.w.counter && d_counters_) {
+      const size_t i = p.w.counter - d_counters_;
+      const double c = i < ctr.size() ? (double)ctr[i] : 0.0;
+      fl += c * p.w.flops_per_count;
+      by += c * p.w.bytes_per_count;
+    }
+    TimeAcc& a = time_table()[p.w.cls ? p.w.cls : "other"];
+    a.launches += 1;
+    a.ms += ms;
+    a.flops += fl;
+    a.bytes += by;
+    event_pool_.push_back(p.a);
+    event_pool_.push_back(p.b);
+  }
+  pending_.clear();
+  if (d_counters_ && counter_cursor_ > 0) {
+    hip_check(hipMemsetAsync(d_counters_, 0, counter_cursor_ * sizeof(unsigned long long), stream),
+              "hipMemsetAsync(ctr)");
+    counter_cursor_ = 0;
+  }
+}
+
 // ---------------------------------------------------------------- exec
 namespace {
 std::mutex g_reg_mu;
@@ -176,6 +261,11 @@ void Exec::init(hipStream_t s, const Allocator& a) {
 
 void Exec::destroy() {
   (void)hipDeviceSynchronize();
+  if (!pending_.empty()) resolve_timings();
+  for (hipEvent_t e : event_pool_) (void)hipEventDestroy(e);
+  event_pool_.clear();
+  if (d_counters_) dev_free(d_counters_);
+  d_counters_ = nullptr;
   if (h_ring_) (void)hipHostFree(h_ring_);
   if (h_flags) (void)hipHostFree(h_flags);
   if (d_ring_) dev_free(d_ring_);
@@ -205,7 +295,10 @@ void Exec::dev_free(void* p) {
   (void)hipFree(p);  // hipFree waits for the device to finish with the memory
 }
 
-void Exec::sync() { hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+void Exec::sync() {
+  hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  if (!pending_.empty()) resolve_timings();
+}
 
 const void* Exec::upload_bytes(const void* src, size_t bytes) {
   if (bytes == 0) return nullptr;
@@ -237,14 +330,32 @@ const void* Exec::upload_bytes(const void* src, size_t bytes) {
   return d;
 }
 
-void Exec::submit(std::function<void(hipStream_t)> f) {
+void Exec::submit(std::function<void(hipStream_t)> f, const Work& w) {
   ++launches;
   if (rec) {
     rec->push_back(f);
     return;
   }
+  const bool timed = g_timing && w.cls;
+  Pending p{};
+  if (timed) {
+    for (hipEvent_t* e : {&p.a, &p.b}) {
+      if (!event_pool_.empty()) {
+        *e = event_pool_.back();
+        event_pool_.pop_back();
+      } else {
+        hip_check(hipEventCreate(e), "hipEventCreate");
+      }
+    }
+    hip_check(hipEventRecord(p.a, stream), "hipEventRecord");
+  }
   f(stream);
   hip_check(hipGetLastError(), "kernel launch");
+  if (timed) {
+    hip_check(hipEventRecord(p.b, stream), "hipEventRecord");
+    p.w = w;
+    pending_.push_back(p);
+  }
 }
 
 void Exec::clear_flags() {
@@ -304,10 +415,16 @@ template <class T> void Exec::gemm(const std::vector<GemmTask>& t) {
     flops_gemm += 2.0 * t[i].m * t[i].n * t[i].k;
   }
   if (nt == 0) return;
+  Work w;
+  w.cls = "gemm";
+  for (auto& x : t) {
+    w.flops += 2.0 * x.m * x.n * (double)x.k;
+    w.bytes += sizeof(T) * ((double)x.m * x.k + (double)x.k * x.n + (double)x.m * x.n * (x.beta != 0.0 ? 2 : 1));
+  }
   const GemmTask* dt = upload(t);
   const int* dtt = upload(tile_task);
   const int* dft = upload(first);
-  submit([=](hipStream_t s) { launch_gemm<T>(dt, dtt, dft, nt, s); });
+  submit([=](hipStream_t s) { launch_gemm<T>(dt, dtt, dft, nt, s); }, w);
 }
 
 template <class T> void Exec::copy(const std::vector<CopyTask>& t) {
@@ -321,9 +438,12 @@ template <class T> void Exec::copy(const std::vector<CopyTask>& t) {
       if (x.cs) check_range(x.cs, e * x.n, "copy cs");
       if (x.ldd < x.m || (x.src && x.lds < x.m)) throw Failure(ST_HIP, "bounds check: copy ld");
     }
+  Work w;
+  w.cls = "copy";
+  for (auto& x : t) w.bytes += sizeof(T) * (double)x.m * x.n * ((x.src ? 1 : 0) + 1 + (x.accumulate ? 1 : 0));
   const CopyTask* dt = upload(t);
   const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_copy<T>(dt, n, s); });
+  submit([=](hipStream_t s) { launch_copy<T>(dt, n, s); }, w);
 }
 
 template <class T> void Exec::inverse(const std::vector<InvTask>& t) {
@@ -338,10 +458,16 @@ template <class T> void Exec::inverse(const std::vector<InvTask>& t) {
     mx = std::max(mx, x.s);
     flops_inv += 2.0 * x.s * x.s * (double)x.s;
   }
+  Work w;
+  w.cls = "inverse";
+  for (auto& x : t) {
+    w.flops += 2.0 * x.s * x.s * (double)x.s;
+    w.bytes += 2.0 * sizeof(T) * x.s * (double)x.s;
+  }
   const InvTask* dt = upload(t);
   const int n = (int)t.size();
   int* fl = d_flags;
-  submit([=](hipStream_t s) { launch_inverse<T>(dt, n, mx, fl, s); });
+  submit([=](hipStream_t s) { launch_inverse<T>(dt, n, mx, fl, s); }, w);
 }
 
 template <class T> void Exec::qr(const std::vector<QrTask>& t) {
@@ -358,10 +484,16 @@ template <class T> void Exec::qr(const std::vector<QrTask>& t) {
   }
   bucketed(t, [](const QrTask& x) { return lds_bytes_qr(x, sizeof(T)); },
            [this](const std::vector<QrTask>& b, size_t lds) {
+             Work w;
+             w.cls = lds ? "qr_lds" : "qr";
+             for (auto& x : b) {
+               const double m = x.m, r = x.r, p = std::min(x.m, x.r);
+               w.flops += 4.0 * m * r * p - 2.0 * p * p * (m + r) + 4.0 / 3.0 * p * p * p;
+               w.bytes += 2.0 * sizeof(T) * m * r;
+             }
              const QrTask* dt = upload(b);
              const int n = (int)b.size();
-             if (lds) submit([=](hipStream_t s) { launch_qr_lds<T>(dt, n, lds, s); });
-             else submit([=](hipStream_t s) { launch_qr_lds<T>(dt, n, 0, s); });
+             submit([=](hipStream_t s) { launch_qr_lds<T>(dt, n, lds, s); }, w);
            });
 }
 
@@ -385,9 +517,15 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
   for (auto& x : t) flops_svd += 4.0 * x.p * x.q * (double)std::min(x.p, x.q);
   bucketed(t, [](const SvdTask& x) { return lds_bytes_qrcp(x); },
            [this, delta](const std::vector<SvdTask>& b, size_t lds) {
+             Work w;
+             w.cls = lds ? "qrcp_lds" : "qrcp";
+             for (auto& x : b) {
+               w.flops += 2.0 * x.p * x.q * (double)x.r;  // forming the core (pivoted QR added below)
+               w.bytes += 8.0 * ((double)x.p + x.q) * x.r + 8.0 * x.q * std::min(x.p, x.q);
+             }
              const SvdTask* dt = upload(b);
              const int n = (int)b.size();
-             submit([=](hipStream_t s) { launch_qrcp<T>(dt, n, delta, lds, s); });
+             submit([=](hipStream_t s) { launch_qrcp<T>(dt, n, delta, lds, s); }, w);
            });
   // numerical ranks of the cores size the Jacobi stage
   std::vector<int> tv(t.size());
@@ -398,12 +536,32 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
     t[i].tc = tv[i];
     flops_svd += 6.0 * (double)t[i].q * tv[i] * tv[i] * 4.0;
   }
+  {
+    // the pivoted QR stopped at rank t: add its Householder work to the timing record
+    double qf = 0;
+    for (size_t i = 0; i < t.size(); ++i) {
+      const double p = t[i].p, q = t[i].q, k = tv[i];
+      qf += 4.0 * p * q * k - 2.0 * k * k * (p + q) + 4.0 / 3.0 * k * k * k;
+    }
+    for (auto it = pending_.rbegin(); it != pending_.rend(); ++it)
+      if (it->w.cls && std::strncmp(it->w.cls, "qrcp", 4) == 0) { it->w.flops += qf; break; }
+  }
   int* fl = d_flags;
   bucketed(t, [](const SvdTask& x) { return lds_bytes_jacobi(x); },
            [this, eps, fl](const std::vector<SvdTask>& b, size_t lds) {
-             const SvdTask* dt = upload(b);
-             const int n = (int)b.size();
-             submit([=](hipStream_t s) { launch_jacobi<T>(dt, n, eps, fl, lds, s); });
+             Work w;
+             w.cls = lds ? "jacobi_lds" : "jacobi";
+             unsigned long long* ctr = g_timing ? counter_slot() : nullptr;
+             std::vector<SvdTask> bb = b;
+             for (auto& x : bb) x.sweep_ctr = ctr;
+             // one pair visit reads two columns of `rows` values, 3 dot products and a
+             // rotation of both: 12 * rows flops (the counter sums rows per visit)
+             w.counter = ctr;
+             w.flops_per_count = 12.0;
+             w.bytes_per_count = 32.0;
+             const SvdTask* dt = upload(bb);
+             const int n = (int)bb.size();
+             submit([=](hipStream_t s) { launch_jacobi<T>(dt, n, eps, fl, lds, s); }, w);
            });
 }
 
@@ -420,10 +578,15 @@ template <class T> void Exec::applyq(const std::vector<ApplyQTask>& t) {
   for (auto& x : t) flops_qr += 4.0 * x.m * x.p * (double)x.k;
   bucketed(t, [](const ApplyQTask& x) { return lds_bytes_applyq(x, sizeof(T)); },
            [this](const std::vector<ApplyQTask>& b, size_t lds) {
+             Work w;
+             w.cls = lds ? "applyq_lds" : "applyq";
+             for (auto& x : b) {
+               w.flops += 4.0 * x.m * x.p * (double)x.k;
+               w.bytes += sizeof(T) * ((double)x.m * x.p + (double)x.m * x.k) + 8.0 * x.p * x.k;
+             }
              const ApplyQTask* dt = upload(b);
              const int n = (int)b.size();
-             if (lds) submit([=](hipStream_t s) { launch_applyq_lds<T>(dt, n, lds, s); });
-             else submit([=](hipStream_t s) { launch_applyq_lds<T>(dt, n, 0, s); });
+             submit([=](hipStream_t s) { launch_applyq_lds<T>(dt, n, lds, s); }, w);
            });
 }
 
@@ -446,11 +609,17 @@ template <class T> void Exec::gram(const std::vector<GramTask>& t) {
     nt += tiles;
     flops_qr += (double)x.m * x.r * x.r;
   }
+  Work w;
+  w.cls = "gram";
+  for (auto& x : t) {
+    w.flops += (double)x.m * x.r * (x.r + 1);
+    w.bytes += sizeof(T) * (double)x.m * x.r + 8.0 * x.r * x.r * ((x.m + x.rows_per_chunk - 1) / x.rows_per_chunk);
+  }
   const GramTask* dt = upload(t);
   const int* dtt = upload(tile_task);
   const int* dft = upload(first);
   const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_gram<T>(dt, n, dtt, dft, nt, s); });
+  submit([=](hipStream_t s) { launch_gram<T>(dt, n, dtt, dft, nt, s); }, w);
 }
 
 void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
@@ -463,9 +632,15 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
     check_range(x.rank_out, sizeof(int), "pchol rank");
     flops_qr += (double)x.r * x.r * x.r / 3.0;
   }
+  Work w;
+  w.cls = "pchol";
+  for (auto& x : t) {
+    w.flops += (double)x.r * x.r * x.r / 3.0;
+    w.bytes += 16.0 * x.r * x.r;
+  }
   const PcholTask* dt = upload(t);
   const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_pchol(dt, n, tol, s); });
+  submit([=](hipStream_t s) { launch_pchol(dt, n, tol, s); }, w);
 }
 
 void Exec::materialize_r(const std::vector<PcholTask>& t) {
@@ -483,9 +658,15 @@ template <class T> void Exec::wtilde(const std::vector<WtTask>& t) {
     check_range(x.Z, sizeof(double) * ext(x.r1, x.k, x.ldz), "wtilde Z");
     check_range(x.L, sizeof(double) * (size_t)x.r * x.r, "wtilde L");
   }
+  Work w;
+  w.cls = "wtilde";
+  for (auto& x : t) {
+    w.flops += (double)x.r1 * x.r1 * x.k;
+    w.bytes += 8.0 * x.r1 * x.r1 / 2 + sizeof(T) * (double)x.r * x.k;
+  }
   const WtTask* dt = upload(t);
   const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_wtilde<T>(dt, n, s); });
+  submit([=](hipStream_t s) { launch_wtilde<T>(dt, n, s); }, w);
 }
 
 template <class T> void Exec::inner(const std::vector<InnerTask>& t) {
@@ -503,10 +684,16 @@ template <class T> void Exec::inner(const std::vector<InnerTask>& t) {
     for (int j = 0; j < x.k; ++j) wave_task.push_back((int)i);
     nw += x.k;
   }
+  Work w;
+  w.cls = "solve_inner";
+  for (auto& x : t) {
+    w.flops += 2.0 * x.rows * x.k * (double)x.c;
+    w.bytes += sizeof(T) * ((double)x.rows * x.k + (double)x.rows * x.c + (double)x.k * x.c);
+  }
   const InnerTask* dt = upload(t);
   const int* dwt = upload(wave_task);
   const int* dfw = upload(first);
-  submit([=](hipStream_t s) { launch_inner<T>(dt, dwt, dfw, nw, s); });
+  submit([=](hipStream_t s) { launch_inner<T>(dt, dwt, dfw, nw, s); }, w);
 }
 
 template <class T> void Exec::apply_leaf(const std::vector<LeafTask>& t) {
@@ -526,9 +713,22 @@ template <class T> void Exec::apply_leaf(const std::vector<LeafTask>& t) {
         }
       }
     }
+  Work w;
+  w.cls = "solve_leaf";
+  for (auto& x : t) {
+    double el = (double)x.n * x.c * ((x.yin && x.beta != 0.0) ? 2 : 1);
+    for (int q = 0; q < x.nterm; ++q) {
+      const LeafTerm& m = x.term[q];
+      double mat = m.diag ? x.n : (double)x.n * x.n;
+      for (int d = 0; d < m.nd; ++d) mat += (double)x.n * m.kd[d];
+      w.flops += 2.0 * mat * x.c;
+      el += mat + (double)x.n * x.c;
+    }
+    w.bytes += sizeof(T) * el;
+  }
   const LeafTask* dt = upload(t);
   const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_apply_leaf<T>(dt, n, s); });
+  submit([=](hipStream_t s) { launch_apply_leaf<T>(dt, n, s); }, w);
 }
 
 #define ACR_EXEC_INST(T)                                              \

@@ -201,9 +201,11 @@ __global__ __launch_bounds__(256) void k_jacobi(const SvdTask* __restrict__ task
   const int groups = 256 / G;
   const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   const double tol = fmax(1e-15, 2.3e-16 * (double)rows);
+  int sweeps = 0;
   for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
     if (threadIdx.x == 0) sh_rot = 0;
     __syncthreads();
+    ++sweeps;
     for (int round = 0; round < ne - 1; ++round) {
       for (int pi = gi; pi < npairs; pi += groups) {
         const int pa = pi, pb = ne - 1 - pi;
@@ -318,7 +320,11 @@ __global__ __launch_bounds__(256) void k_jacobi(const SvdTask* __restrict__ task
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *t.rank_out = k;
+  if (threadIdx.x == 0) {
+    *t.rank_out = k;
+    if (t.sweep_ctr)
+      atomicAdd(t.sweep_ctr, (unsigned long long)sweeps * (unsigned long long)(n * (n - 1) / 2) * (unsigned long long)rows);
+  }
 }
 
 template <class K> void allow(K kernel, size_t bytes) {
