@@ -21,7 +21,7 @@
 #include <cstring>
 #include <memory>
 
-#include "../../include/acr.h"
+#include "acr.h"
 #include "hodlr.h"
 #include "stencil.h"
 
@@ -646,7 +646,7 @@ template <class T> struct FactorT : FactorBase {
     st->factor_seconds = t_factor;
     st->flops_gemm = ex.flops_gemm;
     st->flops_qr = ex.flops_qr;
-    st->flops_svd = ex.flops_svd;
+    st->flops_svd = ex.flops_svd + ex.device_svd_flops();
     st->flops_inverse = ex.flops_inv;
     st->launches = ex.launches;
   }

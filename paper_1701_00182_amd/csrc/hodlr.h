@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/acr.h"
+#include "acr.h"
 #include "kern.h"
 
 namespace acr {
@@ -93,6 +93,7 @@ class Exec {
   Allocator al;
   int* d_flags = nullptr;
   int* h_flags = nullptr;
+  unsigned long long* d_svd_flops = nullptr;   // SVD flops counted by the kernels
   std::vector<std::function<void(hipStream_t)>>* rec = nullptr;
   Arena* rec_arena = nullptr;
 
@@ -111,6 +112,7 @@ class Exec {
   unsigned long long* counter_slot();   // zeroed device counter for one launch
   void resolve_timings();               // after the stream is idle
   void read_flags(int out[NFLAGS]);
+  double device_svd_flops();            // synchronizes the stream
   void clear_flags();
 
   template <class T> void gemm(const std::vector<GemmTask>& t);

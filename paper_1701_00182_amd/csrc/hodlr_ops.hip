@@ -85,7 +85,6 @@ void compress_householder(Exec& ex, std::vector<CJob<T>*>& live, double eps, int
     s.mode = 0;
     s.perm = tmp.get_n<int>(q);
     s.t_out = d_tv + i;
-    s.tmp = tmp.get_n<double>(j.r);
     st.push_back(s);
   }
   ex.qr<T>(qt);
@@ -191,7 +190,6 @@ void compress_gram(Exec& ex, std::vector<CJob<T>*>& live, double eps, int max_ra
     s.mode = 1;
     s.perm = tmp.get_n<int>(q);
     s.t_out = d_tv + st.size();
-    s.tmp = tmp.get_n<double>(live[i]->r);
     st.push_back(s);
     idx.push_back(i);
   }

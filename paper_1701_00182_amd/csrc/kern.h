@@ -64,12 +64,12 @@ struct SvdTask {
   double* sig;      // q workspace
   int* perm;        // q workspace (column pivots)
   int* t_out;       // numerical rank found by the pivoted QR
-  double* tmp;      // r workspace
   int* rank_out;
   int max_rank;     // 0 = unlimited
   int mode;         // 0: Ru, Rv upper-trapezoidal panels in T; 1: full FP64 factors
   int tc;           // host copy of *t_out (used to size the Jacobi stage)
   unsigned long long* sweep_ctr;  // optional: += rows * pairs visited (timing table)
+  unsigned long long* flop_ctr;   // += flops counted on the device (sweeps, small cores, left factor)
 };
 
 // out (m x k) = Q * [Z; 0] with Q the product of the panel's reflectors
@@ -166,6 +166,13 @@ template <class T> void launch_qr_lds(const QrTask* d_tasks, int ntasks, size_t 
 template <class T> void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, hipStream_t s);
 template <class T> void launch_jacobi(const SvdTask* d_tasks, int ntasks, double eps, int* d_flags, size_t lds,
                                       hipStream_t s);
+// Small cores (p, q, r <= kSvdWave, triangular panels): the pivoted QR, the
+// sweeps and the right vectors in one wavefront per core, no host round trip
+template <class T> void launch_svd_wave(const SvdTask* d_tasks, int ntasks, double delta, double eps, int* d_flags,
+                                        size_t lds, hipStream_t s);
+// Zu = Ru (Rv^T Zv) for the kept columns, kc columns per workgroup
+template <class T> void launch_core_left(const SvdTask* d_tasks, int ntasks, int kc, int nchunks, size_t lds,
+                                         unsigned long long* ctr, hipStream_t s);
 template <class T> void launch_applyq_lds(const ApplyQTask* d_tasks, int ntasks, size_t lds, hipStream_t s);
 template <class T> void launch_gram(const GramTask* d_tasks, int ntasks, const int* d_tile_task,
                                    const int* d_first_tile, int ntiles, hipStream_t s);
@@ -179,6 +186,14 @@ constexpr size_t kLdsBudget = 156 * 1024;
 inline size_t lds_bytes_qr(const QrTask& t, size_t w) { return (size_t)t.m * t.r * w; }
 inline size_t lds_bytes_qrcp(const SvdTask& t) { return ((size_t)t.p * t.q + t.q) * 8 + (size_t)t.q * 4; }
 inline size_t lds_bytes_jacobi(const SvdTask& t) { return (size_t)t.q * t.tc * 8; }
+constexpr int kSvdWave = 64;
+inline bool svd_wave_ok(const SvdTask& t) {
+  return t.mode == 0 && t.p <= kSvdWave && t.q <= kSvdWave && t.r <= kSvdWave;
+}
+inline size_t lds_bytes_svd_wave(const SvdTask& t) {
+  const size_t lc = t.p | 1, lw = t.q | 1, stage = (size_t)(t.p + t.q) * t.r;
+  return (lc * t.q + (lw * t.q > stage ? lw * t.q : stage) + t.q) * 8 + (size_t)t.q * 4;
+}
 inline size_t lds_bytes_applyq(const ApplyQTask& t, size_t w) { return ((size_t)t.m * t.p + (size_t)t.m * t.k) * w; }
 
 }  // namespace acr

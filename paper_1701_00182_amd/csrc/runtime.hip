@@ -256,7 +256,17 @@ void Exec::init(hipStream_t s, const Allocator& a) {
   d_ring_ = static_cast<char*>(dev_alloc(ring_bytes_));
   d_flags = static_cast<int*>(dev_alloc(NFLAGS * sizeof(int)));
   hip_check(hipHostMalloc((void**)&h_flags, NFLAGS * sizeof(int), hipHostMallocDefault), "hipHostMalloc(flags)");
+  d_svd_flops = static_cast<unsigned long long*>(dev_alloc(sizeof(unsigned long long)));
+  hip_check(hipMemsetAsync(d_svd_flops, 0, sizeof(unsigned long long), stream), "hipMemsetAsync(svd flops)");
   clear_flags();
+}
+
+double Exec::device_svd_flops() {
+  unsigned long long v = 0;
+  if (!d_svd_flops) return 0.0;
+  hip_check(hipMemcpyAsync(&v, d_svd_flops, sizeof(v), hipMemcpyDeviceToHost, stream), "hipMemcpyAsync(svd flops)");
+  hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  return (double)v;
 }
 
 void Exec::destroy() {
@@ -270,6 +280,8 @@ void Exec::destroy() {
   if (h_flags) (void)hipHostFree(h_flags);
   if (d_ring_) dev_free(d_ring_);
   if (d_flags) dev_free(d_flags);
+  if (d_svd_flops) dev_free(d_svd_flops);
+  d_svd_flops = nullptr;
   h_ring_ = nullptr; h_flags = nullptr; d_ring_ = nullptr; d_flags = nullptr;
 }
 
@@ -508,14 +520,70 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
       check_range(x.Y, sizeof(double) * 2 * (size_t)x.q * x.q, "svd Y");
       check_range(x.perm, sizeof(int) * x.q, "svd perm");
       check_range(x.sig, sizeof(double) * x.q, "svd sig");
-      check_range(x.tmp, sizeof(double) * x.r, "svd tmp");
       check_range(x.t_out, sizeof(int), "svd t");
       check_range(x.rank_out, sizeof(int), "svd rank");
       if (x.ldu < x.p || x.ldv < x.q) throw Failure(ST_HIP, "bounds check: svd ld");
+      if (x.r < x.p || x.r < x.q) throw Failure(ST_HIP, "bounds check: svd core shape");
     }
   const double delta = eps > 0.0 ? 0.01 * eps : 0.0;
-  for (auto& x : t) flops_svd += 4.0 * x.p * x.q * (double)std::min(x.p, x.q);
-  bucketed(t, [](const SvdTask& x) { return lds_bytes_qrcp(x); },
+  int* fl = d_flags;
+  for (auto& x : t) x.flop_ctr = d_svd_flops;
+  std::vector<SvdTask> small, big;
+  std::vector<int> big_idx;
+  for (size_t i = 0; i < t.size(); ++i) {
+    if (svd_wave_ok(t[i])) {
+      small.push_back(t[i]);
+    } else {
+      big.push_back(t[i]);
+      big_idx.push_back((int)i);
+    }
+  }
+  // left factors of a batch of finished cores
+  auto left = [this](std::vector<SvdTask>& b) {
+    if (b.empty()) return;
+    int qr = 0, mn = 0;
+    for (auto& x : b) {
+      qr = std::max(qr, x.q + x.r);
+      mn = std::max(mn, std::min(x.p, x.q));
+    }
+    int kc = 32;
+    while (kc > 1 && (size_t)qr * kc * 8 > 64 * 1024) kc >>= 1;
+    const int nchunks = (mn + kc - 1) / kc;
+    const size_t lds = (size_t)qr * kc * 8;
+    if (lds > kLdsBudget) throw Failure(ST_NOT_SUPPORTED, "core too large for the left-factor kernel");
+    Work w;
+    w.cls = "core_left";
+    unsigned long long* ctr = g_timing ? counter_slot() : nullptr;
+    w.counter = ctr;
+    w.flops_per_count = 2.0;
+    for (auto& x : b) w.bytes += (double)sizeof(T) * 0.5 * ((double)x.p + x.q) * x.r;
+    const SvdTask* dt = upload(b);
+    const int n = (int)b.size();
+    submit([=](hipStream_t s) { launch_core_left<T>(dt, n, kc, nchunks, lds, ctr, s); }, w);
+  };
+  if (!small.empty()) {
+    bucketed(small, [](const SvdTask& x) { return lds_bytes_svd_wave(x); },
+             [this, delta, eps, fl](const std::vector<SvdTask>& b, size_t lds) {
+               Work w;
+               w.cls = "svd_wave";
+               unsigned long long* ctr = g_timing ? counter_slot() : nullptr;
+               std::vector<SvdTask> bb = b;
+               for (auto& x : bb) {
+                 x.sweep_ctr = ctr;
+                 w.bytes += (double)sizeof(T) * 0.5 * ((double)x.p + x.q) * x.r;
+               }
+               // the kernel counts the flops of its core product, pivoted QR and sweeps
+               w.counter = ctr;
+               w.flops_per_count = 1.0;
+               const SvdTask* dt = upload(bb);
+               const int n = (int)bb.size();
+               submit([=](hipStream_t s) { launch_svd_wave<T>(dt, n, delta, eps, fl, lds, s); }, w);
+             });
+    left(small);
+  }
+  if (big.empty()) return;
+  for (auto& x : big) flops_svd += 2.0 * x.p * x.q * (double)x.r;
+  bucketed(big, [](const SvdTask& x) { return lds_bytes_qrcp(x); },
            [this, delta](const std::vector<SvdTask>& b, size_t lds) {
              Work w;
              w.cls = lds ? "qrcp_lds" : "qrcp";
@@ -532,22 +600,18 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
   hip_check(hipMemcpyAsync(tv.data(), d_tvals, tv.size() * sizeof(int), hipMemcpyDeviceToHost, stream),
             "hipMemcpyAsync(core ranks)");
   sync();
-  for (size_t i = 0; i < t.size(); ++i) {
-    t[i].tc = tv[i];
-    flops_svd += 6.0 * (double)t[i].q * tv[i] * tv[i] * 4.0;
+  double qf = 0;
+  for (size_t i = 0; i < big.size(); ++i) {
+    const int k = tv[big_idx[i]];
+    big[i].tc = k;
+    const double p = big[i].p, q = big[i].q;
+    qf += 4.0 * p * q * k - 2.0 * (double)k * k * (p + q) + 4.0 / 3.0 * (double)k * k * k;
   }
-  {
-    // the pivoted QR stopped at rank t: add its Householder work to the timing record
-    double qf = 0;
-    for (size_t i = 0; i < t.size(); ++i) {
-      const double p = t[i].p, q = t[i].q, k = tv[i];
-      qf += 4.0 * p * q * k - 2.0 * k * k * (p + q) + 4.0 / 3.0 * k * k * k;
-    }
-    for (auto it = pending_.rbegin(); it != pending_.rend(); ++it)
-      if (it->w.cls && std::strncmp(it->w.cls, "qrcp", 4) == 0) { it->w.flops += qf; break; }
-  }
-  int* fl = d_flags;
-  bucketed(t, [](const SvdTask& x) { return lds_bytes_jacobi(x); },
+  flops_svd += qf;
+  // the pivoted QR stopped at rank t: add its Householder work to the timing record
+  for (auto it = pending_.rbegin(); it != pending_.rend(); ++it)
+    if (it->w.cls && std::strncmp(it->w.cls, "qrcp", 4) == 0) { it->w.flops += qf; break; }
+  bucketed(big, [](const SvdTask& x) { return lds_bytes_jacobi(x); },
            [this, eps, fl](const std::vector<SvdTask>& b, size_t lds) {
              Work w;
              w.cls = lds ? "jacobi_lds" : "jacobi";
@@ -563,6 +627,7 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
              const int n = (int)bb.size();
              submit([=](hipStream_t s) { launch_jacobi<T>(dt, n, eps, fl, lds, s); }, w);
            });
+  left(big);
 }
 
 template <class T> void Exec::applyq(const std::vector<ApplyQTask>& t) {

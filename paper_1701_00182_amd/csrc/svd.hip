@@ -7,7 +7,13 @@
 // up to the dropped tail.  QR with column pivoting both removes the directions
 // far below the truncation level and preconditions the Jacobi iteration, which
 // then converges in a few sweeps.  The right singular vectors are the
-// normalised rotated columns; the left factor is recomputed as C Zv = U Sigma.
+// normalised rotated columns; the left factor is recomputed as C Zv = U Sigma
+// by k_core_left, all kept columns at once.
+//
+// Cores with p, q, r <= 64 (most of them: the blocks near the leaves) run both
+// stages in one wavefront (k_svd_wave): one lane per column of C for the
+// pivoted QR, lane groups per column pair for the sweeps, wavefront shuffles
+// instead of workgroup reductions, and no host round trip between the stages.
 #include <cmath>
 
 #include "kern.h"
@@ -19,6 +25,48 @@ namespace {
 __device__ inline double gsum2(double v, int G) {
   for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
   return v;
+}
+
+__device__ inline double wsum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline double wmax(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// wavefront argmax of (v, i); ties go to the smaller index
+__device__ inline void wargmax(double& v, int& i) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(v, off, 64);
+    const int oi = __shfl_xor(i, off, 64);
+    if (o > v || (o == v && oi < i)) { v = o; i = oi; }
+  }
+}
+
+// workgroup reductions: shuffles inside each wavefront, then one slot per
+// wavefront in LDS read back by every thread (all threads must call them)
+template <int NT> __device__ inline double block_sum(double v, double* red) {
+  v = wsum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < NT / 64; ++w) s += red[w];
+  return s;
+}
+
+template <int NT> __device__ inline void block_argmax(double& v, int& i, double* red, int* redi) {
+  wargmax(v, i);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = v; redi[threadIdx.x >> 6] = i; }
+  __syncthreads();
+  v = red[0];
+  i = redi[0];
+  for (int w = 1; w < NT / 64; ++w)
+    if (red[w] > v || (red[w] == v && redi[w] < i)) { v = red[w]; i = redi[w]; }
 }
 
 __device__ inline int lanes_for(int m) {
@@ -43,8 +91,8 @@ __device__ inline double core_entry(const SvdTask& t, int a, int b) {
   return acc;
 }
 
-template <class T, bool LDS>
-__global__ __launch_bounds__(256) void k_qrcp(const SvdTask* __restrict__ tasks, double delta) {
+template <class T, bool LDS, int NT>
+__global__ __launch_bounds__(NT) void k_qrcp(const SvdTask* __restrict__ tasks, double delta) {
   extern __shared__ double smc[];
   const SvdTask t = tasks[blockIdx.x];
   const int p = t.p, q = t.q;
@@ -56,58 +104,37 @@ __global__ __launch_bounds__(256) void k_qrcp(const SvdTask* __restrict__ tasks,
   double* C = LDS ? smc : t.C;
   double* nrm = LDS ? smc + (int64_t)p * q : t.sig;
   int* perm = LDS ? reinterpret_cast<int*>(nrm + q) : t.perm;
-  __shared__ double rv[256];
-  __shared__ int ri[256];
-  __shared__ double sh_tau, sh_scale, sh_beta;
-  __shared__ int sh_stop;
-  for (int64_t e = threadIdx.x; e < (int64_t)p * q; e += 256) C[e] = core_entry<T>(t, (int)(e % p), (int)(e / p));
+  __shared__ double red[NT / 64];
+  __shared__ int redi[NT / 64];
+  for (int64_t e = threadIdx.x; e < (int64_t)p * q; e += NT) C[e] = core_entry<T>(t, (int)(e % p), (int)(e / p));
   __syncthreads();
-  const int G = lanes_for(p), groups = 256 / G;
+  const int G = lanes_for(p), groups = NT / G;
   const int gi = threadIdx.x / G, gl = threadIdx.x % G;
+  double mx = 0.0;
   for (int c = gi; c < q; c += groups) {
     double s = 0.0;
     for (int i = gl; i < p; i += G) s += C[i + (int64_t)c * p] * C[i + (int64_t)c * p];
     s = gsum2(s, G);
     if (gl == 0) { nrm[c] = s; perm[c] = c; }
+    mx = fmax(mx, s);
   }
-  __syncthreads();
-  double mx = 0.0;
-  for (int c = threadIdx.x; c < q; c += 256) mx = fmax(mx, nrm[c]);
-  rv[threadIdx.x] = mx;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) rv[threadIdx.x] = fmax(rv[threadIdx.x], rv[threadIdx.x + w]);
-    __syncthreads();
+  {
+    int dummy = 0;
+    block_argmax<NT>(mx, dummy, red, redi);
   }
   // dropped tail: Frobenius norm <= sqrt(q) * sqrt(thr2) = delta * (largest column norm)
-  const double thr2 = delta * delta * rv[0] / (double)q;
-  __syncthreads();
+  const double thr2 = delta * delta * mx / (double)q;
   int tcount = 0;
   for (int j = 0; j < mn; ++j) {
     double best = -1.0;
     int bc = j;
-    for (int c = j + threadIdx.x; c < q; c += 256)
+    for (int c = j + threadIdx.x; c < q; c += NT)
       if (nrm[c] > best) { best = nrm[c]; bc = c; }
-    rv[threadIdx.x] = best;
-    ri[threadIdx.x] = bc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) {
-        const double o = rv[threadIdx.x + w];
-        const int oi = ri[threadIdx.x + w];
-        if (o > rv[threadIdx.x] || (o == rv[threadIdx.x] && oi < ri[threadIdx.x])) {
-          rv[threadIdx.x] = o;
-          ri[threadIdx.x] = oi;
-        }
-      }
-      __syncthreads();
-    }
-    const int pc = ri[0];
-    if (threadIdx.x == 0) sh_stop = !(rv[0] > thr2) || !(rv[0] > 0.0);
-    __syncthreads();
-    if (sh_stop) break;
+    block_argmax<NT>(best, bc, red, redi);
+    if (!(best > thr2) || !(best > 0.0)) break;
+    const int pc = bc;
     if (pc != j) {
-      for (int i = threadIdx.x; i < p; i += 256) {
+      for (int i = threadIdx.x; i < p; i += NT) {
         const double a = C[i + (int64_t)j * p];
         C[i + (int64_t)j * p] = C[i + (int64_t)pc * p];
         C[i + (int64_t)pc * p] = a;
@@ -120,37 +147,25 @@ __global__ __launch_bounds__(256) void k_qrcp(const SvdTask* __restrict__ tasks,
         perm[j] = perm[pc];
         perm[pc] = b;
       }
-    }
-    __syncthreads();
-    double* col = C + (int64_t)j * p;
-    double ps = 0.0;
-    for (int i = j + 1 + threadIdx.x; i < p; i += 256) ps += col[i] * col[i];
-    rv[threadIdx.x] = ps;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) rv[threadIdx.x] += rv[threadIdx.x + w];
       __syncthreads();
     }
-    if (threadIdx.x == 0) {
-      const double sigma = rv[0], x0 = col[j];
-      if (sigma == 0.0) {
-        sh_tau = 0.0;
-        sh_scale = 0.0;
-        sh_beta = x0;
-      } else {
-        const double nr = sqrt(x0 * x0 + sigma);
-        const double beta = x0 >= 0.0 ? -nr : nr;
-        sh_tau = (beta - x0) / beta;
-        sh_scale = 1.0 / (x0 - beta);
-        sh_beta = beta;
-      }
+    double* col = C + (int64_t)j * p;
+    double ps = 0.0;
+    for (int i = j + 1 + threadIdx.x; i < p; i += NT) ps += col[i] * col[i];
+    const double sigma = block_sum<NT>(ps, red);
+    const double x0 = col[j];
+    double tj = 0.0, scale = 0.0, beta = x0;
+    if (sigma != 0.0) {
+      const double nr = sqrt(x0 * x0 + sigma);
+      beta = x0 >= 0.0 ? -nr : nr;
+      tj = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
     }
     __syncthreads();
-    const double tj = sh_tau;
     if (tj != 0.0)
-      for (int i = j + 1 + threadIdx.x; i < p; i += 256) col[i] *= sh_scale;
+      for (int i = j + 1 + threadIdx.x; i < p; i += NT) col[i] *= scale;
+    if (threadIdx.x == 0) col[j] = beta;
     __syncthreads();
-    if (threadIdx.x == 0) col[j] = sh_beta;
     for (int c = j + 1 + gi; c < q; c += groups) {
       double* ac = C + (int64_t)c * p;
       if (tj != 0.0) {
@@ -169,16 +184,39 @@ __global__ __launch_bounds__(256) void k_qrcp(const SvdTask* __restrict__ tasks,
   }
   // W^T (q x tcount), rows in the original column order of C
   double* Wt = t.Y;
-  for (int64_t e = threadIdx.x; e < (int64_t)q * tcount; e += 256) {
+  for (int64_t e = threadIdx.x; e < (int64_t)q * tcount; e += NT) {
     const int c = (int)(e % q), a = (int)(e / q);
     Wt[perm[c] + (int64_t)a * q] = c >= a ? C[a + (int64_t)c * p] : 0.0;
   }
   if (threadIdx.x == 0) *t.t_out = tcount;
 }
 
-template <class T, bool LDS>
-__global__ __launch_bounds__(256) void k_jacobi(const SvdTask* __restrict__ tasks, double eps, int* flags) {
+// Jacobi rotation of the column pair (x, y) that zeroes their inner product;
+// false when the pair is already orthogonal to the tolerance.
+__device__ inline bool jacobi_rotation(double al, double be, double ga, double tol, double& cs, double& sn) {
+  if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al * be))) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  double tt;
+  if (fabs(zeta) > 1e150) tt = 0.5 / zeta;
+  else tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  cs = 1.0 / sqrt(1.0 + tt * tt);
+  sn = cs * tt;
+  return true;
+}
+
+// Column indices of pair pi in round `round` of the cyclic tournament over ne
+// (even) columns: column 0 stays, the others shift by one position per round.
+__device__ inline void tournament_pair(int pi, int round, int ne, int& ia, int& ib) {
+  const int pa = pi, pb = ne - 1 - pi;
+  ia = pa == 0 ? 0 : ((pa - 1 + round) % (ne - 1)) + 1;
+  ib = pb == 0 ? 0 : ((pb - 1 + round) % (ne - 1)) + 1;
+  if (ia > ib) { const int tmp = ia; ia = ib; ib = tmp; }
+}
+
+template <class T, bool LDS, int NT>
+__global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks, double eps, int* flags) {
   extern __shared__ double smj[];
+  constexpr int NW = NT / 64;
   const SvdTask t = tasks[blockIdx.x];
   const int rows = t.q;
   const int n = *t.t_out;
@@ -188,17 +226,17 @@ __global__ __launch_bounds__(256) void k_jacobi(const SvdTask* __restrict__ task
   }
   double* A = LDS ? smj : t.Y;
   double* sig = t.sig;
-  __shared__ double red[4];
+  __shared__ double red[NW];
   __shared__ int sh_rot;
   if (LDS)
-    for (int64_t e = threadIdx.x; e < (int64_t)rows * n; e += 256) A[e] = t.Y[e];
+    for (int64_t e = threadIdx.x; e < (int64_t)rows * n; e += NT) A[e] = t.Y[e];
   __syncthreads();
   const int ne = n + (n & 1), npairs = ne / 2;
   int G = 64;
-  while (G > 1 && G * npairs > 256) G >>= 1;
+  while (G > 1 && G * npairs > NT) G >>= 1;
   if (!LDS && G < 16) G = 16;
   while (G > 1 && G > 2 * rows) G >>= 1;
-  const int groups = 256 / G;
+  const int groups = NT / G;
   const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   const double tol = fmax(1e-15, 2.3e-16 * (double)rows);
   int sweeps = 0;
@@ -208,11 +246,9 @@ __global__ __launch_bounds__(256) void k_jacobi(const SvdTask* __restrict__ task
     ++sweeps;
     for (int round = 0; round < ne - 1; ++round) {
       for (int pi = gi; pi < npairs; pi += groups) {
-        const int pa = pi, pb = ne - 1 - pi;
-        int ia = pa == 0 ? 0 : ((pa - 1 + round) % (ne - 1)) + 1;
-        int ib = pb == 0 ? 0 : ((pb - 1 + round) % (ne - 1)) + 1;
-        if (ia >= n || ib >= n) continue;
-        if (ia > ib) { const int tmp = ia; ia = ib; ib = tmp; }
+        int ia, ib;
+        tournament_pair(pi, round, ne, ia, ib);
+        if (ib >= n) continue;
         double* ca = A + (int64_t)ia * rows;
         double* cb = A + (int64_t)ib * rows;
         double al = 0.0, be = 0.0, ga = 0.0;
@@ -225,12 +261,8 @@ __global__ __launch_bounds__(256) void k_jacobi(const SvdTask* __restrict__ task
         al = gsum2(al, G);
         be = gsum2(be, G);
         ga = gsum2(ga, G);
-        if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al * be))) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        double tt;
-        if (fabs(zeta) > 1e150) tt = 0.5 / zeta;
-        else tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        double cs, sn;
+        if (!jacobi_rotation(al, be, ga, tol, cs, sn)) continue;
         for (int i = gl; i < rows; i += G) {
           const double x = ca[i], y = cb[i];
           ca[i] = cs * x - sn * y;
@@ -253,27 +285,29 @@ __global__ __launch_bounds__(256) void k_jacobi(const SvdTask* __restrict__ task
   }
   __syncthreads();
   double mx = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) mx = fmax(mx, sig[i]);
+  for (int i = threadIdx.x; i < n; i += NT) mx = fmax(mx, sig[i]);
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-  __shared__ double sh_mx[4];
-  if ((threadIdx.x & 63) == 0) sh_mx[threadIdx.x >> 6] = mx;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
-  const double smax = fmax(fmax(sh_mx[0], sh_mx[1]), fmax(sh_mx[2], sh_mx[3]));
+  double smax = 0.0;
+  for (int w = 0; w < NW; ++w) smax = fmax(smax, red[w]);
   const double thr = eps > 0.0 ? eps * smax : 0.0;
   int cnt = 0;
-  for (int i = threadIdx.x; i < n; i += 256) cnt += (smax > 0.0 && sig[i] > thr) ? 1 : 0;
+  for (int i = threadIdx.x; i < n; i += NT) cnt += (smax > 0.0 && sig[i] > thr) ? 1 : 0;
   double cs_ = (double)cnt;
   for (int off = 32; off > 0; off >>= 1) cs_ += __shfl_xor(cs_, off, 64);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cs_;
   __syncthreads();
-  int k = (int)(red[0] + red[1] + red[2] + red[3]);
+  double kk = 0.0;
+  for (int w = 0; w < NW; ++w) kk += red[w];
+  int k = (int)kk;
   if (t.max_rank > 0 && k > t.max_rank) {
     if (threadIdx.x == 0) atomicOr(&flags[FLAG_RANK], 1);
     k = t.max_rank;
   }
   // right vectors: normalised rotated columns, ordered by decreasing sigma
-  const int q = t.q, p = t.p;
+  const int q = t.q;
   double* Zv = t.Y + (int64_t)q * q;
   for (int i = gi; i < n; i += groups) {
     const double si = sig[i];
@@ -288,42 +322,274 @@ __global__ __launch_bounds__(256) void k_jacobi(const SvdTask* __restrict__ task
       for (int l = gl; l < rows; l += G) Zv[l + (int64_t)ps * q] = A[l + (int64_t)i * rows] * inv;
     }
   }
-  __syncthreads();
-  // left factor: Zu = C Zv = Ru (Rv^T Zv)
-  double* Zu = t.C + (int64_t)p * q;
-  double* tmp = t.tmp;
-  for (int c = 0; c < k; ++c) {
-    const double* zv = Zv + (int64_t)c * q;
-    for (int l = threadIdx.x; l < t.r; l += 256) {
-      double s = 0.0;
-      if (t.mode == 0) {
-        const T* Rv = static_cast<const T*>(t.Rv);
-        const int bmax = l < q - 1 ? l : q - 1;
-        for (int b = 0; b <= bmax; ++b) s += (double)Rv[b + (int64_t)l * t.ldv] * zv[b];
-      } else {
-        const double* Rv = static_cast<const double*>(t.Rv);
-        for (int b = 0; b < q; ++b) s += Rv[b + (int64_t)l * t.ldv] * zv[b];
-      }
-      tmp[l] = s;
-    }
-    __syncthreads();
-    for (int a = threadIdx.x; a < p; a += 256) {
-      double s = 0.0;
-      if (t.mode == 0) {
-        const T* Ru = static_cast<const T*>(t.Ru);
-        for (int l = a; l < t.r; ++l) s += (double)Ru[a + (int64_t)l * t.ldu] * tmp[l];
-      } else {
-        const double* Ru = static_cast<const double*>(t.Ru);
-        for (int l = 0; l < t.r; ++l) s += Ru[a + (int64_t)l * t.ldu] * tmp[l];
-      }
-      Zu[a + (int64_t)c * p] = s;
-    }
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
     *t.rank_out = k;
-    if (t.sweep_ctr)
-      atomicAdd(t.sweep_ctr, (unsigned long long)sweeps * (unsigned long long)(n * (n - 1) / 2) * (unsigned long long)rows);
+    const unsigned long long visits =
+        (unsigned long long)sweeps * (unsigned long long)(n * (n - 1) / 2) * (unsigned long long)rows;
+    if (t.sweep_ctr) atomicAdd(t.sweep_ctr, visits);
+    if (t.flop_ctr) atomicAdd(t.flop_ctr, 12ull * visits);
+  }
+}
+
+// The whole truncated SVD of one small core (p, q, r <= 64, triangular panels)
+// in one wavefront.  LDS: C (p x q, ld p|1), then a region holding first the
+// staged panels Ru, Rv and later W^T (q x t, ld q|1), then q norms and q pivots.
+template <class T>
+__global__ __launch_bounds__(64) void k_svd_wave(const SvdTask* __restrict__ tasks, double delta, double eps,
+                                                 int* flags) {
+  extern __shared__ double sw[];
+  const SvdTask t = tasks[blockIdx.x];
+  const int p = t.p, q = t.q, r = t.r, lane = threadIdx.x;
+  if (p == 0 || q == 0) {
+    if (lane == 0) { *t.t_out = 0; *t.rank_out = 0; }
+    return;
+  }
+  const int lc = p | 1, lw = q | 1;
+  const int wsz = lw * q > (p + q) * r ? lw * q : (p + q) * r;
+  double* C = sw;
+  double* W = sw + lc * q;
+  double* nrm = W + wsz;
+  int* perm = reinterpret_cast<int*>(nrm + q);
+  // stage the panels (rows a <= l of column l are the nonzero part)
+  {
+    const T* Ru = static_cast<const T*>(t.Ru);
+    const T* Rv = static_cast<const T*>(t.Rv);
+    double* su = W;            // p x r, ld p
+    double* sv = W + p * r;    // q x r, ld q
+    for (int l = 0; l < r; ++l) {
+      if (lane < p) su[lane + l * p] = lane <= l ? (double)Ru[lane + (int64_t)l * t.ldu] : 0.0;
+      if (lane < q) sv[lane + l * q] = lane <= l ? (double)Rv[lane + (int64_t)l * t.ldv] : 0.0;
+    }
+    __syncthreads();
+    // C = Ru Rv^T, lane b forms column b
+    if (lane < q)
+      for (int a = 0; a < p; ++a) {
+        double s = 0.0;
+        for (int l = a > lane ? a : lane; l < r; ++l) s += su[a + l * p] * sv[lane + l * q];
+        C[a + lane * lc] = s;
+      }
+    __syncthreads();
+  }
+  // pivoted QR, lane c owns column c
+  double nc = 0.0;
+  if (lane < q) {
+    for (int a = 0; a < p; ++a) nc += C[a + lane * lc] * C[a + lane * lc];
+    nrm[lane] = nc;
+    perm[lane] = lane;
+  }
+  const double thr2 = delta * delta * wmax(nc) / (double)q;
+  __syncthreads();
+  const int mn = p < q ? p : q;
+  int tcount = 0;
+  for (int j = 0; j < mn; ++j) {
+    double best = (lane >= j && lane < q) ? nrm[lane] : -1.0;
+    int bi = lane;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (o > best || (o == best && oi < bi)) { best = o; bi = oi; }
+    }
+    if (!(best > thr2) || !(best > 0.0)) break;
+    if (bi != j) {
+      if (lane < p) {
+        const double a = C[lane + j * lc];
+        C[lane + j * lc] = C[lane + bi * lc];
+        C[lane + bi * lc] = a;
+      }
+      if (lane == 0) {
+        const double a = nrm[j];
+        nrm[j] = nrm[bi];
+        nrm[bi] = a;
+        const int b = perm[j];
+        perm[j] = perm[bi];
+        perm[bi] = b;
+      }
+    }
+    __syncthreads();
+    // Householder vector of column j below the diagonal
+    const double x = lane < p ? C[lane + j * lc] : 0.0;
+    const double sigma = wsum(lane > j && lane < p ? x * x : 0.0);
+    const double x0 = __shfl(x, j, 64);
+    double tau = 0.0, scale = 0.0, beta = x0;
+    if (sigma != 0.0) {
+      const double nr = sqrt(x0 * x0 + sigma);
+      beta = x0 >= 0.0 ? -nr : nr;
+      tau = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    if (lane < p && lane >= j) C[lane + j * lc] = lane == j ? beta : (tau != 0.0 ? x * scale : x);
+    __syncthreads();
+    if (lane > j && lane < q) {
+      double* ac = C + lane * lc;
+      const double* v = C + j * lc;
+      if (tau != 0.0) {
+        double w = ac[j];
+        for (int i = j + 1; i < p; ++i) w += v[i] * ac[i];
+        w *= tau;
+        ac[j] -= w;
+        for (int i = j + 1; i < p; ++i) ac[i] -= w * v[i];
+      }
+      double s = 0.0;
+      for (int i = j + 1; i < p; ++i) s += ac[i] * ac[i];
+      nrm[lane] = s;
+    }
+    __syncthreads();
+    tcount = j + 1;
+  }
+  const int n = tcount;
+  // W^T (q x n), rows in the original column order of C
+  for (int a = 0; a < n; ++a)
+    if (lane < q) W[perm[lane] + a * lw] = lane >= a ? C[a + lane * lc] : 0.0;
+  __syncthreads();
+  // one-sided Jacobi on the n columns of W^T
+  const int ne = n + (n & 1), npairs = ne / 2;
+  int G = 64;
+  while (G > 1 && G * npairs > 64) G >>= 1;
+  while (G > 1 && G > 2 * q) G >>= 1;
+  const int groups = 64 / G;
+  const int gi = lane / G, gl = lane % G;
+  const double tol = fmax(1e-15, 2.3e-16 * (double)q);
+  int sweeps = 0;
+  for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
+    ++sweeps;
+    int rot = 0;
+    for (int round = 0; round < ne - 1; ++round) {
+      for (int pi = gi; pi < npairs; pi += groups) {
+        int ia, ib;
+        tournament_pair(pi, round, ne, ia, ib);
+        if (ib >= n) continue;
+        double* ca = W + ia * lw;
+        double* cb = W + ib * lw;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = gl; i < q; i += G) {
+          const double xa = ca[i], yb = cb[i];
+          al += xa * xa;
+          be += yb * yb;
+          ga += xa * yb;
+        }
+        al = gsum2(al, G);
+        be = gsum2(be, G);
+        ga = gsum2(ga, G);
+        double cs, sn;
+        if (!jacobi_rotation(al, be, ga, tol, cs, sn)) continue;
+        for (int i = gl; i < q; i += G) {
+          const double xa = ca[i], yb = cb[i];
+          ca[i] = cs * xa - sn * yb;
+          cb[i] = sn * xa + cs * yb;
+        }
+        rot = 1;
+      }
+      __syncthreads();
+    }
+    if (!__any(rot)) break;
+  }
+  // singular values, rank, right vectors ordered by decreasing sigma
+  double si = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double ss = 0.0;
+    for (int l = lane; l < q; l += 64) ss += W[l + i * lw] * W[l + i * lw];
+    ss = wsum(ss);
+    if (lane == i) si = sqrt(ss);
+  }
+  const double smax = wmax(lane < n ? si : 0.0);
+  const double thr = eps > 0.0 ? eps * smax : 0.0;
+  int k = __popcll(__ballot(lane < n && smax > 0.0 && si > thr));
+  if (t.max_rank > 0 && k > t.max_rank) {
+    if (lane == 0) atomicOr(&flags[FLAG_RANK], 1);
+    k = t.max_rank;
+  }
+  if (lane < n) {
+    t.sig[lane] = si;
+    int ps = 0;
+    for (int j = 0; j < n; ++j) {
+      const double sj = __shfl(si, j, 64);
+      ps += (sj > si || (sj == si && j < lane)) ? 1 : 0;
+    }
+    perm[lane] = ps;
+  }
+  __syncthreads();
+  double* Zv = t.Y + (int64_t)q * q;
+  for (int i = 0; i < n; ++i) {
+    const int ps = perm[i];
+    if (ps >= k) continue;
+    const double inv = 1.0 / __shfl(si, i, 64);
+    if (lane < q) Zv[lane + (int64_t)ps * q] = W[lane + i * lw] * inv;
+  }
+  // flops: core product, pivoted QR stopped at n, and 12 per row of each pair visit
+  double macs = 0.0;
+  if (lane < q)
+    for (int a = 0; a < p; ++a) macs += (double)(r - (a > lane ? a : lane));
+  macs = wsum(macs);
+  if (lane == 0) {
+    *t.t_out = n;
+    *t.rank_out = k;
+    const double dp = p, dq = q, dn = n;
+    const double fl = 2.0 * macs + 4.0 * dp * dq * dn - 2.0 * dn * dn * (dp + dq) + 4.0 / 3.0 * dn * dn * dn +
+                      12.0 * (double)sweeps * (dn * (dn - 1.0) / 2.0) * dq;
+    const unsigned long long f = (unsigned long long)(fl > 0.0 ? fl : 0.0);
+    if (t.sweep_ctr) atomicAdd(t.sweep_ctr, f);
+    if (t.flop_ctr) atomicAdd(t.flop_ctr, f);
+  }
+}
+
+// Left factor of the core, Zu = C Zv = Ru (Rv^T Zv), for the k kept columns:
+// one workgroup per (core, chunk of kc columns); the chunk of Zv and of the
+// intermediate Rv^T Zv sit in LDS.
+template <class T>
+__global__ __launch_bounds__(256) void k_core_left(const SvdTask* __restrict__ tasks, int kc,
+                                                   unsigned long long* ctr) {
+  extern __shared__ double sl[];
+  const SvdTask t = tasks[blockIdx.x];
+  const int k = *t.rank_out;
+  const int c0 = blockIdx.y * kc;
+  if (c0 >= k) return;
+  const int nc = k - c0 < kc ? k - c0 : kc;
+  const int p = t.p, q = t.q, r = t.r;
+  const double* Zv = t.Y + (int64_t)q * q + (int64_t)c0 * q;
+  double* Zu = t.C + (int64_t)p * q + (int64_t)c0 * p;
+  double* zs = sl;               // q x nc
+  double* t1 = sl + q * kc;      // r x nc
+  for (int e = threadIdx.x; e < q * nc; e += 256) zs[e] = Zv[e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int l = e % r, c = e / r;
+    const double* z = zs + c * q;
+    double s = 0.0;
+    if (t.mode == 0) {
+      const T* col = static_cast<const T*>(t.Rv) + (int64_t)l * t.ldv;
+      const int bmax = l < q - 1 ? l : q - 1;
+      for (int b = 0; b <= bmax; ++b) s += (double)col[b] * z[b];
+    } else {
+      const double* col = static_cast<const double*>(t.Rv) + (int64_t)l * t.ldv;
+      for (int b = 0; b < q; ++b) s += col[b] * z[b];
+    }
+    t1[e] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < p * nc; e += 256) {
+    const int a = e % p, c = e / p;
+    const double* z = t1 + c * r;
+    double s = 0.0;
+    if (t.mode == 0) {
+      const T* Ru = static_cast<const T*>(t.Ru);
+      for (int l = a; l < r; ++l) s += (double)Ru[a + (int64_t)l * t.ldu] * z[l];
+    } else {
+      const double* Ru = static_cast<const double*>(t.Ru);
+      for (int l = 0; l < r; ++l) s += Ru[a + (int64_t)l * t.ldu] * z[l];
+    }
+    Zu[a + (int64_t)c * p] = s;
+  }
+  if ((ctr || t.flop_ctr) && threadIdx.x == 0) {
+    // multiply-adds of this chunk
+    unsigned long long m = 0;
+    if (t.mode == 0) {
+      for (int l = 0; l < r; ++l) m += (unsigned long long)(l < q - 1 ? l + 1 : q);
+      m += (unsigned long long)p * r - (unsigned long long)p * (p - 1) / 2;
+    } else {
+      m = (unsigned long long)r * (p + q);
+    }
+    if (ctr) atomicAdd(ctr, m * (unsigned long long)nc);
+    if (t.flop_ctr) atomicAdd(t.flop_ctr, 2ull * m * (unsigned long long)nc);
   }
 }
 
@@ -335,31 +601,53 @@ template <class K> void allow(K kernel, size_t bytes) {
 
 }  // namespace
 
+// Cores whose columns do not fit in LDS run with 1024 threads: each launch of
+// them holds few cores, so the wider workgroup shortens the critical path.
 template <class T>
 void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, hipStream_t s) {
   if (ntasks <= 0) return;
   if (lds == 0) {
-    hipLaunchKernelGGL((k_qrcp<T, false>), dim3(ntasks), dim3(256), 0, s, d_tasks, delta);
+    hipLaunchKernelGGL((k_qrcp<T, false, 1024>), dim3(ntasks), dim3(1024), 0, s, d_tasks, delta);
     return;
   }
-  allow(k_qrcp<T, true>, lds);
-  hipLaunchKernelGGL((k_qrcp<T, true>), dim3(ntasks), dim3(256), lds, s, d_tasks, delta);
+  allow(k_qrcp<T, true, 256>, lds);
+  hipLaunchKernelGGL((k_qrcp<T, true, 256>), dim3(ntasks), dim3(256), lds, s, d_tasks, delta);
 }
 
 template <class T>
 void launch_jacobi(const SvdTask* d_tasks, int ntasks, double eps, int* d_flags, size_t lds, hipStream_t s) {
   if (ntasks <= 0) return;
   if (lds == 0) {
-    hipLaunchKernelGGL((k_jacobi<T, false>), dim3(ntasks), dim3(256), 0, s, d_tasks, eps, d_flags);
+    hipLaunchKernelGGL((k_jacobi<T, false, 1024>), dim3(ntasks), dim3(1024), 0, s, d_tasks, eps, d_flags);
     return;
   }
-  allow(k_jacobi<T, true>, lds);
-  hipLaunchKernelGGL((k_jacobi<T, true>), dim3(ntasks), dim3(256), lds, s, d_tasks, eps, d_flags);
+  allow(k_jacobi<T, true, 256>, lds);
+  hipLaunchKernelGGL((k_jacobi<T, true, 256>), dim3(ntasks), dim3(256), lds, s, d_tasks, eps, d_flags);
+}
+
+template <class T>
+void launch_svd_wave(const SvdTask* d_tasks, int ntasks, double delta, double eps, int* d_flags, size_t lds,
+                     hipStream_t s) {
+  if (ntasks <= 0) return;
+  allow(k_svd_wave<T>, lds);
+  hipLaunchKernelGGL(k_svd_wave<T>, dim3(ntasks), dim3(64), lds, s, d_tasks, delta, eps, d_flags);
+}
+
+template <class T>
+void launch_core_left(const SvdTask* d_tasks, int ntasks, int kc, int nchunks, size_t lds, unsigned long long* ctr,
+                      hipStream_t s) {
+  if (ntasks <= 0 || nchunks <= 0) return;
+  allow(k_core_left<T>, lds);
+  hipLaunchKernelGGL(k_core_left<T>, dim3(ntasks, nchunks), dim3(256), lds, s, d_tasks, kc, ctr);
 }
 
 template void launch_qrcp<float>(const SvdTask*, int, double, size_t, hipStream_t);
 template void launch_qrcp<double>(const SvdTask*, int, double, size_t, hipStream_t);
 template void launch_jacobi<float>(const SvdTask*, int, double, int*, size_t, hipStream_t);
 template void launch_jacobi<double>(const SvdTask*, int, double, int*, size_t, hipStream_t);
+template void launch_svd_wave<float>(const SvdTask*, int, double, double, int*, size_t, hipStream_t);
+template void launch_svd_wave<double>(const SvdTask*, int, double, double, int*, size_t, hipStream_t);
+template void launch_core_left<float>(const SvdTask*, int, int, int, size_t, unsigned long long*, hipStream_t);
+template void launch_core_left<double>(const SvdTask*, int, int, int, size_t, unsigned long long*, hipStream_t);
 
 }  // namespace acr
