@@ -27,7 +27,7 @@ METRIC = "factor+solve s & solve DOF/s at n=128; FP32+IR vs FP64 at rel resid 1e
 # MI355X published peaks
 PEAK = {"hbm": 8000.0, "fp64": 78.6, "fp32": 157.3}
 HBM_CLASSES = ("solve_leaf", "solve_inner", "copy")
-FP64_CLASSES = ("jacobi", "jacobi_lds", "qrcp", "qrcp_lds", "pchol", "gram", "wtilde")
+FP64_CLASSES = ("jacobi", "jacobi_lds", "svd_wave", "core_left", "qrcp", "qrcp_lds", "pchol", "gram", "wtilde")
 
 
 def log(msg):

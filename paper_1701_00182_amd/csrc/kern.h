@@ -183,6 +183,7 @@ template <class T> void launch_inner(const InnerTask* d_tasks, const int* d_wave
                                     int nwaves, hipStream_t s);
 template <class T> void launch_apply_leaf(const LeafTask* d_tasks, int ntasks, hipStream_t s);
 constexpr size_t kLdsBudget = 156 * 1024;
+constexpr size_t kSmallLds = 32 * 1024;   // LDS-resident tasks up to this size use 256-thread workgroups
 inline size_t lds_bytes_qr(const QrTask& t, size_t w) { return (size_t)t.m * t.r * w; }
 inline size_t lds_bytes_qrcp(const SvdTask& t) { return ((size_t)t.p * t.q + t.q) * 8 + (size_t)t.q * 4; }
 inline size_t lds_bytes_jacobi(const SvdTask& t) { return (size_t)t.q * t.tc * 8; }

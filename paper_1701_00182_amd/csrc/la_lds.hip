@@ -2,7 +2,7 @@
 // LDS-resident instantiation for panels that fit the 160 KB local data share of
 // a CDNA4 compute unit and a global-memory one otherwise.  Trailing columns are
 // processed concurrently by groups of G lanes that reduce with intra-group
-// shuffles, so one workgroup keeps its 256 lanes busy even on 64 x 64 panels.
+// shuffles, so one workgroup keeps its 1024 lanes busy even on 64 x 64 panels.
 #include <cmath>
 
 #include "kern.h"
@@ -16,14 +16,14 @@ __device__ inline double gsum(double v, int G) {
   return v;
 }
 
-__device__ inline double block_sum4(double v, double* red) {
+template <int NT> __device__ inline double block_sum(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) red[wave] = v;
   __syncthreads();
-  const double s = red[0] + red[1] + red[2] + red[3];
-  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < NT / 64; ++w) s += red[w];
   return s;
 }
 
@@ -34,8 +34,8 @@ __device__ inline int lanes_for_rows(int m) {
   return G;
 }
 
-template <class T, bool LDS>
-__global__ __launch_bounds__(256) void k_qr_lds(const QrTask* __restrict__ tasks) {
+template <class T, bool LDS, int NT>
+__global__ __launch_bounds__(NT) void k_qr_lds(const QrTask* __restrict__ tasks) {
   extern __shared__ double smq[];
   const QrTask t = tasks[blockIdx.x];
   T* A = static_cast<T*>(t.A);
@@ -44,21 +44,21 @@ __global__ __launch_bounds__(256) void k_qr_lds(const QrTask* __restrict__ tasks
   T* a = LDS ? reinterpret_cast<T*>(smq) : A;
   const int64_t la = LDS ? m : t.lda;
   if (LDS)
-    for (int e = threadIdx.x; e < m * r; e += 256) a[e] = A[(e % m) + (int64_t)(e / m) * t.lda];
-  __shared__ double red[4];
+    for (int e = threadIdx.x; e < m * r; e += NT) a[e] = A[(e % m) + (int64_t)(e / m) * t.lda];
+  __shared__ double red[NT / 64];
   __shared__ double sh_tau, sh_scale, sh_beta;
-  const int G = lanes_for_rows(m), groups = 256 / G;
+  const int G = lanes_for_rows(m), groups = NT / G;
   const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   const int nref = m < r ? m : r;
   __syncthreads();
   for (int j = 0; j < nref; ++j) {
     T* col = a + j * la;
     double ps = 0.0;
-    for (int i = j + 1 + threadIdx.x; i < m; i += 256) {
+    for (int i = j + 1 + threadIdx.x; i < m; i += NT) {
       const double v = (double)col[i];
       ps += v * v;
     }
-    const double sigma = block_sum4(ps, red);
+    const double sigma = block_sum<NT>(ps, red);
     if (threadIdx.x == 0) {
       const double x0 = (double)col[j];
       if (sigma == 0.0) {
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_qr_lds(const QrTask* __restrict__ tasks
     const double tj = sh_tau;
     if (tj != 0.0) {
       const T sc = T(sh_scale);
-      for (int i = j + 1 + threadIdx.x; i < m; i += 256) col[i] *= sc;
+      for (int i = j + 1 + threadIdx.x; i < m; i += NT) col[i] *= sc;
     }
     __syncthreads();
     if (threadIdx.x == 0) col[j] = T(sh_beta);
@@ -94,11 +94,11 @@ __global__ __launch_bounds__(256) void k_qr_lds(const QrTask* __restrict__ tasks
     __syncthreads();
   }
   if (LDS)
-    for (int e = threadIdx.x; e < m * r; e += 256) A[(e % m) + (int64_t)(e / m) * t.lda] = a[e];
+    for (int e = threadIdx.x; e < m * r; e += NT) A[(e % m) + (int64_t)(e / m) * t.lda] = a[e];
 }
 
-template <class T, bool LDS>
-__global__ __launch_bounds__(256) void k_applyq_lds(const ApplyQTask* __restrict__ tasks) {
+template <class T, bool LDS, int NT>
+__global__ __launch_bounds__(NT) void k_applyq_lds(const ApplyQTask* __restrict__ tasks) {
   extern __shared__ double sma[];
   const ApplyQTask t = tasks[blockIdx.x];
   const int m = t.m, p = t.p, k = t.k;
@@ -111,13 +111,13 @@ __global__ __launch_bounds__(256) void k_applyq_lds(const ApplyQTask* __restrict
   T* o = LDS ? reinterpret_cast<T*>(sma) + m * p : out;
   const int64_t lo = LDS ? m : t.ldo;
   if (LDS)
-    for (int e = threadIdx.x; e < m * p; e += 256)
+    for (int e = threadIdx.x; e < m * p; e += NT)
       reinterpret_cast<T*>(sma)[e] = Aq[(e % m) + (int64_t)(e / m) * t.lda];
-  for (int e = threadIdx.x; e < m * k; e += 256) {
+  for (int e = threadIdx.x; e < m * k; e += NT) {
     const int i = e % m, c = e / m;
     o[i + c * lo] = i < p ? T(t.Z[i + (int64_t)c * t.ldz]) : T(0);
   }
-  const int G = lanes_for_rows(m), groups = 256 / G;
+  const int G = lanes_for_rows(m), groups = NT / G;
   const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   __syncthreads();
   for (int j = p - 1; j >= 0; --j) {
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_applyq_lds(const ApplyQTask* __restrict
     __syncthreads();
   }
   if (LDS)
-    for (int e = threadIdx.x; e < m * k; e += 256) out[(e % m) + (int64_t)(e / m) * t.ldo] = o[e];
+    for (int e = threadIdx.x; e < m * k; e += NT) out[(e % m) + (int64_t)(e / m) * t.ldo] = o[e];
 }
 
 template <class K> void allow_lds(K kernel, size_t bytes) {
@@ -145,25 +145,37 @@ template <class K> void allow_lds(K kernel, size_t bytes) {
 
 }  // namespace
 
-// lds == 0 selects the global-memory instantiation (same algorithm)
+// lds == 0 selects the global-memory instantiation (same algorithm).  Panels
+// of up to kSmallLds bytes run with 256 threads (several workgroups share a
+// compute unit), larger ones with 1024.
 template <class T> void launch_qr_lds(const QrTask* d_tasks, int ntasks, size_t lds, hipStream_t s) {
   if (ntasks <= 0) return;
   if (lds == 0) {
-    hipLaunchKernelGGL((k_qr_lds<T, false>), dim3(ntasks), dim3(256), 0, s, d_tasks);
+    hipLaunchKernelGGL((k_qr_lds<T, false, 1024>), dim3(ntasks), dim3(1024), 0, s, d_tasks);
     return;
   }
-  allow_lds(k_qr_lds<T, true>, lds);
-  hipLaunchKernelGGL((k_qr_lds<T, true>), dim3(ntasks), dim3(256), lds, s, d_tasks);
+  if (lds <= kSmallLds) {
+    allow_lds(k_qr_lds<T, true, 256>, lds);
+    hipLaunchKernelGGL((k_qr_lds<T, true, 256>), dim3(ntasks), dim3(256), lds, s, d_tasks);
+    return;
+  }
+  allow_lds(k_qr_lds<T, true, 1024>, lds);
+  hipLaunchKernelGGL((k_qr_lds<T, true, 1024>), dim3(ntasks), dim3(1024), lds, s, d_tasks);
 }
 
 template <class T> void launch_applyq_lds(const ApplyQTask* d_tasks, int ntasks, size_t lds, hipStream_t s) {
   if (ntasks <= 0) return;
   if (lds == 0) {
-    hipLaunchKernelGGL((k_applyq_lds<T, false>), dim3(ntasks), dim3(256), 0, s, d_tasks);
+    hipLaunchKernelGGL((k_applyq_lds<T, false, 1024>), dim3(ntasks), dim3(1024), 0, s, d_tasks);
     return;
   }
-  allow_lds(k_applyq_lds<T, true>, lds);
-  hipLaunchKernelGGL((k_applyq_lds<T, true>), dim3(ntasks), dim3(256), lds, s, d_tasks);
+  if (lds <= kSmallLds) {
+    allow_lds(k_applyq_lds<T, true, 256>, lds);
+    hipLaunchKernelGGL((k_applyq_lds<T, true, 256>), dim3(ntasks), dim3(256), lds, s, d_tasks);
+    return;
+  }
+  allow_lds(k_applyq_lds<T, true, 1024>, lds);
+  hipLaunchKernelGGL((k_applyq_lds<T, true, 1024>), dim3(ntasks), dim3(1024), lds, s, d_tasks);
 }
 
 #define ACR_LDS_INST(T)                                                                           \

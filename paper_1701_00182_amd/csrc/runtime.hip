@@ -1,5 +1,6 @@
 // Cluster tree, device arenas and the launch executor.
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -608,6 +609,16 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
     qf += 4.0 * p * q * k - 2.0 * (double)k * k * (p + q) + 4.0 / 3.0 * (double)k * k * k;
   }
   flops_svd += qf;
+  if (trace) {
+    int mq = 0, mt = 0, nl = 0;
+    for (auto& x : big) {
+      mq = std::max(mq, x.q);
+      mt = std::max(mt, x.tc);
+      nl += lds_bytes_jacobi(x) <= kLdsBudget;
+    }
+    std::fprintf(stderr, "[acr] svd %s small=%zu big=%zu (lds %d) max_q=%d max_t=%d\n", trace_tag, small.size(),
+                 big.size(), nl, mq, mt);
+  }
   // the pivoted QR stopped at rank t: add its Householder work to the timing record
   for (auto it = pending_.rbegin(); it != pending_.rend(); ++it)
     if (it->w.cls && std::strncmp(it->w.cls, "qrcp", 4) == 0) { it->w.flops += qf; break; }

@@ -213,6 +213,61 @@ __device__ inline void tournament_pair(int pi, int round, int ne, int& ia, int& 
   if (ia > ib) { const int tmp = ia; ia = ib; ib = tmp; }
 }
 
+// One Jacobi step on the column pair (ca, cb) of length rows, handled by the G
+// lanes of a group (gl = lane in group): the three inner products, the rotation
+// and its application.  Columns of up to G * kJR rows stay in registers between
+// the products and the update.  Returns whether a rotation was applied.
+constexpr int kJR = 12;
+__device__ inline bool jacobi_pair(double* ca, double* cb, int rows, int G, int gl, double tol) {
+  double al = 0.0, be = 0.0, ga = 0.0;
+  if (rows <= G * kJR) {
+    double xr[kJR], yr[kJR];
+#pragma unroll
+    for (int u = 0; u < kJR; ++u) {
+      const int i = gl + u * G;
+      xr[u] = i < rows ? ca[i] : 0.0;
+      yr[u] = i < rows ? cb[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kJR; ++u) {
+      al += xr[u] * xr[u];
+      be += yr[u] * yr[u];
+      ga += xr[u] * yr[u];
+    }
+    al = gsum2(al, G);
+    be = gsum2(be, G);
+    ga = gsum2(ga, G);
+    double cs, sn;
+    if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
+#pragma unroll
+    for (int u = 0; u < kJR; ++u) {
+      const int i = gl + u * G;
+      if (i < rows) {
+        ca[i] = cs * xr[u] - sn * yr[u];
+        cb[i] = sn * xr[u] + cs * yr[u];
+      }
+    }
+    return true;
+  }
+  for (int i = gl; i < rows; i += G) {
+    const double x = ca[i], y = cb[i];
+    al += x * x;
+    be += y * y;
+    ga += x * y;
+  }
+  al = gsum2(al, G);
+  be = gsum2(be, G);
+  ga = gsum2(ga, G);
+  double cs, sn;
+  if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
+  for (int i = gl; i < rows; i += G) {
+    const double x = ca[i], y = cb[i];
+    ca[i] = cs * x - sn * y;
+    cb[i] = sn * x + cs * y;
+  }
+  return true;
+}
+
 template <class T, bool LDS, int NT>
 __global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks, double eps, int* flags) {
   extern __shared__ double smj[];
@@ -249,26 +304,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks
         int ia, ib;
         tournament_pair(pi, round, ne, ia, ib);
         if (ib >= n) continue;
-        double* ca = A + (int64_t)ia * rows;
-        double* cb = A + (int64_t)ib * rows;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = gl; i < rows; i += G) {
-          const double x = ca[i], y = cb[i];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
-        }
-        al = gsum2(al, G);
-        be = gsum2(be, G);
-        ga = gsum2(ga, G);
-        double cs, sn;
-        if (!jacobi_rotation(al, be, ga, tol, cs, sn)) continue;
-        for (int i = gl; i < rows; i += G) {
-          const double x = ca[i], y = cb[i];
-          ca[i] = cs * x - sn * y;
-          cb[i] = sn * x + cs * y;
-        }
-        if (gl == 0) sh_rot = 1;
+        if (jacobi_pair(A + (int64_t)ia * rows, A + (int64_t)ib * rows, rows, G, gl, tol) && gl == 0) sh_rot = 1;
       }
       __syncthreads();
     }
@@ -458,26 +494,7 @@ __global__ __launch_bounds__(64) void k_svd_wave(const SvdTask* __restrict__ tas
         int ia, ib;
         tournament_pair(pi, round, ne, ia, ib);
         if (ib >= n) continue;
-        double* ca = W + ia * lw;
-        double* cb = W + ib * lw;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = gl; i < q; i += G) {
-          const double xa = ca[i], yb = cb[i];
-          al += xa * xa;
-          be += yb * yb;
-          ga += xa * yb;
-        }
-        al = gsum2(al, G);
-        be = gsum2(be, G);
-        ga = gsum2(ga, G);
-        double cs, sn;
-        if (!jacobi_rotation(al, be, ga, tol, cs, sn)) continue;
-        for (int i = gl; i < q; i += G) {
-          const double xa = ca[i], yb = cb[i];
-          ca[i] = cs * xa - sn * yb;
-          cb[i] = sn * xa + cs * yb;
-        }
-        rot = 1;
+        if (jacobi_pair(W + ia * lw, W + ib * lw, q, G, gl, tol)) rot = 1;
       }
       __syncthreads();
     }
@@ -601,8 +618,10 @@ template <class K> void allow(K kernel, size_t bytes) {
 
 }  // namespace
 
-// Cores whose columns do not fit in LDS run with 1024 threads: each launch of
-// them holds few cores, so the wider workgroup shortens the critical path.
+// Cores beyond the one-wavefront size whose working set exceeds kSmallLds run
+// with 1024 threads: their LDS footprint already limits them to one or two
+// workgroups per compute unit, and the extra wavefronts hide LDS latency and
+// shorten the critical path of each core.
 template <class T>
 void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, hipStream_t s) {
   if (ntasks <= 0) return;
@@ -610,8 +629,13 @@ void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, h
     hipLaunchKernelGGL((k_qrcp<T, false, 1024>), dim3(ntasks), dim3(1024), 0, s, d_tasks, delta);
     return;
   }
-  allow(k_qrcp<T, true, 256>, lds);
-  hipLaunchKernelGGL((k_qrcp<T, true, 256>), dim3(ntasks), dim3(256), lds, s, d_tasks, delta);
+  if (lds <= kSmallLds) {
+    allow(k_qrcp<T, true, 256>, lds);
+    hipLaunchKernelGGL((k_qrcp<T, true, 256>), dim3(ntasks), dim3(256), lds, s, d_tasks, delta);
+    return;
+  }
+  allow(k_qrcp<T, true, 1024>, lds);
+  hipLaunchKernelGGL((k_qrcp<T, true, 1024>), dim3(ntasks), dim3(1024), lds, s, d_tasks, delta);
 }
 
 template <class T>
@@ -621,8 +645,13 @@ void launch_jacobi(const SvdTask* d_tasks, int ntasks, double eps, int* d_flags,
     hipLaunchKernelGGL((k_jacobi<T, false, 1024>), dim3(ntasks), dim3(1024), 0, s, d_tasks, eps, d_flags);
     return;
   }
-  allow(k_jacobi<T, true, 256>, lds);
-  hipLaunchKernelGGL((k_jacobi<T, true, 256>), dim3(ntasks), dim3(256), lds, s, d_tasks, eps, d_flags);
+  if (lds <= kSmallLds) {
+    allow(k_jacobi<T, true, 256>, lds);
+    hipLaunchKernelGGL((k_jacobi<T, true, 256>), dim3(ntasks), dim3(256), lds, s, d_tasks, eps, d_flags);
+    return;
+  }
+  allow(k_jacobi<T, true, 1024>, lds);
+  hipLaunchKernelGGL((k_jacobi<T, true, 1024>), dim3(ntasks), dim3(1024), lds, s, d_tasks, eps, d_flags);
 }
 
 template <class T>
