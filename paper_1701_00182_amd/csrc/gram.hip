@@ -80,90 +80,91 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const GramTask* __restrict_
   }
 }
 
+__device__ inline double gsumw(double v, int G) {
+  for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+
 // Pivoted Cholesky of an r x r FP64 Gram matrix, stopped when the largest
-// remaining diagonal falls to tol * (largest initial diagonal).
-__global__ __launch_bounds__(256) void k_pchol(const PcholTask* __restrict__ tasks, double tol) {
+// remaining diagonal falls to tol * (largest initial diagonal).  Left-looking:
+// column j of L is formed from the rows of the previous columns, G lanes per
+// row (G chosen so that the remaining rows fill the workgroup).  Only the
+// entries on and below the diagonal of the first `rank` columns are written.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pchol(const PcholTask* __restrict__ tasks, double tol) {
   const PcholTask t = tasks[blockIdx.x];
   const int r = t.r;
   const double* G = t.G;
   double* L = t.L;
   int* perm = t.perm;
   double* d = t.d;
-  __shared__ double rv[256];
-  __shared__ int ri[256];
-  __shared__ double sh_ljj;
-  __shared__ int sh_stop;
-  for (int64_t e = threadIdx.x; e < (int64_t)r * r; e += 256) L[e] = 0.0;
-  for (int i = threadIdx.x; i < r; i += 256) {
+  __shared__ double red[NT / 64];
+  __shared__ int redi[NT / 64];
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < r; i += NT) {
     perm[i] = i;
     d[i] = G[i + (int64_t)i * r];
+    mx = fmax(mx, d[i]);
   }
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
-  double mx = 0.0;
-  for (int i = threadIdx.x; i < r; i += 256) mx = fmax(mx, d[i]);
-  rv[threadIdx.x] = mx;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) rv[threadIdx.x] = fmax(rv[threadIdx.x], rv[threadIdx.x + w]);
-    __syncthreads();
-  }
-  const double thr = tol * rv[0];
-  const bool zero = !(rv[0] > 0.0);
-  __syncthreads();
+  mx = 0.0;
+  for (int w = 0; w < NT / 64; ++w) mx = fmax(mx, red[w]);
+  const double thr = tol * mx;
+  const bool zero = !(mx > 0.0);
   int rank = 0;
   for (int j = 0; j < r && !zero; ++j) {
     double best = -1.0;
     int bp = j;
-    for (int i = j + threadIdx.x; i < r; i += 256) {
+    for (int i = j + threadIdx.x; i < r; i += NT) {
       const double v = d[perm[i]];
       if (v > best) { best = v; bp = i; }
     }
-    rv[threadIdx.x] = best;
-    ri[threadIdx.x] = bp;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) {
-        const double o = rv[threadIdx.x + w];
-        const int oi = ri[threadIdx.x + w];
-        if (o > rv[threadIdx.x] || (o == rv[threadIdx.x] && oi < ri[threadIdx.x])) {
-          rv[threadIdx.x] = o;
-          ri[threadIdx.x] = oi;
-        }
-      }
-      __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bp, off, 64);
+      if (o > best || (o == best && oi < bp)) { best = o; bp = oi; }
     }
-    const int p = ri[0];
-    if (threadIdx.x == 0) {
-      sh_stop = !(rv[0] > thr);
-      if (!sh_stop) {
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = best; redi[threadIdx.x >> 6] = bp; }
+    __syncthreads();
+    best = red[0];
+    bp = redi[0];
+    for (int w = 1; w < NT / 64; ++w)
+      if (red[w] > best || (red[w] == best && redi[w] < bp)) { best = red[w]; bp = redi[w]; }
+    if (!(best > thr)) break;
+    const int p = bp;
+    if (p != j) {
+      for (int l = threadIdx.x; l < j; l += NT) {
+        const double a = L[j + (int64_t)l * r];
+        L[j + (int64_t)l * r] = L[p + (int64_t)l * r];
+        L[p + (int64_t)l * r] = a;
+      }
+      if (threadIdx.x == 0) {
         const int tmp = perm[j];
         perm[j] = perm[p];
         perm[p] = tmp;
       }
     }
     __syncthreads();
-    if (sh_stop) break;
-    if (p != j)
-      for (int l = threadIdx.x; l < j; l += 256) {
-        const double a = L[j + (int64_t)l * r];
-        L[j + (int64_t)l * r] = L[p + (int64_t)l * r];
-        L[p + (int64_t)l * r] = a;
-      }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      sh_ljj = sqrt(d[perm[j]]);
-      L[j + (int64_t)j * r] = sh_ljj;
-    }
-    __syncthreads();
-    const double ljj = sh_ljj;
     const int pj = perm[j];
-    for (int i = j + 1 + threadIdx.x; i < r; i += 256) {
-      const int pi = perm[i];
-      double s = G[pi + (int64_t)pj * r];
-      for (int l = 0; l < j; ++l) s -= L[i + (int64_t)l * r] * L[j + (int64_t)l * r];
-      const double lij = s / ljj;
-      L[i + (int64_t)j * r] = lij;
-      d[pi] -= lij * lij;
+    const double ljj = sqrt(d[pj]);
+    if (threadIdx.x == 0) L[j + (int64_t)j * r] = ljj;
+    const int rem = r - j - 1;
+    int Gl = 16;
+    while (Gl > 1 && Gl * rem > NT) Gl >>= 1;
+    const int groups = NT / Gl, gi = threadIdx.x / Gl, gl = threadIdx.x % Gl;
+    for (int i = j + 1 + gi; i < r; i += groups) {
+      double s = 0.0;
+      for (int l = gl; l < j; l += Gl) s += L[i + (int64_t)l * r] * L[j + (int64_t)l * r];
+      s = gsumw(s, Gl);
+      if (gl == 0) {
+        const int pi = perm[i];
+        const double lij = (G[pi + (int64_t)pj * r] - s) / ljj;
+        L[i + (int64_t)j * r] = lij;
+        d[pi] -= lij * lij;
+      }
     }
     __syncthreads();
     rank = j + 1;
@@ -181,22 +182,51 @@ __global__ __launch_bounds__(256) void k_materialize_r(const PcholTask* __restri
   }
 }
 
-// W = P1 L11^{-T} Z scattered into r x k (precision T): back-substitution per column.
+// W = P1 L11^{-T} Z scattered into r x k (precision T): blocked back
+// substitution, one workgroup per (task, chunk of kc right-hand sides) with
+// the chunk of Z in LDS.  Each 32-row diagonal block is solved by the first
+// wavefront (one lane per right-hand side), then subtracted from the rows
+// above it by the whole workgroup.
 template <class T>
-__global__ __launch_bounds__(256) void k_wtilde(const WtTask* __restrict__ tasks) {
+__global__ __launch_bounds__(256) void k_wtilde(const WtTask* __restrict__ tasks, int kc) {
+  extern __shared__ double zs[];
   const WtTask t = tasks[blockIdx.x];
   const int r = t.r, r1 = t.r1, k = t.k;
-  T* W = static_cast<T*>(t.W);
-  for (int64_t e = threadIdx.x; e < (int64_t)r * k; e += 256) W[e] = T(0);
+  const int c0 = blockIdx.y * kc;
+  if (c0 >= k) return;
+  const int nc = k - c0 < kc ? k - c0 : kc;
+  const double* L = t.L;
+  for (int e = threadIdx.x; e < r1 * nc; e += 256) {
+    const int a = e % r1, c = e / r1;
+    zs[e] = t.Z[a + (int64_t)(c0 + c) * t.ldz];
+  }
   __syncthreads();
-  for (int c = threadIdx.x; c < k; c += 256) {
-    double* z = t.Z + (int64_t)c * t.ldz;   // overwritten with the solution
-    for (int a = r1 - 1; a >= 0; --a) {
-      double s = z[a];
-      for (int b = a + 1; b < r1; ++b) s -= t.L[b + (int64_t)a * r] * z[b];
-      z[a] = s / t.L[a + (int64_t)a * r];
+  for (int hi = r1; hi > 0; hi -= 32) {
+    const int lo = hi - 32 > 0 ? hi - 32 : 0;
+    if (threadIdx.x < nc) {
+      double* z = zs + threadIdx.x * r1;
+      for (int a = hi - 1; a >= lo; --a) {
+        const double* la = L + (int64_t)a * r;
+        double s = z[a];
+        for (int b = a + 1; b < hi; ++b) s -= la[b] * z[b];
+        z[a] = s / la[a];
+      }
     }
-    for (int a = 0; a < r1; ++a) W[t.perm[a] + (int64_t)c * r] = T(z[a]);
+    __syncthreads();
+    for (int e = threadIdx.x; e < lo * nc; e += 256) {
+      const int b = e % lo, c = e / lo;
+      const double* lb = L + (int64_t)b * r;
+      const double* z = zs + c * r1;
+      double s = 0.0;
+      for (int a = lo; a < hi; ++a) s += lb[a] * z[a];
+      zs[b + c * r1] -= s;
+    }
+    __syncthreads();
+  }
+  T* W = static_cast<T*>(t.W);
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int a = e % r, c = e / r;
+    W[t.perm[a] + (int64_t)(c0 + c) * r] = a < r1 ? T(zs[a + c * r1]) : T(0);
   }
 }
 
@@ -212,7 +242,7 @@ void launch_gram(const GramTask* d_tasks, int ntasks, const int* d_tile_task, co
 
 void launch_pchol(const PcholTask* d_tasks, int ntasks, double tol, hipStream_t s) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_pchol, dim3(ntasks), dim3(256), 0, s, d_tasks, tol);
+  hipLaunchKernelGGL(k_pchol<1024>, dim3(ntasks), dim3(1024), 0, s, d_tasks, tol);
 }
 
 void launch_materialize_r(const PcholTask* d_tasks, int ntasks, hipStream_t s) {
@@ -220,14 +250,18 @@ void launch_materialize_r(const PcholTask* d_tasks, int ntasks, hipStream_t s) {
   hipLaunchKernelGGL(k_materialize_r, dim3(ntasks, 8), dim3(256), 0, s, d_tasks);
 }
 
-template <class T> void launch_wtilde(const WtTask* d_tasks, int ntasks, hipStream_t s) {
-  if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_wtilde<T>, dim3(ntasks), dim3(256), 0, s, d_tasks);
+template <class T>
+void launch_wtilde(const WtTask* d_tasks, int ntasks, int kc, int nchunks, size_t lds, hipStream_t s) {
+  if (ntasks <= 0 || nchunks <= 0) return;
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_wtilde<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  hipLaunchKernelGGL(k_wtilde<T>, dim3(ntasks, nchunks), dim3(256), lds, s, d_tasks, kc);
 }
 
 template void launch_gram<float>(const GramTask*, int, const int*, const int*, int, hipStream_t);
 template void launch_gram<double>(const GramTask*, int, const int*, const int*, int, hipStream_t);
-template void launch_wtilde<float>(const WtTask*, int, hipStream_t);
-template void launch_wtilde<double>(const WtTask*, int, hipStream_t);
+template void launch_wtilde<float>(const WtTask*, int, int, int, size_t, hipStream_t);
+template void launch_wtilde<double>(const WtTask*, int, int, int, size_t, hipStream_t);
 
 }  // namespace acr

@@ -135,6 +135,7 @@ class Exec {
   bool checking = false;
   bool trace = false;          // ACR_TRACE=1: one line per compression batch on stderr
   bool gram_ok = true;         // ACR_GRAM=0 forces Householder compression everywhere
+  size_t fused_lds = 0;        // one-workgroup SVD up to this LDS size (ACR_FUSED_LDS, bytes)
   const char* trace_tag = "";
   void check_range(const void* p, size_t bytes, const char* what) const;
 

@@ -247,7 +247,7 @@ void compress(Exec& ex, std::vector<CJob<T>>& jobs, double eps, int max_rank, Ar
     sv.p = p;
     sv.q = q;
     const bool fits = lds_bytes_qr(qu, sizeof(T)) <= kLdsBudget && lds_bytes_qr(qv, sizeof(T)) <= kLdsBudget &&
-                      lds_bytes_qrcp(sv) <= kLdsBudget;
+                      lds_bytes_svd_block(sv) <= kLdsBudget;
     (!fits && ex.gram_ok && eps >= 1e-4 ? gr : hh).push_back(&j);
   }
   if (ex.trace) {

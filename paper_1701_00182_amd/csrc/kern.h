@@ -166,10 +166,13 @@ template <class T> void launch_qr_lds(const QrTask* d_tasks, int ntasks, size_t 
 template <class T> void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, hipStream_t s);
 template <class T> void launch_jacobi(const SvdTask* d_tasks, int ntasks, double eps, int* d_flags, size_t lds,
                                       hipStream_t s);
-// Small cores (p, q, r <= kSvdWave, triangular panels): the pivoted QR, the
-// sweeps and the right vectors in one wavefront per core, no host round trip
+// Cores whose C fits in LDS: the pivoted QR, the sweeps and the right vectors
+// in one workgroup per core (one wavefront when p, q, r <= kSvdWave), with no
+// host round trip; larger cores: launch_qrcp, then launch_jacobi
 template <class T> void launch_svd_wave(const SvdTask* d_tasks, int ntasks, double delta, double eps, int* d_flags,
                                         size_t lds, hipStream_t s);
+template <class T> void launch_svd_block(const SvdTask* d_tasks, int ntasks, double delta, double eps, int* d_flags,
+                                         size_t lds, hipStream_t s);
 // Zu = Ru (Rv^T Zv) for the kept columns, kc columns per workgroup
 template <class T> void launch_core_left(const SvdTask* d_tasks, int ntasks, int kc, int nchunks, size_t lds,
                                          unsigned long long* ctr, hipStream_t s);
@@ -178,22 +181,30 @@ template <class T> void launch_gram(const GramTask* d_tasks, int ntasks, const i
                                    const int* d_first_tile, int ntiles, hipStream_t s);
 void launch_pchol(const PcholTask* d_tasks, int ntasks, double tol, hipStream_t s);
 void launch_materialize_r(const PcholTask* d_tasks, int ntasks, hipStream_t s);
-template <class T> void launch_wtilde(const WtTask* d_tasks, int ntasks, hipStream_t s);
+template <class T> void launch_wtilde(const WtTask* d_tasks, int ntasks, int kc, int nchunks, size_t lds,
+                                      hipStream_t s);
 template <class T> void launch_inner(const InnerTask* d_tasks, const int* d_wave_task, const int* d_first_wave,
                                     int nwaves, hipStream_t s);
 template <class T> void launch_apply_leaf(const LeafTask* d_tasks, int ntasks, hipStream_t s);
 constexpr size_t kLdsBudget = 156 * 1024;
 constexpr size_t kSmallLds = 32 * 1024;   // LDS-resident tasks up to this size use 256-thread workgroups
 inline size_t lds_bytes_qr(const QrTask& t, size_t w) { return (size_t)t.m * t.r * w; }
-inline size_t lds_bytes_qrcp(const SvdTask& t) { return ((size_t)t.p * t.q + t.q) * 8 + (size_t)t.q * 4; }
 inline size_t lds_bytes_jacobi(const SvdTask& t) { return (size_t)t.q * t.tc * 8; }
 constexpr int kSvdWave = 64;
 inline bool svd_wave_ok(const SvdTask& t) {
   return t.mode == 0 && t.p <= kSvdWave && t.q <= kSvdWave && t.r <= kSvdWave;
 }
-inline size_t lds_bytes_svd_wave(const SvdTask& t) {
-  const size_t lc = t.p | 1, lw = t.q | 1, stage = (size_t)(t.p + t.q) * t.r;
-  return (lc * t.q + (lw * t.q > stage ? lw * t.q : stage) + t.q) * 8 + (size_t)t.q * 4;
+inline size_t lds_bytes_svd_wave(const SvdTask& t, size_t w) {
+  const size_t lc = t.p | 1;
+  return (lc * t.q + t.q) * 8 + (size_t)2 * t.q * 4 + (size_t)t.q * t.r * w;
+}
+// one-workgroup cores up to this LDS size (beyond it the Jacobi stage runs on
+// the smaller W^T in a kernel of its own, at higher occupancy)
+constexpr size_t kFusedLds = 64 * 1024;
+inline size_t lds_bytes_qrcp(const SvdTask& t) { return ((size_t)(t.p | 1) * t.q + t.q) * 8 + (size_t)t.q * 4; }
+inline size_t lds_bytes_svd_block(const SvdTask& t) {
+  const size_t lc = t.p | 1;
+  return (lc * t.q + t.q) * 8 + (size_t)2 * t.q * 4;
 }
 inline size_t lds_bytes_applyq(const ApplyQTask& t, size_t w) { return ((size_t)t.m * t.p + (size_t)t.m * t.k) * w; }
 

@@ -250,6 +250,8 @@ void Exec::init(hipStream_t s, const Allocator& a) {
   trace = tr && tr[0] == '1';
   const char* gm = std::getenv("ACR_GRAM");
   gram_ok = !(gm && gm[0] == '0');
+  const char* fu = std::getenv("ACR_FUSED_LDS");
+  fused_lds = fu ? std::min<size_t>(std::strtoull(fu, nullptr, 10), kLdsBudget) : kFusedLds;
   stream = s;
   al = a;
   ring_bytes_ = size_t(64) << 20;
@@ -529,11 +531,13 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
   const double delta = eps > 0.0 ? 0.01 * eps : 0.0;
   int* fl = d_flags;
   for (auto& x : t) x.flop_ctr = d_svd_flops;
-  std::vector<SvdTask> small, big;
+  std::vector<SvdTask> small, mid, big;
   std::vector<int> big_idx;
   for (size_t i = 0; i < t.size(); ++i) {
     if (svd_wave_ok(t[i])) {
       small.push_back(t[i]);
+    } else if (lds_bytes_svd_block(t[i]) <= fused_lds) {
+      mid.push_back(t[i]);
     } else {
       big.push_back(t[i]);
       big_idx.push_back((int)i);
@@ -562,26 +566,32 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
     const int n = (int)b.size();
     submit([=](hipStream_t s) { launch_core_left<T>(dt, n, kc, nchunks, lds, ctr, s); }, w);
   };
-  if (!small.empty()) {
-    bucketed(small, [](const SvdTask& x) { return lds_bytes_svd_wave(x); },
-             [this, delta, eps, fl](const std::vector<SvdTask>& b, size_t lds) {
-               Work w;
-               w.cls = "svd_wave";
-               unsigned long long* ctr = g_timing ? counter_slot() : nullptr;
-               std::vector<SvdTask> bb = b;
-               for (auto& x : bb) {
-                 x.sweep_ctr = ctr;
-                 w.bytes += (double)sizeof(T) * 0.5 * ((double)x.p + x.q) * x.r;
-               }
-               // the kernel counts the flops of its core product, pivoted QR and sweeps
-               w.counter = ctr;
-               w.flops_per_count = 1.0;
-               const SvdTask* dt = upload(bb);
-               const int n = (int)bb.size();
-               submit([=](hipStream_t s) { launch_svd_wave<T>(dt, n, delta, eps, fl, lds, s); }, w);
-             });
-    left(small);
-  }
+  // one-workgroup cores: the kernels count the flops of their core product,
+  // pivoted QR and sweeps
+  auto fused = [this, delta, eps, fl](const std::vector<SvdTask>& b, size_t lds, bool wave) {
+    Work w;
+    w.cls = wave ? "svd_wave" : "svd_block";
+    unsigned long long* ctr = g_timing ? counter_slot() : nullptr;
+    std::vector<SvdTask> bb = b;
+    for (auto& x : bb) {
+      x.sweep_ctr = ctr;
+      w.bytes += (double)sizeof(T) * 0.5 * ((double)x.p + x.q) * x.r;
+    }
+    w.counter = ctr;
+    w.flops_per_count = 1.0;
+    const SvdTask* dt = upload(bb);
+    const int n = (int)bb.size();
+    if (wave)
+      submit([=](hipStream_t s) { launch_svd_wave<T>(dt, n, delta, eps, fl, lds, s); }, w);
+    else
+      submit([=](hipStream_t s) { launch_svd_block<T>(dt, n, delta, eps, fl, lds, s); }, w);
+  };
+  bucketed(small, [](const SvdTask& x) { return lds_bytes_svd_wave(x, sizeof(T)); },
+           [&](const std::vector<SvdTask>& b, size_t lds) { fused(b, lds, true); });
+  bucketed(mid, [](const SvdTask& x) { return lds_bytes_svd_block(x); },
+           [&](const std::vector<SvdTask>& b, size_t lds) { fused(b, lds, false); });
+  small.insert(small.end(), mid.begin(), mid.end());
+  left(small);
   if (big.empty()) return;
   for (auto& x : big) flops_svd += 2.0 * x.p * x.q * (double)x.r;
   bucketed(big, [](const SvdTask& x) { return lds_bytes_qrcp(x); },
@@ -616,7 +626,7 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
       mt = std::max(mt, x.tc);
       nl += lds_bytes_jacobi(x) <= kLdsBudget;
     }
-    std::fprintf(stderr, "[acr] svd %s small=%zu big=%zu (lds %d) max_q=%d max_t=%d\n", trace_tag, small.size(),
+    std::fprintf(stderr, "[acr] svd %s fused=%zu big=%zu (jacobi in lds %d) max_q=%d max_t=%d\n", trace_tag, small.size(),
                  big.size(), nl, mq, mt);
   }
   // the pivoted QR stopped at rank t: add its Householder work to the timing record
@@ -733,6 +743,7 @@ template <class T> void Exec::wtilde(const std::vector<WtTask>& t) {
     check_range(x.W, sizeof(T) * (size_t)x.r * x.k, "wtilde W");
     check_range(x.Z, sizeof(double) * ext(x.r1, x.k, x.ldz), "wtilde Z");
     check_range(x.L, sizeof(double) * (size_t)x.r * x.r, "wtilde L");
+    check_range(x.perm, sizeof(int) * x.r, "wtilde perm");
   }
   Work w;
   w.cls = "wtilde";
@@ -740,9 +751,20 @@ template <class T> void Exec::wtilde(const std::vector<WtTask>& t) {
     w.flops += (double)x.r1 * x.r1 * x.k;
     w.bytes += 8.0 * x.r1 * x.r1 / 2 + sizeof(T) * (double)x.r * x.k;
   }
+  int r1max = 1, kmax = 0;
+  for (auto& x : t) {
+    if (x.r1 > x.r || x.r1 < 0) throw Failure(ST_HIP, "bounds check: wtilde rank");
+    r1max = std::max(r1max, x.r1);
+    kmax = std::max(kmax, x.k);
+  }
+  int kc = 64;
+  while (kc > 1 && (size_t)r1max * kc * 8 > 64 * 1024) kc >>= 1;
+  const size_t lds = (size_t)r1max * kc * 8;
+  if (lds > kLdsBudget) throw Failure(ST_NOT_SUPPORTED, "rank too large for the back-substitution kernel");
+  const int nchunks = (kmax + kc - 1) / kc;
   const WtTask* dt = upload(t);
   const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_wtilde<T>(dt, n, s); }, w);
+  submit([=](hipStream_t s) { launch_wtilde<T>(dt, n, kc, nchunks, lds, s); }, w);
 }
 
 template <class T> void Exec::inner(const std::vector<InnerTask>& t) {

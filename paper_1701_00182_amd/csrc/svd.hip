@@ -1,19 +1,21 @@
 // Truncated SVD of the compression core C = Ru Rv^T (FP64).
 //
-// Stage 1 (k_qrcp): Householder QR with column pivoting of C, stopped when the
-// largest remaining column norm drops below delta times the largest initial
-// one; C P ~= Q [R11 R12].  Stage 2 (k_jacobi): one-sided Jacobi on the
-// columns of W^T = P [R11 R12]^T (q x t), whose singular values are those of C
-// up to the dropped tail.  QR with column pivoting both removes the directions
-// far below the truncation level and preconditions the Jacobi iteration, which
-// then converges in a few sweeps.  The right singular vectors are the
-// normalised rotated columns; the left factor is recomputed as C Zv = U Sigma
-// by k_core_left, all kept columns at once.
+// Stage 1: Householder QR with column pivoting of C, stopped when the largest
+// remaining column norm drops below delta times the largest initial one;
+// C P ~= Q R with R = [R11 R12] (t x q).  Stage 2: one-sided Jacobi on the t
+// rows of R, whose singular values are those of C up to the dropped tail.  QR
+// with column pivoting both removes the directions far below the truncation
+// level and preconditions the Jacobi iteration, which then converges in a few
+// sweeps.  The right singular vectors are the normalised rotated rows (mapped
+// back through P); the left factor is recomputed as C Zv = U Sigma by
+// k_core_left, all kept columns at once.
 //
-// Cores with p, q, r <= 64 (most of them: the blocks near the leaves) run both
-// stages in one wavefront (k_svd_wave): one lane per column of C for the
-// pivoted QR, lane groups per column pair for the sweeps, wavefront shuffles
-// instead of workgroup reductions, and no host round trip between the stages.
+// Cores whose C is small run both stages in one workgroup with R rotated in
+// place (k_svd_wave: one wavefront, lane per column, for p, q, r <= 64;
+// k_svd_block up to kFusedLds bytes); larger ones take the pivoted QR (C in
+// LDS when it fits, else in global memory) and then k_jacobi on the smaller
+// W^T = P R^T (q x t), in LDS when it fits.
+
 #include <cmath>
 
 #include "kern.h"
@@ -91,29 +93,20 @@ __device__ inline double core_entry(const SvdTask& t, int a, int b) {
   return acc;
 }
 
-template <class T, bool LDS, int NT>
-__global__ __launch_bounds__(NT) void k_qrcp(const SvdTask* __restrict__ tasks, double delta) {
-  extern __shared__ double smc[];
-  const SvdTask t = tasks[blockIdx.x];
-  const int p = t.p, q = t.q;
+// Householder QR with column pivoting of C (p x q, column stride lc), stopped
+// at the first pivot column whose remaining norm^2 is at most thr2 (see
+// callers); returns the number of reflectors t.  R is left in the upper
+// triangle of the first t rows, reflectors below it.  All threads call it.
+template <int NT>
+__device__ int qrcp_body(double* C, int64_t lc, int p, int q, double* nrm, int* perm, double delta, double* red,
+                         int* redi) {
   const int mn = p < q ? p : q;
-  if (p == 0 || q == 0) {
-    if (threadIdx.x == 0) *t.t_out = 0;
-    return;
-  }
-  double* C = LDS ? smc : t.C;
-  double* nrm = LDS ? smc + (int64_t)p * q : t.sig;
-  int* perm = LDS ? reinterpret_cast<int*>(nrm + q) : t.perm;
-  __shared__ double red[NT / 64];
-  __shared__ int redi[NT / 64];
-  for (int64_t e = threadIdx.x; e < (int64_t)p * q; e += NT) C[e] = core_entry<T>(t, (int)(e % p), (int)(e / p));
-  __syncthreads();
   const int G = lanes_for(p), groups = NT / G;
   const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   double mx = 0.0;
   for (int c = gi; c < q; c += groups) {
     double s = 0.0;
-    for (int i = gl; i < p; i += G) s += C[i + (int64_t)c * p] * C[i + (int64_t)c * p];
+    for (int i = gl; i < p; i += G) s += C[i + c * lc] * C[i + c * lc];
     s = gsum2(s, G);
     if (gl == 0) { nrm[c] = s; perm[c] = c; }
     mx = fmax(mx, s);
@@ -135,9 +128,9 @@ __global__ __launch_bounds__(NT) void k_qrcp(const SvdTask* __restrict__ tasks, 
     const int pc = bc;
     if (pc != j) {
       for (int i = threadIdx.x; i < p; i += NT) {
-        const double a = C[i + (int64_t)j * p];
-        C[i + (int64_t)j * p] = C[i + (int64_t)pc * p];
-        C[i + (int64_t)pc * p] = a;
+        const double a = C[i + j * lc];
+        C[i + j * lc] = C[i + pc * lc];
+        C[i + pc * lc] = a;
       }
       if (threadIdx.x == 0) {
         const double a = nrm[j];
@@ -149,7 +142,7 @@ __global__ __launch_bounds__(NT) void k_qrcp(const SvdTask* __restrict__ tasks, 
       }
       __syncthreads();
     }
-    double* col = C + (int64_t)j * p;
+    double* col = C + j * lc;
     double ps = 0.0;
     for (int i = j + 1 + threadIdx.x; i < p; i += NT) ps += col[i] * col[i];
     const double sigma = block_sum<NT>(ps, red);
@@ -167,7 +160,7 @@ __global__ __launch_bounds__(NT) void k_qrcp(const SvdTask* __restrict__ tasks, 
     if (threadIdx.x == 0) col[j] = beta;
     __syncthreads();
     for (int c = j + 1 + gi; c < q; c += groups) {
-      double* ac = C + (int64_t)c * p;
+      double* ac = C + c * lc;
       if (tj != 0.0) {
         double w = 0.0;
         for (int i = j + gl; i < p; i += G) w += (i == j ? 1.0 : col[i]) * ac[i];
@@ -182,16 +175,42 @@ __global__ __launch_bounds__(NT) void k_qrcp(const SvdTask* __restrict__ tasks, 
     __syncthreads();
     tcount = j + 1;
   }
-  // W^T (q x tcount), rows in the original column order of C
+  return tcount;
+}
+
+// Pivoted QR of cores that do not take the one-workgroup path, with C in LDS
+// (ld p|1, then q norms and q pivots) or in the global workspace; writes
+// W^T = P R^T (q x t) to Y for k_jacobi.
+template <class T, bool LDS, int NT>
+__global__ __launch_bounds__(NT) void k_qrcp(const SvdTask* __restrict__ tasks, double delta) {
+  extern __shared__ double smc[];
+  const SvdTask t = tasks[blockIdx.x];
+  const int p = t.p, q = t.q;
+  if (p == 0 || q == 0) {
+    if (threadIdx.x == 0) *t.t_out = 0;
+    return;
+  }
+  const int lc = LDS ? (p | 1) : p;
+  double* C = LDS ? smc : t.C;
+  double* nrm = LDS ? smc + (int64_t)lc * q : t.sig;
+  int* perm = LDS ? reinterpret_cast<int*>(nrm + q) : t.perm;
+  __shared__ double red[NT / 64];
+  __shared__ int redi[NT / 64];
+  for (int64_t e = threadIdx.x; e < (int64_t)p * q; e += NT) {
+    const int a = (int)(e % p), c = (int)(e / p);
+    C[a + (int64_t)c * lc] = core_entry<T>(t, a, c);
+  }
+  __syncthreads();
+  const int tcount = qrcp_body<NT>(C, lc, p, q, nrm, perm, delta, red, redi);
   double* Wt = t.Y;
   for (int64_t e = threadIdx.x; e < (int64_t)q * tcount; e += NT) {
     const int c = (int)(e % q), a = (int)(e / q);
-    Wt[perm[c] + (int64_t)a * q] = c >= a ? C[a + (int64_t)c * p] : 0.0;
+    Wt[perm[c] + (int64_t)a * q] = c >= a ? C[a + (int64_t)c * lc] : 0.0;
   }
   if (threadIdx.x == 0) *t.t_out = tcount;
 }
 
-// Jacobi rotation of the column pair (x, y) that zeroes their inner product;
+// Jacobi rotation of the vector pair (x, y) that zeroes their inner product;
 // false when the pair is already orthogonal to the tolerance.
 __device__ inline bool jacobi_rotation(double al, double be, double ga, double tol, double& cs, double& sn) {
   if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al * be))) return false;
@@ -204,8 +223,8 @@ __device__ inline bool jacobi_rotation(double al, double be, double ga, double t
   return true;
 }
 
-// Column indices of pair pi in round `round` of the cyclic tournament over ne
-// (even) columns: column 0 stays, the others shift by one position per round.
+// Indices of pair pi in round `round` of the cyclic tournament over ne (even)
+// vectors: vector 0 stays, the others shift by one position per round.
 __device__ inline void tournament_pair(int pi, int round, int ne, int& ia, int& ib) {
   const int pa = pi, pb = ne - 1 - pi;
   ia = pa == 0 ? 0 : ((pa - 1 + round) % (ne - 1)) + 1;
@@ -213,20 +232,21 @@ __device__ inline void tournament_pair(int pi, int round, int ne, int& ia, int& 
   if (ia > ib) { const int tmp = ia; ia = ib; ib = tmp; }
 }
 
-// One Jacobi step on the column pair (ca, cb) of length rows, handled by the G
-// lanes of a group (gl = lane in group): the three inner products, the rotation
-// and its application.  Columns of up to G * kJR rows stay in registers between
-// the products and the update.  Returns whether a rotation was applied.
+// One Jacobi step on the vector pair (xa, xb) of length len (element i at
+// index i * st), handled by the G lanes of a group (gl = lane in group): the
+// three inner products, the rotation and its application.  Vectors of up to
+// G * kJR elements stay in registers between the products and the update.
+// Returns whether a rotation was applied.
 constexpr int kJR = 12;
-__device__ inline bool jacobi_pair(double* ca, double* cb, int rows, int G, int gl, double tol) {
+__device__ inline bool jacobi_pair(double* xa, double* xb, int st, int len, int G, int gl, double tol) {
   double al = 0.0, be = 0.0, ga = 0.0;
-  if (rows <= G * kJR) {
+  if (len <= G * kJR) {
     double xr[kJR], yr[kJR];
 #pragma unroll
     for (int u = 0; u < kJR; ++u) {
       const int i = gl + u * G;
-      xr[u] = i < rows ? ca[i] : 0.0;
-      yr[u] = i < rows ? cb[i] : 0.0;
+      xr[u] = i < len ? xa[i * st] : 0.0;
+      yr[u] = i < len ? xb[i * st] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kJR; ++u) {
@@ -242,15 +262,15 @@ __device__ inline bool jacobi_pair(double* ca, double* cb, int rows, int G, int 
 #pragma unroll
     for (int u = 0; u < kJR; ++u) {
       const int i = gl + u * G;
-      if (i < rows) {
-        ca[i] = cs * xr[u] - sn * yr[u];
-        cb[i] = sn * xr[u] + cs * yr[u];
+      if (i < len) {
+        xa[i * st] = cs * xr[u] - sn * yr[u];
+        xb[i * st] = sn * xr[u] + cs * yr[u];
       }
     }
     return true;
   }
-  for (int i = gl; i < rows; i += G) {
-    const double x = ca[i], y = cb[i];
+  for (int i = gl; i < len; i += G) {
+    const double x = xa[i * st], y = xb[i * st];
     al += x * x;
     be += y * y;
     ga += x * y;
@@ -260,18 +280,102 @@ __device__ inline bool jacobi_pair(double* ca, double* cb, int rows, int G, int 
   ga = gsum2(ga, G);
   double cs, sn;
   if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
-  for (int i = gl; i < rows; i += G) {
-    const double x = ca[i], y = cb[i];
-    ca[i] = cs * x - sn * y;
-    cb[i] = sn * x + cs * y;
+  for (int i = gl; i < len; i += G) {
+    const double x = xa[i * st], y = xb[i * st];
+    xa[i * st] = cs * x - sn * y;
+    xb[i * st] = sn * x + cs * y;
   }
   return true;
 }
 
+// One-sided Jacobi SVD of n vectors of length len: vector i starts at V + i * vs
+// and has element stride es.  Then the singular values (vector norms, written
+// to sig and t.sig), the rank k = #{sigma > eps sigma_max} (capped at
+// max_rank, with a flag), and the right vectors in decreasing-sigma order:
+// Zv[map(e) + ps * q] = x_i[e] / sigma_i, map(e) = perm ? perm[e] : e.  `ord`
+// is n ints of scratch, red / redi one slot per wavefront.  Groups have at
+// least min_g lanes (16 keeps global-memory vectors coalesced).  Returns k;
+// all threads call it.
+template <int NT>
+__device__ int jacobi_svd(double* V, int64_t vs, int64_t es, int n, int len, const int* perm, double* sig, int* ord,
+                          double eps, const SvdTask& t, int* flags, double* red, int* redi, int& sweeps,
+                          int min_g = 1) {
+  const int ne = n + (n & 1), npairs = ne / 2;
+  int G = 64;
+  while (G > min_g && G * npairs > NT) G >>= 1;
+  while (G > 1 && G > 2 * len) G >>= 1;
+  const int groups = NT / G;
+  const int gi = threadIdx.x / G, gl = threadIdx.x % G;
+  const double tol = fmax(1e-15, 2.3e-16 * (double)len);
+  sweeps = 0;
+  for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
+    ++sweeps;
+    int rot = 0;
+    for (int round = 0; round < ne - 1; ++round) {
+      for (int pi = gi; pi < npairs; pi += groups) {
+        int ia, ib;
+        tournament_pair(pi, round, ne, ia, ib);
+        if (ib >= n) continue;
+        if (jacobi_pair(V + ia * vs, V + ib * vs, (int)es, len, G, gl, tol)) rot = 1;
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rot)) break;
+  }
+  for (int i = gi; i < n; i += groups) {
+    const double* x = V + i * vs;
+    double ss = 0.0;
+    for (int e = gl; e < len; e += G) ss += x[e * es] * x[e * es];
+    ss = gsum2(ss, G);
+    if (gl == 0) {
+      sig[i] = sqrt(ss);
+      t.sig[i] = sqrt(ss);
+    }
+  }
+  __syncthreads();
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) mx = fmax(mx, sig[i]);
+  {
+    int dummy = 0;
+    block_argmax<NT>(mx, dummy, red, redi);
+  }
+  const double smax = mx;
+  const double thr = eps > 0.0 ? eps * smax : 0.0;
+  double cnt = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) cnt += (smax > 0.0 && sig[i] > thr) ? 1.0 : 0.0;
+  int k = (int)block_sum<NT>(cnt, red);
+  if (t.max_rank > 0 && k > t.max_rank) {
+    if (threadIdx.x == 0) atomicOr(&flags[FLAG_RANK], 1);
+    k = t.max_rank;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const double si = sig[i];
+    int ps = 0;
+    for (int j = 0; j < n; ++j) {
+      const double sj = sig[j];
+      ps += (sj > si || (sj == si && j < i)) ? 1 : 0;
+    }
+    ord[i] = ps;
+  }
+  __syncthreads();
+  const int q = t.q;
+  double* Zv = t.Y + (int64_t)q * q;
+  for (int i = gi; i < n; i += groups) {
+    const int ps = ord[i];
+    if (ps >= k) continue;
+    const double inv = 1.0 / sig[i];
+    const double* x = V + i * vs;
+    for (int e = gl; e < len; e += G) Zv[(perm ? perm[e] : e) + (int64_t)ps * q] = x[e * es] * inv;
+  }
+  return k;
+}
+
+// Jacobi stage of the cores whose pivoted QR ran in global memory: W^T
+// (q x t, from k_qrcp) in LDS when it fits, else in place in global memory.
 template <class T, bool LDS, int NT>
 __global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks, double eps, int* flags) {
   extern __shared__ double smj[];
-  constexpr int NW = NT / 64;
   const SvdTask t = tasks[blockIdx.x];
   const int rows = t.q;
   const int n = *t.t_out;
@@ -280,84 +384,15 @@ __global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks
     return;
   }
   double* A = LDS ? smj : t.Y;
-  double* sig = t.sig;
-  __shared__ double red[NW];
-  __shared__ int sh_rot;
+  __shared__ double red[NT / 64];
+  __shared__ int redi[NT / 64];
   if (LDS)
     for (int64_t e = threadIdx.x; e < (int64_t)rows * n; e += NT) A[e] = t.Y[e];
   __syncthreads();
-  const int ne = n + (n & 1), npairs = ne / 2;
-  int G = 64;
-  while (G > 1 && G * npairs > NT) G >>= 1;
-  if (!LDS && G < 16) G = 16;
-  while (G > 1 && G > 2 * rows) G >>= 1;
-  const int groups = NT / G;
-  const int gi = threadIdx.x / G, gl = threadIdx.x % G;
-  const double tol = fmax(1e-15, 2.3e-16 * (double)rows);
   int sweeps = 0;
-  for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
-    if (threadIdx.x == 0) sh_rot = 0;
-    __syncthreads();
-    ++sweeps;
-    for (int round = 0; round < ne - 1; ++round) {
-      for (int pi = gi; pi < npairs; pi += groups) {
-        int ia, ib;
-        tournament_pair(pi, round, ne, ia, ib);
-        if (ib >= n) continue;
-        if (jacobi_pair(A + (int64_t)ia * rows, A + (int64_t)ib * rows, rows, G, gl, tol) && gl == 0) sh_rot = 1;
-      }
-      __syncthreads();
-    }
-    const int rot = sh_rot;
-    __syncthreads();
-    if (!rot) break;
-  }
-  for (int i = gi; i < n; i += groups) {
-    const double* ci = A + (int64_t)i * rows;
-    double ss = 0.0;
-    for (int l = gl; l < rows; l += G) ss += ci[l] * ci[l];
-    ss = gsum2(ss, G);
-    if (gl == 0) sig[i] = sqrt(ss);
-  }
-  __syncthreads();
-  double mx = 0.0;
-  for (int i = threadIdx.x; i < n; i += NT) mx = fmax(mx, sig[i]);
-  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  double smax = 0.0;
-  for (int w = 0; w < NW; ++w) smax = fmax(smax, red[w]);
-  const double thr = eps > 0.0 ? eps * smax : 0.0;
-  int cnt = 0;
-  for (int i = threadIdx.x; i < n; i += NT) cnt += (smax > 0.0 && sig[i] > thr) ? 1 : 0;
-  double cs_ = (double)cnt;
-  for (int off = 32; off > 0; off >>= 1) cs_ += __shfl_xor(cs_, off, 64);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cs_;
-  __syncthreads();
-  double kk = 0.0;
-  for (int w = 0; w < NW; ++w) kk += red[w];
-  int k = (int)kk;
-  if (t.max_rank > 0 && k > t.max_rank) {
-    if (threadIdx.x == 0) atomicOr(&flags[FLAG_RANK], 1);
-    k = t.max_rank;
-  }
-  // right vectors: normalised rotated columns, ordered by decreasing sigma
-  const int q = t.q;
-  double* Zv = t.Y + (int64_t)q * q;
-  for (int i = gi; i < n; i += groups) {
-    const double si = sig[i];
-    double pos = 0.0;
-    for (int j = gl; j < n; j += G) {
-      const double sj = sig[j];
-      pos += (sj > si || (sj == si && j < i)) ? 1.0 : 0.0;
-    }
-    const int ps = (int)gsum2(pos, G);
-    if (ps < k) {
-      const double inv = 1.0 / si;
-      for (int l = gl; l < rows; l += G) Zv[l + (int64_t)ps * q] = A[l + (int64_t)i * rows] * inv;
-    }
-  }
+  // the pivot order is no longer needed: its workspace holds the sigma ranks
+  const int k = jacobi_svd<NT>(A, rows, 1, n, rows, nullptr, t.sig, t.perm, eps, t, flags, red, redi, sweeps,
+                               LDS ? 1 : 16);
   if (threadIdx.x == 0) {
     *t.rank_out = k;
     const unsigned long long visits =
@@ -367,9 +402,89 @@ __global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks
   }
 }
 
+// flops of one core: its product (macs multiply-adds), the pivoted QR stopped
+// at n, and 12 per element of each pair visit of the sweeps
+__device__ inline void count_core_flops(const SvdTask& t, double macs, int n, int sweeps) {
+  const double dp = t.p, dq = t.q, dn = n;
+  const double fl = 2.0 * macs + 4.0 * dp * dq * dn - 2.0 * dn * dn * (dp + dq) + 4.0 / 3.0 * dn * dn * dn +
+                    12.0 * (double)sweeps * (dn * (dn - 1.0) / 2.0) * dq;
+  const unsigned long long f = (unsigned long long)(fl > 0.0 ? fl : 0.0);
+  if (t.sweep_ctr) atomicAdd(t.sweep_ctr, f);
+  if (t.flop_ctr) atomicAdd(t.flop_ctr, f);
+}
+
+// multiply-adds of the core product: sum over (a, b) of r - max(a, b) for
+// triangular panels
+__device__ inline double core_macs(const SvdTask& t) {
+  if (t.mode != 0) return (double)t.p * t.q * t.r;
+  const double r = t.r;
+  double m = 0.0;
+  for (int a = 0; a < t.p; ++a) {
+    const double lo = (a + 1 < t.q ? a + 1 : t.q);            // b <= a
+    const double hi = (double)(t.q - a - 1 > 0 ? t.q - a - 1 : 0);  // b = a+1 .. q-1
+    m += lo * (r - a) + hi * r - hi * ((double)a + 1.0 + (double)t.q - 1.0) / 2.0;
+  }
+  return m;
+}
+
+// Zero the strictly lower part of the first n rows of R (the reflectors).
+__device__ inline void clear_below(double* C, int lc, int n, int nt) {
+  for (int e = threadIdx.x; e < n * n; e += nt) {
+    const int a = e % n, c = e / n;
+    if (c < a) C[a + c * lc] = 0.0;
+  }
+}
+
+// Cores whose C fits in LDS: core product, pivoted QR, then the sweeps on the
+// columns of W^T = P R^T (q x t, copied into the C region), in one workgroup.
+// LDS: C (p x q, ld p|1), q norms, q pivots, q ints of scratch.
+template <class T, int NT>
+__global__ __launch_bounds__(NT) void k_svd_block(const SvdTask* __restrict__ tasks, double delta, double eps,
+                                                  int* flags) {
+  extern __shared__ double smb[];
+  const SvdTask t = tasks[blockIdx.x];
+  const int p = t.p, q = t.q;
+  if (p == 0 || q == 0) {
+    if (threadIdx.x == 0) { *t.t_out = 0; *t.rank_out = 0; }
+    return;
+  }
+  const int lc = p | 1;
+  double* C = smb;
+  double* nrm = C + lc * q;
+  int* perm = reinterpret_cast<int*>(nrm + q);
+  int* ord = perm + q;
+  __shared__ double red[NT / 64];
+  __shared__ int redi[NT / 64];
+  for (int e = threadIdx.x; e < p * q; e += NT) {
+    const int a = e % p, c = e / p;
+    C[a + c * lc] = core_entry<T>(t, a, c);
+  }
+  __syncthreads();
+  const int n = qrcp_body<NT>(C, lc, p, q, nrm, perm, delta, red, redi);
+  // W^T = P R^T (q x n) through the global workspace back into the C region:
+  // the sweeps then run on contiguous columns
+  double* Wt = t.Y;
+  for (int e = threadIdx.x; e < q * n; e += NT) {
+    const int c = e % q, a = e / q;
+    Wt[perm[c] + a * q] = c >= a ? C[a + c * lc] : 0.0;
+  }
+  __threadfence();
+  __syncthreads();
+  for (int e = threadIdx.x; e < q * n; e += NT) C[e] = Wt[e];
+  __syncthreads();
+  int sweeps = 0;
+  const int k = n > 0 ? jacobi_svd<NT>(C, q, 1, n, q, nullptr, nrm, ord, eps, t, flags, red, redi, sweeps) : 0;
+  if (threadIdx.x == 0) {
+    *t.t_out = n;
+    *t.rank_out = k;
+    count_core_flops(t, core_macs(t), n, sweeps);
+  }
+}
+
 // The whole truncated SVD of one small core (p, q, r <= 64, triangular panels)
-// in one wavefront.  LDS: C (p x q, ld p|1), then a region holding first the
-// staged panels Ru, Rv and later W^T (q x t, ld q|1), then q norms and q pivots.
+// in one wavefront: lane b forms column b of C from the staged Rv panel, the
+// pivoted QR runs with one lane per column and wavefront shuffles.  LDS: C
+// (p x q, ld p|1), Rv staged in T (q x r), q norms, q pivots, q ints.
 template <class T>
 __global__ __launch_bounds__(64) void k_svd_wave(const SvdTask* __restrict__ tasks, double delta, double eps,
                                                  int* flags) {
@@ -380,28 +495,26 @@ __global__ __launch_bounds__(64) void k_svd_wave(const SvdTask* __restrict__ tas
     if (lane == 0) { *t.t_out = 0; *t.rank_out = 0; }
     return;
   }
-  const int lc = p | 1, lw = q | 1;
-  const int wsz = lw * q > (p + q) * r ? lw * q : (p + q) * r;
+  const int lc = p | 1;
   double* C = sw;
-  double* W = sw + lc * q;
-  double* nrm = W + wsz;
+  double* nrm = C + lc * q;
   int* perm = reinterpret_cast<int*>(nrm + q);
-  // stage the panels (rows a <= l of column l are the nonzero part)
+  int* ord = perm + q;
+  T* sv = reinterpret_cast<T*>(ord + q);   // q x r, ld q (8-byte aligned: 2q ints precede it)
+  __shared__ double red[1];
+  __shared__ int redi[1];
   {
     const T* Ru = static_cast<const T*>(t.Ru);
     const T* Rv = static_cast<const T*>(t.Rv);
-    double* su = W;            // p x r, ld p
-    double* sv = W + p * r;    // q x r, ld q
-    for (int l = 0; l < r; ++l) {
-      if (lane < p) su[lane + l * p] = lane <= l ? (double)Ru[lane + (int64_t)l * t.ldu] : 0.0;
-      if (lane < q) sv[lane + l * q] = lane <= l ? (double)Rv[lane + (int64_t)l * t.ldv] : 0.0;
-    }
+    for (int l = 0; l < r; ++l)
+      if (lane < q) sv[lane + l * q] = lane <= l ? Rv[lane + (int64_t)l * t.ldv] : T(0);
     __syncthreads();
-    // C = Ru Rv^T, lane b forms column b
+    // C = Ru Rv^T: lane b forms column b; Ru entries are uniform across lanes
     if (lane < q)
       for (int a = 0; a < p; ++a) {
+        const T* ra = Ru + a;
         double s = 0.0;
-        for (int l = a > lane ? a : lane; l < r; ++l) s += su[a + l * p] * sv[lane + l * q];
+        for (int l = a > lane ? a : lane; l < r; ++l) s += (double)ra[(int64_t)l * t.ldu] * (double)sv[lane + l * q];
         C[a + lane * lc] = s;
       }
     __syncthreads();
@@ -420,11 +533,7 @@ __global__ __launch_bounds__(64) void k_svd_wave(const SvdTask* __restrict__ tas
   for (int j = 0; j < mn; ++j) {
     double best = (lane >= j && lane < q) ? nrm[lane] : -1.0;
     int bi = lane;
-    for (int off = 32; off > 0; off >>= 1) {
-      const double o = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (o > best || (o == best && oi < bi)) { best = o; bi = oi; }
-    }
+    wargmax(best, bi);
     if (!(best > thr2) || !(best > 0.0)) break;
     if (bi != j) {
       if (lane < p) {
@@ -473,66 +582,11 @@ __global__ __launch_bounds__(64) void k_svd_wave(const SvdTask* __restrict__ tas
     tcount = j + 1;
   }
   const int n = tcount;
-  // W^T (q x n), rows in the original column order of C
-  for (int a = 0; a < n; ++a)
-    if (lane < q) W[perm[lane] + a * lw] = lane >= a ? C[a + lane * lc] : 0.0;
+  clear_below(C, lc, n, 64);
   __syncthreads();
-  // one-sided Jacobi on the n columns of W^T
-  const int ne = n + (n & 1), npairs = ne / 2;
-  int G = 64;
-  while (G > 1 && G * npairs > 64) G >>= 1;
-  while (G > 1 && G > 2 * q) G >>= 1;
-  const int groups = 64 / G;
-  const int gi = lane / G, gl = lane % G;
-  const double tol = fmax(1e-15, 2.3e-16 * (double)q);
   int sweeps = 0;
-  for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
-    ++sweeps;
-    int rot = 0;
-    for (int round = 0; round < ne - 1; ++round) {
-      for (int pi = gi; pi < npairs; pi += groups) {
-        int ia, ib;
-        tournament_pair(pi, round, ne, ia, ib);
-        if (ib >= n) continue;
-        if (jacobi_pair(W + ia * lw, W + ib * lw, q, G, gl, tol)) rot = 1;
-      }
-      __syncthreads();
-    }
-    if (!__any(rot)) break;
-  }
-  // singular values, rank, right vectors ordered by decreasing sigma
-  double si = 0.0;
-  for (int i = 0; i < n; ++i) {
-    double ss = 0.0;
-    for (int l = lane; l < q; l += 64) ss += W[l + i * lw] * W[l + i * lw];
-    ss = wsum(ss);
-    if (lane == i) si = sqrt(ss);
-  }
-  const double smax = wmax(lane < n ? si : 0.0);
-  const double thr = eps > 0.0 ? eps * smax : 0.0;
-  int k = __popcll(__ballot(lane < n && smax > 0.0 && si > thr));
-  if (t.max_rank > 0 && k > t.max_rank) {
-    if (lane == 0) atomicOr(&flags[FLAG_RANK], 1);
-    k = t.max_rank;
-  }
-  if (lane < n) {
-    t.sig[lane] = si;
-    int ps = 0;
-    for (int j = 0; j < n; ++j) {
-      const double sj = __shfl(si, j, 64);
-      ps += (sj > si || (sj == si && j < lane)) ? 1 : 0;
-    }
-    perm[lane] = ps;
-  }
-  __syncthreads();
-  double* Zv = t.Y + (int64_t)q * q;
-  for (int i = 0; i < n; ++i) {
-    const int ps = perm[i];
-    if (ps >= k) continue;
-    const double inv = 1.0 / __shfl(si, i, 64);
-    if (lane < q) Zv[lane + (int64_t)ps * q] = W[lane + i * lw] * inv;
-  }
-  // flops: core product, pivoted QR stopped at n, and 12 per row of each pair visit
+  const int k = n > 0 ? jacobi_svd<64>(C, 1, lc, n, q, perm, nrm, ord, eps, t, flags, red, redi, sweeps) : 0;
+  // multiply-adds of the core product
   double macs = 0.0;
   if (lane < q)
     for (int a = 0; a < p; ++a) macs += (double)(r - (a > lane ? a : lane));
@@ -540,12 +594,7 @@ __global__ __launch_bounds__(64) void k_svd_wave(const SvdTask* __restrict__ tas
   if (lane == 0) {
     *t.t_out = n;
     *t.rank_out = k;
-    const double dp = p, dq = q, dn = n;
-    const double fl = 2.0 * macs + 4.0 * dp * dq * dn - 2.0 * dn * dn * (dp + dq) + 4.0 / 3.0 * dn * dn * dn +
-                      12.0 * (double)sweeps * (dn * (dn - 1.0) / 2.0) * dq;
-    const unsigned long long f = (unsigned long long)(fl > 0.0 ? fl : 0.0);
-    if (t.sweep_ctr) atomicAdd(t.sweep_ctr, f);
-    if (t.flop_ctr) atomicAdd(t.flop_ctr, f);
+    count_core_flops(t, macs, n, sweeps);
   }
 }
 
@@ -618,10 +667,10 @@ template <class K> void allow(K kernel, size_t bytes) {
 
 }  // namespace
 
-// Cores beyond the one-wavefront size whose working set exceeds kSmallLds run
-// with 1024 threads: their LDS footprint already limits them to one or two
-// workgroups per compute unit, and the extra wavefronts hide LDS latency and
-// shorten the critical path of each core.
+// Large-core stages run with 1024 threads when their LDS working set exceeds
+// kSmallLds (it already limits them to one or two workgroups per compute
+// unit; the extra wavefronts hide latency and shorten each core's critical
+// path), with 256 threads otherwise.
 template <class T>
 void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, hipStream_t s) {
   if (ntasks <= 0) return;
@@ -654,6 +703,22 @@ void launch_jacobi(const SvdTask* d_tasks, int ntasks, double eps, int* d_flags,
   hipLaunchKernelGGL((k_jacobi<T, true, 1024>), dim3(ntasks), dim3(1024), lds, s, d_tasks, eps, d_flags);
 }
 
+// Cores whose LDS working set exceeds kSmallLds use 1024 threads (their LDS
+// footprint already limits them to one or two workgroups per compute unit and
+// the extra wavefronts hide LDS latency), smaller ones 256.
+template <class T>
+void launch_svd_block(const SvdTask* d_tasks, int ntasks, double delta, double eps, int* d_flags, size_t lds,
+                      hipStream_t s) {
+  if (ntasks <= 0) return;
+  if (lds <= kSmallLds) {
+    allow(k_svd_block<T, 256>, lds);
+    hipLaunchKernelGGL((k_svd_block<T, 256>), dim3(ntasks), dim3(256), lds, s, d_tasks, delta, eps, d_flags);
+    return;
+  }
+  allow(k_svd_block<T, 1024>, lds);
+  hipLaunchKernelGGL((k_svd_block<T, 1024>), dim3(ntasks), dim3(1024), lds, s, d_tasks, delta, eps, d_flags);
+}
+
 template <class T>
 void launch_svd_wave(const SvdTask* d_tasks, int ntasks, double delta, double eps, int* d_flags, size_t lds,
                      hipStream_t s) {
@@ -670,13 +735,14 @@ void launch_core_left(const SvdTask* d_tasks, int ntasks, int kc, int nchunks, s
   hipLaunchKernelGGL(k_core_left<T>, dim3(ntasks, nchunks), dim3(256), lds, s, d_tasks, kc, ctr);
 }
 
-template void launch_qrcp<float>(const SvdTask*, int, double, size_t, hipStream_t);
-template void launch_qrcp<double>(const SvdTask*, int, double, size_t, hipStream_t);
-template void launch_jacobi<float>(const SvdTask*, int, double, int*, size_t, hipStream_t);
-template void launch_jacobi<double>(const SvdTask*, int, double, int*, size_t, hipStream_t);
-template void launch_svd_wave<float>(const SvdTask*, int, double, double, int*, size_t, hipStream_t);
-template void launch_svd_wave<double>(const SvdTask*, int, double, double, int*, size_t, hipStream_t);
-template void launch_core_left<float>(const SvdTask*, int, int, int, size_t, unsigned long long*, hipStream_t);
-template void launch_core_left<double>(const SvdTask*, int, int, int, size_t, unsigned long long*, hipStream_t);
+#define ACR_SVD_INST(T)                                                                                     \
+  template void launch_qrcp<T>(const SvdTask*, int, double, size_t, hipStream_t);                           \
+  template void launch_jacobi<T>(const SvdTask*, int, double, int*, size_t, hipStream_t);                   \
+  template void launch_svd_block<T>(const SvdTask*, int, double, double, int*, size_t, hipStream_t);        \
+  template void launch_svd_wave<T>(const SvdTask*, int, double, double, int*, size_t, hipStream_t);         \
+  template void launch_core_left<T>(const SvdTask*, int, int, int, size_t, unsigned long long*, hipStream_t);
+ACR_SVD_INST(float)
+ACR_SVD_INST(double)
+#undef ACR_SVD_INST
 
 }  // namespace acr
