@@ -45,8 +45,13 @@ typedef enum {
 } acr_status_t;
 
 typedef enum {
-  ACR_PREC_FP64 = 0,  /* factors stored and applied in FP64                              */
-  ACR_PREC_FP32 = 1   /* factors in FP32 (QR / products FP32, Jacobi SVD sweeps FP64)   */
+  ACR_PREC_FP64 = 0,           /* factors stored and applied in FP64                              */
+  ACR_PREC_FP32 = 1,           /* factors in FP32 (QR / products FP32, Jacobi SVD sweeps FP64)   */
+  ACR_PREC_FP32_BF16LEAF = 2,  /* as FP32, but the dense leaf x leaf products of the factorisation */
+                               /* run on BF16 matrix-core inputs: each operand panel of a 64 x 64  */
+                               /* output tile is scaled by a power of two (largest magnitude into */
+                               /* [0.5, 1)), rounded to nearest even, accumulated in FP32          */
+  ACR_PREC_FP32_FP16LEAF = 3   /* the same with FP16 inputs                                        */
 } acr_precision_t;
 
 typedef struct {

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libacr.so")
 _LIB = None
 
-PREC = {"fp64": 0, "fp32": 1}
+PREC = {"fp64": 0, "fp32": 1, "fp32_bf16leaf": 2, "fp32_fp16leaf": 3}
 STATUS = {0: "success", 1: "invalid value", 2: "out of memory", 3: "HIP error",
           4: "singular", 5: "rank capacity", 6: "not converged", 7: "not supported"}
 

@@ -662,6 +662,7 @@ FactorBase* make_factor(const acr_options_t* o, const double* coef_in, hipStream
   al.release = o->release;
   al.ctx = o->alloc_ctx;
   f->ex.init(s, al);
+  f->ex.leaf_lowp = o->precision == ACR_PREC_FP32_BF16LEAF ? 1 : (o->precision == ACR_PREC_FP32_FP16LEAF ? 2 : 0);
   f->grid = Grid{o->nx, o->ny, o->nplanes};
   f->persist.init(&f->ex, size_t(32) << 20);
   f->refine_mem.init(&f->ex, size_t(64) << 20);
@@ -876,7 +877,7 @@ bool valid_opts(const acr_options_t* o) {
   if (o->nx < 1 || o->ny < 1 || o->nplanes < 1 || o->leaf < 1) return false;
   if (!(o->eps >= 0.0) || !std::isfinite(o->eps)) return false;
   if (o->max_rank < 0) return false;
-  if (o->precision != ACR_PREC_FP64 && o->precision != ACR_PREC_FP32) return false;
+  if (o->precision < ACR_PREC_FP64 || o->precision > ACR_PREC_FP32_FP16LEAF) return false;
   if ((o->alloc == nullptr) != (o->release == nullptr)) return false;
   if (!(o->inner_eps_ratio >= 0.0)) return false;
   if ((int64_t)o->nx * o->ny > (int64_t)1 << 28) return false;
@@ -900,8 +901,8 @@ acr_status_t acr_factor(const acr_options_t* opt, const double* coef, hipStream_
   if (out) *out = nullptr;
   if (!out || !coef || !valid_opts(opt)) return ACR_ERROR_INVALID_VALUE;
   return guarded([&]() -> acr_status_t {
-    FactorBase* f = opt->precision == ACR_PREC_FP32 ? make_factor<float>(opt, coef, stream)
-                                                     : make_factor<double>(opt, coef, stream);
+    FactorBase* f = opt->precision == ACR_PREC_FP64 ? make_factor<double>(opt, coef, stream)
+                                                     : make_factor<float>(opt, coef, stream);
     *out = new acr_factor_s{f};
     return ACR_SUCCESS;
   });

@@ -1,0 +1,262 @@
+// Batched GEMM on the CDNA4 matrix cores: C = alpha op(A) op(B) + beta C over a
+// list of independent problems (every block product of one hierarchical depth
+// across all planes of a reduction level goes into one launch).
+//
+// Each workgroup (4 wavefronts) computes one 64 x 64 output tile; wavefront w
+// owns the 32 x 32 quadrant (w & 1, w >> 1).  The matrix cores compute the
+// transposed quadrant (B-panel columns as the first operand), so that
+// consecutive lanes hold consecutive rows of the column-major C and the
+// stores coalesce.  K advances in blocks staged through LDS, converted to the
+// matrix-core input type on the way in:
+//   FP64 data            v_mfma_f64_16x16x4_f64   (2 x 2 per wavefront)
+//   FP32 data            v_mfma_f32_32x32x2_f32
+//   FP32 data, 16-bit    v_mfma_f32_32x32x16_{bf16,f16}: the A row panel and
+//                        the B column panel of the tile are scaled by powers of
+//                        two that bring their largest magnitude into [0.5, 1),
+//                        rounded to nearest even, accumulated in FP32, and the
+//                        scales are removed exactly when C is written.
+// Operand / accumulator lane layouts (64 lanes, lane l):
+//   32x32xK: A[i = l % 32][k = kb * (l / 32) + 0..kb-1], B[k ...][j = l % 32],
+//            D[v] = C[8 (v / 4) + 4 (l / 32) + v % 4][l % 32]  (v = 0..15)
+//   16x16x4: A[i = l % 16][k = l / 16], B[k = l / 16][j = l % 16],
+//            D[v] = C[l / 16 + 4 v][l % 16]  (v = 0..3)
+#include <cmath>
+
+#include "kern.h"
+
+namespace acr {
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <class T>
+__device__ inline T load_a(const GemmTask& t, const T* A, int i, int k) {
+  return (i < t.m && k < t.k) ? (t.ta ? A[k + (int64_t)i * t.lda] : A[i + (int64_t)k * t.lda]) : T(0);
+}
+template <class T>
+__device__ inline T load_b(const GemmTask& t, const T* B, int k, int j) {
+  return (j < t.n && k < t.k) ? (t.tb ? B[j + (int64_t)k * t.ldb] : B[k + (int64_t)j * t.ldb]) : T(0);
+}
+
+__device__ inline void tile_of(const GemmTask& t, int local, int& row0, int& col0) {
+  const int ntn = (t.n + 63) >> 6;
+  row0 = (local / ntn) * 64;
+  col0 = (local % ntn) * 64;
+}
+
+// C(i, j) of the tile = alpha * v + beta * C(i, j)
+template <class T>
+__device__ inline void store_tile(const GemmTask& t, int row0, int col0, int i, int j, T v) {
+  const int gi = row0 + i, gj = col0 + j;
+  if (gi >= t.m || gj >= t.n) return;
+  T* c = static_cast<T*>(t.C) + gi + (int64_t)gj * t.ldc;
+  T r = T(t.alpha) * v;
+  if (t.beta != 0.0) r += T(t.beta) * *c;
+  *c = r;
+}
+
+// FP32 data, FP32 matrix cores.
+__global__ __launch_bounds__(256) void k_gemm_f32(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_task,
+                                                  const int* __restrict__ first_tile) {
+  constexpr int KB = 16;
+  const int ti = tile_task[blockIdx.x];
+  const GemmTask t = tasks[ti];
+  int row0, col0;
+  tile_of(t, blockIdx.x - first_tile[ti], row0, col0);
+  __shared__ float As[KB][64 + 4];
+  __shared__ float Bs[KB][64 + 4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+  const float* A = static_cast<const float*>(t.A);
+  const float* B = static_cast<const float*>(t.B);
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  for (int k0 = 0; k0 < t.k; k0 += KB) {
+    for (int e = tid; e < 64 * KB; e += 256) {
+      int i, kk;
+      if (!t.ta) { i = e & 63; kk = e >> 6; } else { kk = e % KB; i = e / KB; }
+      As[kk][i] = load_a(t, A, row0 + i, k0 + kk);
+      int j, k2;
+      if (!t.tb) { k2 = e % KB; j = e / KB; } else { j = e & 63; k2 = e >> 6; }
+      Bs[k2][j] = load_b(t, B, k0 + k2, col0 + j);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KB; kk += 2) {
+      const float a = As[kk + (lane >> 5)][wr + (lane & 31)];
+      const float b = Bs[kk + (lane >> 5)][wc + (lane & 31)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b, a, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v)
+    store_tile<float>(t, row0, col0, wr + (lane & 31), wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), acc[v]);
+}
+
+// FP64 data, FP64 matrix cores.
+__global__ __launch_bounds__(256) void k_gemm_f64(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_task,
+                                                  const int* __restrict__ first_tile) {
+  constexpr int KB = 16;
+  const int ti = tile_task[blockIdx.x];
+  const GemmTask t = tasks[ti];
+  int row0, col0;
+  tile_of(t, blockIdx.x - first_tile[ti], row0, col0);
+  __shared__ double As[KB][64 + 2];
+  __shared__ double Bs[KB][64 + 2];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+  const double* A = static_cast<const double*>(t.A);
+  const double* B = static_cast<const double*>(t.B);
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.0;
+  for (int k0 = 0; k0 < t.k; k0 += KB) {
+    for (int e = tid; e < 64 * KB; e += 256) {
+      int i, kk;
+      if (!t.ta) { i = e & 63; kk = e >> 6; } else { kk = e % KB; i = e / KB; }
+      As[kk][i] = load_a(t, A, row0 + i, k0 + kk);
+      int j, k2;
+      if (!t.tb) { k2 = e % KB; j = e / KB; } else { j = e & 63; k2 = e >> 6; }
+      Bs[k2][j] = load_b(t, B, k0 + k2, col0 + j);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KB; kk += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        a[s] = As[kk + (lane >> 4)][wr + 16 * s + (lane & 15)];
+        b[s] = Bs[kk + (lane >> 4)][wc + 16 * s + (lane & 15)];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[y], a[x], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        store_tile<double>(t, row0, col0, wr + 16 * x + (lane & 15), wc + 16 * y + (lane >> 4) + 4 * v, acc[x][y][v]);
+}
+
+template <class H> struct Mfma16;
+template <> struct Mfma16<__bf16> {
+  typedef bf16x8 V;
+  static __device__ inline f32x16 run(V a, V b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
+};
+template <> struct Mfma16<_Float16> {
+  typedef f16x8 V;
+  static __device__ inline f32x16 run(V a, V b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0); }
+};
+
+// power of two s with max * s in [0.5, 1) (1 for an all-zero panel)
+__device__ inline float panel_scale(float mx) {
+  if (!(mx > 0.f) || !isfinite(mx)) return 1.f;
+  int e;
+  (void)frexpf(mx, &e);
+  return ldexpf(1.f, -e);
+}
+
+// FP32 data through 16-bit matrix-core inputs with per-panel scaling.
+template <class H>
+__global__ __launch_bounds__(256) void k_gemm_lowp(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_task,
+                                                   const int* __restrict__ first_tile) {
+  constexpr int KB = 32;
+  const int ti = tile_task[blockIdx.x];
+  const GemmTask t = tasks[ti];
+  int row0, col0;
+  tile_of(t, blockIdx.x - first_tile[ti], row0, col0);
+  // operands stored k-contiguous so that each lane reads its 8 k values at once
+  __shared__ __attribute__((aligned(16))) H As[64][KB + 8];
+  __shared__ __attribute__((aligned(16))) H Bs[64][KB + 8];
+  __shared__ float red[2][4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+  const float* A = static_cast<const float*>(t.A);
+  const float* B = static_cast<const float*>(t.B);
+  // panel maxima: rows row0.. of op(A) and columns col0.. of op(B) over all k
+  float ma = 0.f, mb = 0.f;
+  for (int e = tid; e < 64 * t.k; e += 256) {
+    int i, kk;
+    if (!t.ta) { i = e & 63; kk = e >> 6; } else { kk = e % t.k; i = e / t.k; }
+    ma = fmaxf(ma, fabsf(load_a(t, A, row0 + i, kk)));
+    int j, k2;
+    if (!t.tb) { k2 = e % t.k; j = e / t.k; } else { j = e & 63; k2 = e >> 6; }
+    mb = fmaxf(mb, fabsf(load_b(t, B, k2, col0 + j)));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ma = fmaxf(ma, __shfl_xor(ma, off, 64));
+    mb = fmaxf(mb, __shfl_xor(mb, off, 64));
+  }
+  if (lane == 0) { red[0][w] = ma; red[1][w] = mb; }
+  __syncthreads();
+  ma = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
+  mb = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
+  const float sa = panel_scale(ma), sb = panel_scale(mb);
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  typedef typename Mfma16<H>::V V;
+  for (int k0 = 0; k0 < t.k; k0 += KB) {
+    for (int e = tid; e < 64 * KB; e += 256) {
+      int i, kk;
+      if (!t.ta) { i = e & 63; kk = e >> 6; } else { kk = e % KB; i = e / KB; }
+      As[i][kk] = H(load_a(t, A, row0 + i, k0 + kk) * sa);
+      int j, k2;
+      if (!t.tb) { k2 = e % KB; j = e / KB; } else { j = e & 63; k2 = e >> 6; }
+      Bs[j][k2] = H(load_b(t, B, k0 + k2, col0 + j) * sb);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KB; kk += 16) {
+      const V a = *reinterpret_cast<const V*>(&As[wr + (lane & 31)][kk + 8 * (lane >> 5)]);
+      const V b = *reinterpret_cast<const V*>(&Bs[wc + (lane & 31)][kk + 8 * (lane >> 5)]);
+      acc = Mfma16<H>::run(b, a, acc);
+    }
+    __syncthreads();
+  }
+  const double inv = 1.0 / ((double)sa * (double)sb);   // a power of two: exact
+#pragma unroll
+  for (int v = 0; v < 16; ++v)
+    store_tile<float>(t, row0, col0, wr + (lane & 31), wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3),
+                      (float)((double)acc[v] * inv));
+}
+
+}  // namespace
+
+template <>
+void launch_gemm_mfma<float>(const GemmTask* d_tasks, const int* d_tile_task, const int* d_first_tile, int ntiles,
+                             int lowp, hipStream_t s) {
+  if (ntiles <= 0) return;
+  if (lowp == 1)
+    hipLaunchKernelGGL(k_gemm_lowp<__bf16>, dim3(ntiles), dim3(256), 0, s, d_tasks, d_tile_task, d_first_tile);
+  else if (lowp == 2)
+    hipLaunchKernelGGL(k_gemm_lowp<_Float16>, dim3(ntiles), dim3(256), 0, s, d_tasks, d_tile_task, d_first_tile);
+  else
+    hipLaunchKernelGGL(k_gemm_f32, dim3(ntiles), dim3(256), 0, s, d_tasks, d_tile_task, d_first_tile);
+}
+
+template <>
+void launch_gemm_mfma<double>(const GemmTask* d_tasks, const int* d_tile_task, const int* d_first_tile, int ntiles,
+                              int lowp, hipStream_t s) {
+  (void)lowp;
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_gemm_f64, dim3(ntiles), dim3(256), 0, s, d_tasks, d_tile_task, d_first_tile);
+}
+
+}  // namespace acr

@@ -23,7 +23,7 @@ namespace {
 template <class T>
 GemmTask gt(const T* A, int64_t lda, int ta, const T* B, int64_t ldb, int tb, T* C, int64_t ldc, int m, int n,
             int k, double alpha, double beta) {
-  GemmTask g;
+  GemmTask g{};
   g.A = A; g.B = B; g.C = C;
   g.lda = lda; g.ldb = ldb; g.ldc = ldc;
   g.m = m; g.n = n; g.k = k;
@@ -683,6 +683,7 @@ void hodlr_product(Exec& ex, const Tree& tr, const std::vector<ProdJob<T>>& jobs
       for (int s = 0; s < nseg(L); ++s) {
         const int n = tr.sz[L][s];
         lg.push_back(gt<T>(j->A->leaf[s], n, 0, j->B->leaf[s], n, 0, j->C->leaf[s], n, n, n, n, j->alpha, 0.0));
+        lg.back().lowp = ex.leaf_lowp;
       }
     }
     ex.gemm<T>(lg);

@@ -19,6 +19,7 @@ struct GemmTask {
   int m, n, k;
   int ta, tb;
   double alpha, beta;
+  int lowp;   // FP32 data only: 1 = BF16, 2 = FP16 matrix-core inputs with panel scaling
 };
 
 // dst = alpha * diag(rs) * src * diag(cs) (+ dst if accumulate); rs / cs may be
@@ -156,8 +157,10 @@ struct LeafTask {
 
 enum : int { FLAG_SINGULAR = 0, FLAG_RANK = 1, FLAG_NONFINITE = 2, FLAG_INVALID = 3, NFLAGS = 8 };
 
-template <class T> void launch_gemm(const GemmTask* d_tasks, const int* d_tile_task,
-                                    const int* d_first_tile, int ntiles, hipStream_t s);
+// matrix-core GEMM over the same tile map; lowp selects the 16-bit input
+// variant for FP32 data (0 = FP32 / FP64 inputs)
+template <class T> void launch_gemm_mfma(const GemmTask* d_tasks, const int* d_tile_task, const int* d_first_tile,
+                                         int ntiles, int lowp, hipStream_t s);
 template <class T> void launch_copy(const CopyTask* d_tasks, int ntasks, hipStream_t s);
 template <class T> void launch_inverse(const InvTask* d_tasks, int ntasks, int max_s,
                                        int* d_flags, hipStream_t s);

@@ -2,12 +2,12 @@
 //
 // One launch processes a list of independent small problems (all blocks of one
 // hierarchical depth over all planes of a cyclic-reduction level).  Kernels:
-//   k_gemm     tiled C = alpha op(A) op(B) + beta C over a tile map
 //   k_copy     scaled copies / accumulations of sub-matrices (stack assembly)
 //   k_inverse  Gauss-Jordan inverse with partial pivoting (dense leaves,
 //              the small capacitance matrices of the HODLR inverse)
 // The compression kernels (Householder QR, pivoted-QR + Jacobi SVD, apply-Q,
-// Gram path) live in la_lds.hip, svd.hip and gram.hip.
+// Gram path) live in la_lds.hip, svd.hip and gram.hip; the matrix-core GEMM
+// in gemm_mfma.hip.
 #include "kern.h"
 
 #include <cfloat>
@@ -33,80 +33,6 @@ __device__ inline double block_sum(double v, double* red) {
   double s = red[0] + red[1] + red[2] + red[3];
   __syncthreads();
   return s;
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_gemm(const GemmTask* __restrict__ tasks,
-                                              const int* __restrict__ tile_task,
-                                              const int* __restrict__ first_tile) {
-  const int tile = blockIdx.x;
-  const int ti = tile_task[tile];
-  const GemmTask t = tasks[ti];
-  const int local = tile - first_tile[ti];
-  const int ntn = (t.n + 63) >> 6;
-  const int row0 = (local / ntn) * 64, col0 = (local % ntn) * 64;
-  __shared__ T As[16][65];
-  __shared__ T Bs[16][65];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  T acc[4][4];
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[p][q] = T(0);
-  const T* A = static_cast<const T*>(t.A);
-  const T* B = static_cast<const T*>(t.B);
-  for (int k0 = 0; k0 < t.k; k0 += 16) {
-    for (int e = tid; e < 1024; e += 256) {
-      int i, kk;
-      if (!t.ta) { i = e & 63; kk = e >> 6; } else { kk = e & 15; i = e >> 4; }
-      const int gi = row0 + i, gk = k0 + kk;
-      T v = T(0);
-      if (gi < t.m && gk < t.k)
-        v = t.ta ? A[gk + (int64_t)gi * t.lda] : A[gi + (int64_t)gk * t.lda];
-      As[kk][i] = v;
-    }
-    for (int e = tid; e < 1024; e += 256) {
-      int j, kk;
-      if (!t.tb) { kk = e & 15; j = e >> 4; } else { j = e & 63; kk = e >> 6; }
-      const int gj = col0 + j, gk = k0 + kk;
-      T v = T(0);
-      if (gj < t.n && gk < t.k)
-        v = t.tb ? B[gj + (int64_t)gk * t.ldb] : B[gk + (int64_t)gj * t.ldb];
-      Bs[kk][j] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      T a[4], b[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = As[kk][tx + 16 * q];
-        b[q] = Bs[kk][ty + 16 * q];
-      }
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
-    }
-    __syncthreads();
-  }
-  T* C = static_cast<T*>(t.C);
-  const T alpha = T(t.alpha), beta = T(t.beta);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int gj = col0 + ty + 16 * q;
-    if (gj >= t.n) continue;
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int gi = row0 + tx + 16 * p;
-      if (gi >= t.m) continue;
-      T* c = C + gi + (int64_t)gj * t.ldc;
-      T v = alpha * acc[p][q];
-      if (t.beta != 0.0) v += beta * *c;
-      *c = v;
-    }
-  }
 }
 
 template <class T>
@@ -224,12 +150,6 @@ __global__ __launch_bounds__(256) void k_inverse(const InvTask* __restrict__ tas
 
 }  // namespace
 
-template <class T>
-void launch_gemm(const GemmTask* d_tasks, const int* d_tile_task, const int* d_first_tile, int ntiles,
-                 hipStream_t s) {
-  if (ntiles <= 0) return;
-  hipLaunchKernelGGL(k_gemm<T>, dim3(ntiles), dim3(256), 0, s, d_tasks, d_tile_task, d_first_tile);
-}
 
 template <class T>
 void launch_copy(const CopyTask* d_tasks, int ntasks, hipStream_t s) {
@@ -250,7 +170,6 @@ void launch_inverse(const InvTask* d_tasks, int ntasks, int max_s, int* d_flags,
 }
 
 #define ACR_INST(T)                                                                              \
-  template void launch_gemm<T>(const GemmTask*, const int*, const int*, int, hipStream_t);      \
   template void launch_copy<T>(const CopyTask*, int, hipStream_t);                              \
   template void launch_inverse<T>(const InvTask*, int, int, int*, hipStream_t);
 

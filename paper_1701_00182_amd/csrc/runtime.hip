@@ -420,26 +420,33 @@ template <class T> void Exec::gemm(const std::vector<GemmTask>& t) {
       if ((x.tb ? x.ldb < x.n : x.ldb < x.k) && x.n * x.k > 0) throw Failure(ST_HIP, "bounds check: gemm ldb");
       if (x.ldc < x.m && x.m * x.n > 0) throw Failure(ST_HIP, "bounds check: gemm ldc");
     }
-  std::vector<int> first(t.size()), tile_task;
-  int nt = 0;
-  for (size_t i = 0; i < t.size(); ++i) {
-    first[i] = nt;
-    const int tiles = ((t[i].m + 63) / 64) * ((t[i].n + 63) / 64);
-    for (int j = 0; j < tiles; ++j) tile_task.push_back((int)i);
-    nt += tiles;
-    flops_gemm += 2.0 * t[i].m * t[i].n * t[i].k;
+  // one launch per input kind: native-precision matrix cores, or 16-bit inputs
+  for (int mode = 0; mode < 3; ++mode) {
+    std::vector<int> first, tile_task;
+    std::vector<GemmTask> sel;
+    int nt = 0;
+    for (const GemmTask& x : t) {
+      const int m = (sizeof(T) == 4) ? x.lowp : 0;
+      if (m != mode) continue;
+      first.push_back(nt);
+      const int tiles = ((x.m + 63) / 64) * ((x.n + 63) / 64);
+      for (int j = 0; j < tiles; ++j) tile_task.push_back((int)sel.size());
+      nt += tiles;
+      sel.push_back(x);
+      flops_gemm += 2.0 * x.m * x.n * (double)x.k;
+    }
+    if (nt == 0) continue;
+    Work w;
+    w.cls = mode == 0 ? "gemm" : (mode == 1 ? "gemm_bf16" : "gemm_f16");
+    for (auto& x : sel) {
+      w.flops += 2.0 * x.m * x.n * (double)x.k;
+      w.bytes += sizeof(T) * ((double)x.m * x.k + (double)x.k * x.n + (double)x.m * x.n * (x.beta != 0.0 ? 2 : 1));
+    }
+    const GemmTask* dt = upload(sel);
+    const int* dtt = upload(tile_task);
+    const int* dft = upload(first);
+    submit([=](hipStream_t s) { launch_gemm_mfma<T>(dt, dtt, dft, nt, mode, s); }, w);
   }
-  if (nt == 0) return;
-  Work w;
-  w.cls = "gemm";
-  for (auto& x : t) {
-    w.flops += 2.0 * x.m * x.n * (double)x.k;
-    w.bytes += sizeof(T) * ((double)x.m * x.k + (double)x.k * x.n + (double)x.m * x.n * (x.beta != 0.0 ? 2 : 1));
-  }
-  const GemmTask* dt = upload(t);
-  const int* dtt = upload(tile_task);
-  const int* dft = upload(first);
-  submit([=](hipStream_t s) { launch_gemm<T>(dt, dtt, dft, nt, s); }, w);
 }
 
 template <class T> void Exec::copy(const std::vector<CopyTask>& t) {

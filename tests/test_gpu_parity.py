@@ -132,3 +132,50 @@ def test_gram_compression_matches_householder(prec, monkeypatch):
     assert np.linalg.norm(xg - xh) <= 20 * eps * np.linalg.norm(xh)
     fg.free()
     fh.free()
+
+
+@pytest.mark.parametrize("leaf", [16, 64])
+@pytest.mark.parametrize("prec", ["fp32_bf16leaf", "fp32_fp16leaf"])
+def test_lowp_leaf_variant(prec, leaf):
+    """Leaf x leaf products on 16-bit matrix-core inputs (power-of-two panel
+    scaling, FP32 accumulation): unit roundoff 2^-9 (BF16) / 2^-12 (FP16) is
+    below the truncation level, so the unrefined residual stays within the
+    FP32 form's bound, and FP64 GMRES still reaches 1e-10."""
+    n, eps = 16, 1e-2
+    coef = problem("convdiff", n)
+    f = rhs_normal(n ** 3)
+    A = operator_from_coef(coef)
+    fr = _gpu(coef, eps=eps, leaf=leaf, precision="fp32")
+    fl = _gpu(coef, eps=eps, leaf=leaf, precision=prec)
+    r32 = float(relres(A, _solve(fr, f), f))
+    rlo = float(relres(A, _solve(fl, f), f))
+    assert rlo <= max(2.0 * r32, 5 * eps)
+    x, info = fl.solve_refined(torch.from_numpy(f).to(DEV), tol=1e-10, method="gmres")
+    assert info["converged"] and float(relres(A, x.cpu().numpy(), f)) <= 1e-10
+    fr.free()
+    fl.free()
+
+
+@pytest.fixture(scope="module")
+def convdiff20_oracle():
+    n, leaf, eps = 20, 32, 1e-6
+    coef = problem("convdiff", n)
+    f = rhs_normal(n ** 3)
+    return coef, f, OracleACR(coef, leaf, eps).solve(f)
+
+
+@pytest.mark.parametrize("fused", ["0", "65536", "160000"])
+def test_svd_paths_agree(fused, monkeypatch, convdiff20_oracle):
+    """The one-workgroup core SVD and the two-kernel path (pivoted QR, then
+    Jacobi on W^T) compute the same truncation: all thresholds give solutions
+    within the eps bound of the oracle's (n = 20, FP64; eps small enough that
+    stacked cores exceed 64 columns)."""
+    leaf, eps = 32, 1e-6
+    coef, f, xo = convdiff20_oracle
+    A = operator_from_coef(coef)
+    monkeypatch.setenv("ACR_FUSED_LDS", fused)
+    fac = _gpu(coef, eps=eps, leaf=leaf, precision="fp64")
+    x = _solve(fac, f)
+    assert float(relres(A, x, f)) <= 5 * eps
+    assert np.linalg.norm(x - xo) <= 20 * eps * np.linalg.norm(xo)
+    fac.free()
