@@ -1,20 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark of the ACR hot path on one MI355X.
 
-One step = factorisation (FP32 factors, eps = 1e-2, HODLR leaf 64) of the
-n = 128 nonsymmetric convection-diffusion operator (N = 2,097,152) plus an FP64
-right-preconditioned GMRES(30) solve to relative residual 1e-8 with the
-factorisation as preconditioner.  Inputs are synthetic (seeded lognormal
-kappa, random divergence-free velocity at cell Peclet 1, f ~ N(0, 1)) and are
-resident in device memory before the timed region.  The plain FP64 form
-(FP64 factors, same eps and GMRES) is measured once beside it.
+Default workload (the headline line): one step = factorisation (FP32 factors,
+eps = 1e-2, HODLR leaf 64) of the n = 128 nonsymmetric convection-diffusion
+operator (N = 2,097,152) plus an FP64 right-preconditioned GMRES(30) solve to
+relative residual 1e-8 with the factorisation as preconditioner.  Inputs are
+synthetic (seeded lognormal kappa, random divergence-free velocity at cell
+Peclet 1, f ~ N(0, 1)) and resident in device memory before the timed region.
+The plain FP64 form and the BF16-leaf variant (same eps and GMRES) are measured
+once beside it, and the oracle is timed on the host on a bounded sample.
+
+Other workloads (--workload, one JSON line each, not the headline):
+  helmholtz_mrhs  indefinite Helmholtz n = 64, FP32 factors, eps = 1e-3, 256
+                  right-hand sides in one graph-replayed solve
+  poisson_ir      Poisson n = 64, eps = 1e-4: plain FP64 factor + solve against
+                  FP32 factors + FP64 iterative refinement to 1e-8
+  gradient        Poisson n = 64: loss and gradient with respect to all N nodal
+                  kappa values (forward refined solve, adjoint transpose solve,
+                  per-cell gradient kernel)
+  copy_calibration  a plain 1 GiB device copy (reference dispatch for scaling
+                  the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)
 
 Prints one JSON line; progress goes to stderr.
 """
 import argparse
 import ctypes
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -24,10 +36,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "factor+solve s & solve DOF/s at n=128; FP32+IR vs FP64 at rel resid 1e-8"
-# MI355X published peaks
-PEAK = {"hbm": 8000.0, "fp64": 78.6, "fp32": 157.3}
+# MI355X published peaks (GB/s, dense TFLOP/s)
+PEAK = {"hbm": 8000.0, "fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
 HBM_CLASSES = ("solve_leaf", "solve_inner", "copy")
-FP64_CLASSES = ("jacobi", "jacobi_lds", "svd_wave", "core_left", "qrcp", "qrcp_lds", "pchol", "gram", "wtilde")
+FP64_CLASSES = ("jacobi", "jacobi_lds", "svd_wave", "svd_block", "core_left", "qrcp", "qrcp_lds", "pchol", "gram",
+                "wtilde")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
 def log(msg):
@@ -35,8 +49,6 @@ def log(msg):
 
 
 def kernel_table(lib):
-    from paper_1701_00182_amd import lib as _lib  # noqa: F401
-
     class KT(ctypes.Structure):
         _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                     ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -49,32 +61,74 @@ def kernel_table(lib):
              "bytes": a.bytes} for a in arr[:n]]
 
 
-def roofline(table, precision):
+def set_timing(lib, level):
+    lib.acr_set_kernel_timing.argtypes = [ctypes.c_int32]
+    lib.acr_set_kernel_timing.restype = None
+    lib.acr_set_kernel_timing(level)
+
+
+def class_bound(name, precision):
+    """(bound, peak, unit) of a kernel class."""
+    if name in HBM_CLASSES:
+        return "hbm", PEAK["hbm"], "GB/s"
+    if name == "gemm":
+        return "mfma", PEAK["fp64"] if precision == "fp64" else PEAK["fp32"], "TFLOP/s"
+    if name == "gemm_bf16":
+        return "mfma", PEAK["bf16"], "TFLOP/s"
+    if name == "gemm_f16":
+        return "mfma", PEAK["fp16"], "TFLOP/s"
+    fp64 = name in FP64_CLASSES or precision == "fp64"
+    return "alu", PEAK["fp64"] if fp64 else PEAK["fp32"], "TFLOP/s"
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3 PMC
+    summary, if that summary was taken on the current source of the kernel."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)["classes"][cls]
+        with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != rec["sha256"]:
+                return None
+        return rec["bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def roofline(table, precision, steps):
     if not table:
         return None
     dom = max(table, key=lambda r: r["ms"])
-    avg_s = dom["ms"] / 1e3 / max(dom["launches"], 1)
-    name = dom["name"]
-    if name in HBM_CLASSES:
-        bound, unit = "hbm", "GB/s"
-        achieved = dom["bytes"] / max(dom["launches"], 1) / avg_s / 1e9
-        peak = PEAK["hbm"]
-    else:
-        bound, unit = "alu", "TFLOP/s"
-        achieved = dom["flops"] / max(dom["launches"], 1) / avg_s / 1e12
-        fp64 = name in FP64_CLASSES or precision == "fp64"
-        peak = PEAK["fp64"] if fp64 else PEAK["fp32"]
-    return {"bound": bound, "kernel": name, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None,
-            "avg_launch_ms": avg_s * 1e3, "launches_per_step": None,
-            "algorithmic_per_launch": (dom["bytes"] if bound == "hbm" else dom["flops"]) / max(dom["launches"], 1),
+    nl = max(dom["launches"], 1)
+    avg_s = dom["ms"] / 1e3 / nl
+    bound, peak, unit = class_bound(dom["name"], precision)
+    per_launch = (dom["bytes"] if bound == "hbm" else dom["flops"]) / nl
+    achieved = per_launch / avg_s / (1e9 if bound == "hbm" else 1e12)
+    return {"bound": bound, "kernel": dom["name"], "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": measured_traffic(dom["name"]),
+            "avg_launch_ms": avg_s * 1e3, "launches_per_step": dom["launches"] / max(steps, 1),
+            "algorithmic_per_launch": per_launch,
             "share_of_kernel_time": dom["ms"] / sum(r["ms"] for r in table)}
 
 
+def brief_table(table, precision, k=10):
+    out = []
+    for r in sorted(table, key=lambda r: -r["ms"])[:k]:
+        bound, peak, unit = class_bound(r["name"], precision)
+        rate = (r["bytes"] / 1e9 if bound == "hbm" else r["flops"] / 1e12) / max(r["ms"] / 1e3, 1e-12)
+        out.append({"class": r["name"], "launches": r["launches"], "ms": round(r["ms"], 3), "bound": bound,
+                    "achieved": rate, "unit": unit, "frac": rate / peak})
+    return out
+
+
+# ----------------------------------------------------------------- headline
 def run_form(acr, coef_d, b, args, precision, timed_steps, warmup):
     import torch
     N = b.numel()
     rec = []
+    st = None
+    t_apply = float("nan")
+    x = None
     for step in range(warmup + timed_steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -105,10 +159,11 @@ def run_form(acr, coef_d, b, args, precision, timed_steps, warmup):
     info = rec[-1][2]
     return {"t_factor_s": tf, "t_solve_s": ts, "factor_plus_solve_s": tf + ts,
             "solve_dof_per_s": N / ts, "apply_ms": t_apply * 1e3, "apply_dof_per_s": N / t_apply,
-            "iterations": info["iterations"], "relres": info["relres"],
+            "iterations": info["iterations"], "converged": info["converged"], "relres": info["relres"],
             "relres_before_refinement": info["relres0"], "max_rank": st["max_rank"],
             "avg_rank": st["avg_rank"], "factor_GB": st["factor_bytes"] / 1e9,
-            "solve_bytes_GB": st["solve_bytes"] / 1e9}, x
+            "solve_bytes_GB": st["solve_bytes"] / 1e9, "flops_svd": st["flops_svd"],
+            "flops_gemm": st["flops_gemm"]}, x
 
 
 def cpu_baseline(n, eps, leaf):
@@ -134,32 +189,8 @@ def cpu_baseline(n, eps, leaf):
                       f"(N={n ** 3}), eps={eps}, leaf {leaf}, FP64 dense plane blocks; {dt:.2f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=128)
-    ap.add_argument("--eps", type=float, default=1e-2)
-    ap.add_argument("--leaf", type=int, default=64)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--no-fp64-form", action="store_true")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=24)
-    args = ap.parse_args()
-    ws = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or ws != 1:
-        print("bench.py measures one GPU only: the cyclic-reduction hot path is built and timed on a "
-              "single MI355X (multi-GPU plane distribution is design-only); run with --gpus 1",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-    import paper_1701_00182_amd as acr
+def headline(args, torch, acr):
     from workloads import problem, rhs_normal
-
     n = args.n
     N = n ** 3
     log(f"building inputs n={n}")
@@ -169,23 +200,16 @@ def main():
     coef_d = torch.from_numpy(coef).to(dev)
     b = torch.from_numpy(f).to(dev)
     torch.cuda.synchronize()
-
     L = acr.lib()
-    L.acr_set_kernel_timing.argtypes = [ctypes.c_int32]
-    L.acr_set_kernel_timing.restype = None
-    # warmup without instrumentation, timed steps with per-kernel event timing
     log("warmup")
     run_form(acr, coef_d, b, args, args.precision, 0, args.warmup)
-    L.acr_set_kernel_timing(1)
+    # timed steps; the factorisation kernels carry HIP events on their stream
+    set_timing(L, 1)
     log("timed steps")
     main_form, x_main = run_form(acr, coef_d, b, args, args.precision, args.steps, 0)
-    L.acr_set_kernel_timing(0)
+    set_timing(L, 0)
     table = kernel_table(L)
-    rl = roofline(table, args.precision)
-    if rl is not None:
-        per_step = next(r for r in table if r["name"] == rl["kernel"])["launches"] / args.steps
-        rl["launches_per_step"] = per_step
-
+    rl = roofline(table, args.precision, args.steps)
     out = {
         "metric": METRIC,
         "value": N / main_form["factor_plus_solve_s"],
@@ -197,7 +221,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"convection-diffusion n={n} (N={N}), lognormal kappa, divergence-free "
                                f"velocity at cell Peclet 1, eps={args.eps}, HODLR leaf {args.leaf}, "
@@ -206,7 +230,7 @@ def main():
                    "refinement": "fp64 gmres(30)", "tol": args.tol},
         "value_definition": "N / (t_factor + t_solve) for one step (whole job, inputs resident)",
         "form": main_form,
-        "kernel_table": sorted(table, key=lambda r: -r["ms"])[:8],
+        "kernel_table": brief_table(table, args.precision),
         "roofline": rl,
     }
     if not args.no_fp64_form and args.precision != "fp64":
@@ -215,10 +239,192 @@ def main():
         f64["error_vs_fp64_form"] = 0.0
         out["fp64_form"] = f64
         out["form"]["error_vs_fp64_form"] = float(torch.linalg.norm(x_main - x64) / torch.linalg.norm(x64))
+        if not args.no_lowp_form:
+            log("bf16-leaf form")
+            fb, xb = run_form(acr, coef_d, b, args, "fp32_bf16leaf", 1, 0)
+            fb["error_vs_fp64_form"] = float(torch.linalg.norm(xb - x64) / torch.linalg.norm(x64))
+            out["bf16leaf_form"] = fb
     if not args.no_cpu_baseline:
         log(f"cpu baseline (oracle) n={args.cpu_n}")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.eps, args.leaf)
-    print(json.dumps(out), flush=True)
+    return out
+
+
+# ------------------------------------------------------- other workloads
+def helmholtz_mrhs(args, torch, acr):
+    from workloads import problem, rhs_normal
+    n, nrhs, eps, leaf = 64, args.nrhs, 1e-3, 64
+    N = n ** 3
+    coef_d = torch.from_numpy(problem("helmholtz", n)).cuda()
+    B = torch.from_numpy(rhs_normal(N, nrhs=nrhs).T.copy()).cuda()   # (nrhs, N): one row per right-hand side
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fac = acr.Factor(coef_d, eps=eps, leaf=leaf, precision="fp32")
+    torch.cuda.synchronize()
+    t_factor = time.perf_counter() - t0
+    X = fac.solve(B)                       # records the plan and its graph
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        fac.solve(B, out=X)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fac.solve(B, out=X)
+    torch.cuda.synchronize()
+    t_solve = (time.perf_counter() - t0) / args.steps
+    L = acr.lib()
+    set_timing(L, 2)                        # one instrumented replay for the kernel table
+    fac.solve(B, out=X)
+    torch.cuda.synchronize()
+    set_timing(L, 0)
+    table = kernel_table(L)
+    rel = []
+    for j in range(nrhs):
+        r = fac.residual(X[j].contiguous(), B[j].contiguous())
+        rel.append(float(r.norm() / B[j].norm()))
+    rel.sort()
+    x0, info = fac.solve_refined(B[0].contiguous(), tol=1e-8, method="gmres", maxit=300, raise_on_fail=False)
+    st = fac.stats()
+    fac.free()
+    log(f"helmholtz n={n}: factor {t_factor:.3f}s, {nrhs}-RHS solve {t_solve * 1e3:.2f} ms, "
+        f"GMRES rhs0 {info['iterations']} its relres {info['relres']:.2e}")
+    return {
+        "metric": f"multi-RHS solve DOF/s (Helmholtz n={n}, {nrhs} RHS, FP32 factors)",
+        "value": N * nrhs / t_solve, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_solve * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"indefinite Helmholtz n={n} (N={N}), c = 1 + 0.3 smoothed noise, 10 points per "
+                               f"wavelength, eps={eps}, leaf {leaf}, FP32 factors, {nrhs} RHS per graph replay",
+                   "n": n, "nrhs": nrhs, "eps": eps, "leaf": leaf},
+        "t_factor_s": t_factor, "max_rank": st["max_rank"], "factor_GB": st["factor_bytes"] / 1e9,
+        "relres_unrefined": {"min": rel[0], "median": rel[len(rel) // 2], "max": rel[-1]},
+        "gmres_rhs0": {"iterations": info["iterations"], "converged": info["converged"], "relres": info["relres"]},
+        "kernel_table": brief_table(table, "fp32"),
+        "roofline": roofline(table, "fp32", 1),
+    }
+
+
+def poisson_ir(args, torch, acr):
+    from workloads import problem, rhs_normal
+    n, eps, leaf = 64, 1e-4, 64
+    N = n ** 3
+    coef_d = torch.from_numpy(problem("poisson", n)).cuda()
+    b = torch.from_numpy(rhs_normal(N)).cuda()
+    res = {}
+    for prec in ("fp64", "fp32"):
+        for step in range(args.warmup + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fac = acr.Factor(coef_d, eps=eps, leaf=leaf, precision=prec)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if prec == "fp64":
+                x = fac.solve(b)
+                torch.cuda.synchronize()
+                r = fac.residual(x, b)
+                info = {"iterations": 0, "relres": float(r.norm() / b.norm())}
+            else:
+                x, info = fac.solve_refined(b, tol=1e-8, method="ir", maxit=100)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            fac.free()
+        res[prec] = {"t_factor_s": t1 - t0, "t_solve_s": t2 - t1, "factor_plus_solve_s": t2 - t0,
+                     "iterations": info["iterations"], "relres": info["relres"], "x": x}
+        log(f"poisson n={n} {prec}: factor {t1 - t0:.3f}s solve {t2 - t1:.3f}s relres {info['relres']:.2e}")
+    err = float(torch.linalg.norm(res["fp32"]["x"] - res["fp64"]["x"]) / torch.linalg.norm(res["fp64"]["x"]))
+    for v in res.values():
+        v.pop("x")
+    return {
+        "metric": f"factor+solve DOF/s (Poisson n={n}, FP32 factors + FP64 IR to 1e-8)",
+        "value": N / res["fp32"]["factor_plus_solve_s"], "unit": "DOF/s", "n_gpus": 1, "steps": 1,
+        "warmup": args.warmup, "ms_per_step": res["fp32"]["factor_plus_solve_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"variable-coefficient Poisson n={n} (N={N}), lognormal kappa, eps={eps}, "
+                               f"leaf {leaf}", "n": n, "eps": eps, "leaf": leaf},
+        "fp32_ir": res["fp32"], "fp64_plain": res["fp64"], "fp32_ir_vs_fp64_plain_rel_diff": err,
+    }
+
+
+def gradient(args, torch, acr):
+    from workloads import lognormal_kappa, rhs_normal, observation_cells, observation_noise
+    n = 64
+    N = n ** 3
+    kappa = torch.from_numpy(lognormal_kappa(n)).cuda()
+    f = torch.from_numpy(rhs_normal(N)).cuda()
+    obs = torch.from_numpy(observation_cells(N, count=512)).cuda()
+    data = torch.from_numpy(observation_noise(512)).cuda()   # a data vector of the right shape
+    times = []
+    gnorm = float("nan")
+    for step in range(args.warmup + args.steps):
+        k = kappa.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = acr.ACRSolve.apply(k, f, 1e-4, 64, "fp32", 1e-12)
+        r = u[obs] - data
+        loss = 0.5 * (r * r).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if step >= args.warmup:
+            times.append(dt)
+        gnorm = float(k.grad.norm())
+        log(f"gradient step {step}: {dt:.3f}s loss {float(loss.detach()):.4e}")
+    t = sum(times) / len(times)
+    return {
+        "metric": f"loss+gradient DOF/s (Poisson n={n}, all nodal kappa)",
+        "value": N / t, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Poisson n={n} (N={N}), lognormal kappa, 512 observation cells, eps=1e-4, "
+                               f"FP32 factors, forward and adjoint solves refined to 1e-12", "n": n},
+        "grad_norm": gnorm,
+    }
+
+
+def copy_calibration(torch):
+    """A plain device copy of exactly 1 GiB, the reference dispatch for scaling
+    rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"copy_bytes": src.numel() * 4, "dispatches": 3}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="convdiff",
+                    choices=["convdiff", "helmholtz_mrhs", "poisson_ir", "gradient", "copy_calibration"])
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--eps", type=float, default=1e-2)
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp32_bf16leaf", "fp32_fp16leaf"])
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--nrhs", type=int, default=256)
+    ap.add_argument("--no-fp64-form", action="store_true")
+    ap.add_argument("--no-lowp-form", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=22)
+    args = ap.parse_args()
+    ws = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or ws != 1:
+        print("bench.py measures one GPU only: the cyclic-reduction hot path is built and timed on a "
+              "single MI355X (multi-GPU plane distribution is design-only); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.workload == "copy_calibration":
+        print(json.dumps(copy_calibration(torch)), flush=True)
+        return
+    import paper_1701_00182_amd as acr
+    fn = {"convdiff": headline, "helmholtz_mrhs": helmholtz_mrhs, "poisson_ir": poisson_ir,
+          "gradient": gradient}[args.workload]
+    print(json.dumps(fn(args, torch, acr)), flush=True)
 
 
 if __name__ == "__main__":

@@ -174,16 +174,17 @@ acr_status_t acr_kappa_gradient(int32_t nx, int32_t ny, int32_t nz, const double
 const char* acr_status_string(acr_status_t s);
 
 /*
- * Per-kernel-class timing (instrumentation).  acr_set_kernel_timing(1) clears
- * the process-wide table and makes every later factorisation launch record a
- * pair of HIP events on its stream around each kernel; the table accumulates,
- * per kernel class, launches, event-measured milliseconds and the algorithmic
- * flops and bytes of those launches (counted from the task shapes and, for
- * the Jacobi sweeps, from a device counter of pair visits).  Solves replayed
- * from a graph are not timed; acr_set_kernel_timing(0) stops recording and keeps
- * the table.  acr_get_kernel_times copies up to cap entries
- * and returns the number of classes.  Host-side tables; not thread-safe with
- * concurrent factorisations.
+ * Per-kernel-class timing (instrumentation).  acr_set_kernel_timing(level)
+ * with level >= 1 clears the process-wide table and makes every later
+ * factorisation launch record a pair of HIP events on its stream around each
+ * kernel; the table accumulates, per kernel class, launches, event-measured
+ * milliseconds and the algorithmic flops and bytes of those launches (counted
+ * from the task shapes and, for the SVD kernels, from device counters).  At
+ * level 1 solves still replay their graph and are not timed; at level 2 each
+ * solve is replayed launch by launch with events (and synchronises its
+ * stream).  acr_set_kernel_timing(0) stops recording and keeps the table.
+ * acr_get_kernel_times copies up to cap entries and returns the number of
+ * classes.  Host-side tables; not thread-safe with concurrent factorisations.
  */
 typedef struct {
   char name[32];
@@ -192,7 +193,7 @@ typedef struct {
   double flops;
   double bytes;
 } acr_kernel_time_t;
-void acr_set_kernel_timing(int32_t enable);
+void acr_set_kernel_timing(int32_t level);
 int32_t acr_get_kernel_times(acr_kernel_time_t* out, int32_t cap);
 
 /* Text of the last failure on the calling host thread ("" if none); valid until the next call. */

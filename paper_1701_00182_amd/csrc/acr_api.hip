@@ -30,7 +30,7 @@ namespace acr {
 namespace {
 
 struct Plan {
-  std::vector<std::function<void(hipStream_t)>> launches;
+  std::vector<Exec::Recorded> launches;
   Arena mem;
   void* W = nullptr;    // permuted right-hand sides / reduced right-hand sides
   void* Ub = nullptr;   // solution per plane, cluster order
@@ -572,10 +572,17 @@ template <class T> struct FactorT : FactorBase {
   }
 
   void run_plan(Plan* pl, hipStream_t s) {
+    if (solve_timing_enabled()) {
+      // per-kernel timing table: eager replay with events around every launch
+      ex.replay_timed(pl->launches, s);
+      hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+      ex.resolve_timings();
+      return;
+    }
     if (use_graph && !pl->exec && !pl->graph) {
       bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
       if (ok) {
-        for (auto& f : pl->launches) f(s);
+        for (auto& r : pl->launches) r.f(s);
         ok = hipStreamEndCapture(s, &pl->graph) == hipSuccess && pl->graph;
         if (ok) ok = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) == hipSuccess;
       }
@@ -590,7 +597,7 @@ template <class T> struct FactorT : FactorBase {
     if (pl->exec) {
       hip_check(hipGraphLaunch(pl->exec, s), "hipGraphLaunch");
     } else {
-      for (auto& f : pl->launches) f(s);
+      for (auto& r : pl->launches) r.f(s);
       hip_check(hipGetLastError(), "solve launch");
     }
   }
@@ -1005,7 +1012,7 @@ const char* acr_status_string(acr_status_t s) {
 
 const char* acr_last_error_message(void) { return g_last_error.c_str(); }
 
-void acr_set_kernel_timing(int32_t enable) { acr::timing_enable(enable != 0); }
+void acr_set_kernel_timing(int32_t level) { acr::timing_enable(level); }
 
 int32_t acr_get_kernel_times(acr_kernel_time_t* out, int32_t cap) {
   return acr::timing_report(out, cap < 0 ? 0 : cap);

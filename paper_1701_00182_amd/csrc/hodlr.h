@@ -81,8 +81,9 @@ struct Work {
 };
 
 // Process-wide switch and table of per-kernel-class event timings.
-void timing_enable(bool on);
+void timing_enable(int level);   // 0 off, 1 factorisation launches, 2 also solve replays
 bool timing_enabled();
+bool solve_timing_enabled();
 int timing_report(acr_kernel_time_t* out, int cap);
 
 // Launch executor: uploads task arrays and launches, or records the launches
@@ -94,7 +95,11 @@ class Exec {
   int* d_flags = nullptr;
   int* h_flags = nullptr;
   unsigned long long* d_svd_flops = nullptr;   // SVD flops counted by the kernels
-  std::vector<std::function<void(hipStream_t)>>* rec = nullptr;
+  struct Recorded {
+    std::function<void(hipStream_t)> f;
+    Work w;
+  };
+  std::vector<Recorded>* rec = nullptr;
   Arena* rec_arena = nullptr;
 
   void init(hipStream_t s, const Allocator& a);
@@ -109,6 +114,9 @@ class Exec {
     return static_cast<const Task*>(upload_bytes(v.data(), v.size() * sizeof(Task)));
   }
   void submit(std::function<void(hipStream_t)> f, const Work& w = Work{});
+  // Eager replay of recorded launches on `s`, each timed like a submitted one
+  // (used instead of the graph while the per-kernel timing table is on).
+  void replay_timed(const std::vector<Recorded>& r, hipStream_t s);
   unsigned long long* counter_slot();   // zeroed device counter for one launch
   void resolve_timings();               // after the stream is idle
   void read_flags(int out[NFLAGS]);

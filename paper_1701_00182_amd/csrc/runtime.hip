@@ -126,6 +126,7 @@ size_t Arena::reserved() const {
 namespace {
 std::mutex g_time_mu;
 bool g_timing = false;
+int g_timing_level = 0;
 struct TimeAcc { long launches = 0; double ms = 0, flops = 0, bytes = 0; };
 std::map<std::string, TimeAcc>& time_table() {
   static std::map<std::string, TimeAcc> t;
@@ -134,12 +135,14 @@ std::map<std::string, TimeAcc>& time_table() {
 constexpr size_t kCounters = 1 << 16;
 }  // namespace
 
-void timing_enable(bool on) {
+void timing_enable(int level) {
   std::lock_guard<std::mutex> lk(g_time_mu);
-  if (on) time_table().clear();   // a new measurement starts; disabling keeps the table
-  g_timing = on;
+  if (level > 0) time_table().clear();   // a new measurement starts; disabling keeps the table
+  g_timing = level > 0;
+  g_timing_level = level > 0 ? level : 0;
 }
 bool timing_enabled() { return g_timing; }
+bool solve_timing_enabled() { return g_timing_level >= 2; }
 
 int timing_report(acr_kernel_time_t* out, int cap) {
   std::lock_guard<std::mutex> lk(g_time_mu);
@@ -345,10 +348,26 @@ const void* Exec::upload_bytes(const void* src, size_t bytes) {
   return d;
 }
 
+void Exec::replay_timed(const std::vector<Recorded>& r, hipStream_t s) {
+  hipStream_t saved = stream;
+  stream = s;
+  std::vector<Recorded>* saved_rec = rec;
+  const long saved_launches = launches;
+  rec = nullptr;
+  for (const Recorded& x : r) {
+    Work w = x.w;
+    if (w.counter) w.counter = nullptr;   // device counters belong to the recording
+    submit(x.f, w);
+  }
+  rec = saved_rec;
+  stream = saved;
+  launches = saved_launches;
+}
+
 void Exec::submit(std::function<void(hipStream_t)> f, const Work& w) {
   ++launches;
   if (rec) {
-    rec->push_back(f);
+    rec->push_back(Recorded{f, w});
     return;
   }
   const bool timed = g_timing && w.cls;
