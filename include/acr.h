@@ -65,9 +65,14 @@ typedef struct {
   void* (*alloc)(size_t bytes, void* ctx, hipStream_t stream);
   void (*release)(void* ptr, void* ctx, hipStream_t stream);
   void* alloc_ctx;
+  int32_t svd_fused_lds;     /* cores whose pivoted QR + Jacobi working set needs at most this  */
+                             /* many bytes of LDS run both in one workgroup; 0 = default      */
+                             /* (64 KiB), < 0 = never (two-kernel path); capped at the LDS    */
+                             /* budget.  Tuned by acr_autotune.                                */
 } acr_options_t;
 
-/* Fills defaults: eps 1e-6, leaf 64, FP64, no rank cap, no allocator. Grid fields 0. */
+/* Fills defaults: eps 1e-6, leaf 64, FP64, no rank cap, no allocator, default SVD
+ * dispatch. Grid fields 0. */
 void acr_options_default(acr_options_t* opt);
 
 /*
@@ -172,6 +177,32 @@ acr_status_t acr_kappa_gradient(int32_t nx, int32_t ny, int32_t nz, const double
                                 const double* lam, double* grad, hipStream_t stream);
 
 const char* acr_status_string(acr_status_t s);
+
+/*
+ * Autotuner for the leaf size and the core-SVD dispatch (the tile-size knobs of
+ * the factorisation).  It factorises a sample of the operator -- its first
+ * sample_planes planes (0 -> 16, capped at nplanes), with the coupling out of
+ * the last sample plane dropped -- for every candidate leaf size in
+ * {32, 64, 128, opt->leaf} (those that fit the plane) and every SVD dispatch in
+ * {never, 64 KiB, LDS budget}, times factorisation + 16 single-RHS solves
+ * (the cost of a refined solve), and returns the fastest pair.  All other
+ * options are taken from opt.  coef: DEVICE, as for acr_factor (read only).
+ * cache_path (may be NULL): a text file of one result per line keyed by
+ * (nx, ny, sample planes, eps, precision, max_rank, inner_eps_ratio); a
+ * matching line is returned without measuring (from_cache = 1), a new result
+ * is appended.  Synchronises `stream`; allocates and frees its own scratch.
+ * Errors: ACR_ERROR_INVALID_VALUE for bad options or pointers; the status of
+ * the last failure if no candidate factorises.
+ */
+typedef struct {
+  int32_t leaf;            /* chosen leaf size                                   */
+  int32_t svd_fused_lds;   /* chosen acr_options_t.svd_fused_lds                 */
+  double seconds;          /* sample factorisation + 16 solves with that choice  */
+  int32_t tried;           /* candidates measured (0 when read from the cache)   */
+  int32_t from_cache;      /* 1 if the result came from cache_path                */
+} acr_tune_result_t;
+acr_status_t acr_autotune(const acr_options_t* opt, const double* coef, int32_t sample_planes,
+                          const char* cache_path, hipStream_t stream, acr_tune_result_t* out);
 
 /*
  * Per-kernel-class timing (instrumentation).  acr_set_kernel_timing(level)

@@ -34,7 +34,13 @@ class Options(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nplanes", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("leaf", ctypes.c_int32), ("max_rank", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_eps_ratio", ctypes.c_double),
-                ("alloc", ctypes.c_void_p), ("release", ctypes.c_void_p), ("alloc_ctx", ctypes.c_void_p)]
+                ("alloc", ctypes.c_void_p), ("release", ctypes.c_void_p), ("alloc_ctx", ctypes.c_void_p),
+                ("svd_fused_lds", ctypes.c_int32)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_int32), ("svd_fused_lds", ctypes.c_int32), ("seconds", ctypes.c_double),
+                ("tried", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -92,6 +98,9 @@ def lib():
         L.acr_kappa_gradient.restype = ctypes.c_int
         L.acr_status_string.argtypes = [ctypes.c_int]
         L.acr_status_string.restype = ctypes.c_char_p
+        L.acr_autotune.argtypes = [ctypes.POINTER(Options), vp, i32, ctypes.c_char_p, vp,
+                                    ctypes.POINTER(TuneResult)]
+        L.acr_autotune.restype = ctypes.c_int
         L.acr_last_error_message.argtypes = []
         L.acr_last_error_message.restype = ctypes.c_char_p
         _LIB = L
@@ -127,7 +136,8 @@ def _rhs_view(b, N):
 class Factor:
     """ACR factorisation of a 7-point operator given as coef[7, nz, ny, nx] (FP64, CUDA)."""
 
-    def __init__(self, coef, eps=1e-6, leaf=64, precision="fp64", max_rank=0, inner_eps_ratio=1.0):
+    def __init__(self, coef, eps=1e-6, leaf=64, precision="fp64", max_rank=0, inner_eps_ratio=1.0,
+                 svd_fused_lds=0):
         L = lib()
         if coef.dim() != 4 or coef.shape[0] != 7:
             raise ValueError("coef must be shaped (7, nz, ny, nx)")
@@ -139,6 +149,7 @@ class Factor:
         o.eps, o.leaf, o.max_rank = float(eps), int(leaf), int(max_rank)
         o.precision = PREC[precision]
         o.inner_eps_ratio = float(inner_eps_ratio)
+        o.svd_fused_lds = int(svd_fused_lds)
         h = ctypes.c_void_p()
         _check(L.acr_factor(ctypes.byref(o), ctypes.c_void_p(coef.data_ptr()), _stream(), ctypes.byref(h)),
                "acr_factor")
@@ -226,6 +237,30 @@ def kappa_gradient(kappa, u, lam):
                                     ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(g.data_ptr()), _stream()),
            "acr_kappa_gradient")
     return g
+
+
+def autotune(coef, eps=1e-6, precision="fp64", leaf=64, sample_planes=16, cache=None, max_rank=0,
+             inner_eps_ratio=1.0):
+    """Leaf size and core-SVD dispatch picked by timing a sample of the operator
+    (acr_autotune); returns a dict with leaf, svd_fused_lds, seconds, tried,
+    from_cache.  Pass leaf / svd_fused_lds on to Factor."""
+    if coef.dim() != 4 or coef.shape[0] != 7:
+        raise ValueError("coef must be shaped (7, nz, ny, nx)")
+    _dev_f64(coef, "coef")
+    L = lib()
+    _, nz, ny, nx = coef.shape
+    o = Options()
+    L.acr_options_default(ctypes.byref(o))
+    o.nx, o.ny, o.nplanes = nx, ny, nz
+    o.eps, o.leaf, o.max_rank = float(eps), int(leaf), int(max_rank)
+    o.precision = PREC[precision]
+    o.inner_eps_ratio = float(inner_eps_ratio)
+    r = TuneResult()
+    path = None if cache is None else os.fsencode(cache)
+    _check(L.acr_autotune(ctypes.byref(o), ctypes.c_void_p(coef.data_ptr()), int(sample_planes), path, _stream(),
+                          ctypes.byref(r)), "acr_autotune")
+    return {"leaf": r.leaf, "svd_fused_lds": r.svd_fused_lds, "seconds": r.seconds, "tried": r.tried,
+            "from_cache": bool(r.from_cache)}
 
 
 class ACRSolve(torch.autograd.Function):

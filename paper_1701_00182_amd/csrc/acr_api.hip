@@ -670,6 +670,11 @@ FactorBase* make_factor(const acr_options_t* o, const double* coef_in, hipStream
   al.ctx = o->alloc_ctx;
   f->ex.init(s, al);
   f->ex.leaf_lowp = o->precision == ACR_PREC_FP32_BF16LEAF ? 1 : (o->precision == ACR_PREC_FP32_FP16LEAF ? 2 : 0);
+  // core-SVD dispatch: the option, overridden by ACR_FUSED_LDS (bytes) when set
+  if (o->svd_fused_lds < 0) f->ex.fused_lds = 0;
+  else if (o->svd_fused_lds > 0) f->ex.fused_lds = std::min<size_t>((size_t)o->svd_fused_lds, kLdsBudget);
+  if (const char* fu = std::getenv("ACR_FUSED_LDS"))
+    f->ex.fused_lds = std::min<size_t>(std::strtoull(fu, nullptr, 10), kLdsBudget);
   f->grid = Grid{o->nx, o->ny, o->nplanes};
   f->persist.init(&f->ex, size_t(32) << 20);
   f->refine_mem.init(&f->ex, size_t(64) << 20);
@@ -891,6 +896,120 @@ bool valid_opts(const acr_options_t* o) {
   return true;
 }
 
+std::string tune_key(const acr_options_t* o, int sp) {
+  char k[256];
+  std::snprintf(k, sizeof(k), "nx=%d ny=%d planes=%d eps=%.17g precision=%d max_rank=%d inner=%.17g", o->nx, o->ny,
+                sp, o->eps, o->precision, o->max_rank, o->inner_eps_ratio > 0 ? o->inner_eps_ratio : 1.0);
+  return k;
+}
+
+bool tune_cache_read(const char* path, const std::string& key, acr_tune_result_t* out) {
+  if (!path) return false;
+  std::FILE* fh = std::fopen(path, "r");
+  if (!fh) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), fh)) {
+    const char* bar = std::strchr(line, '|');
+    if (!bar || std::string(line, bar - line) != key) continue;
+    int leaf = 0, fl = 0;
+    double sec = 0;
+    if (std::sscanf(bar + 1, " leaf=%d svd_fused_lds=%d seconds=%lf", &leaf, &fl, &sec) == 3 && leaf > 0) {
+      out->leaf = leaf;
+      out->svd_fused_lds = fl;
+      out->seconds = sec;
+      found = true;   // the last matching line wins
+    }
+  }
+  std::fclose(fh);
+  return found;
+}
+
+void tune_cache_append(const char* path, const std::string& key, const acr_tune_result_t* r) {
+  if (!path) return;
+  std::FILE* fh = std::fopen(path, "a");
+  if (!fh) return;
+  std::fprintf(fh, "%s| leaf=%d svd_fused_lds=%d seconds=%.6f\n", key.c_str(), r->leaf, r->svd_fused_lds,
+               r->seconds);
+  std::fclose(fh);
+}
+
+acr_status_t autotune_impl(const acr_options_t* opt, const double* coef, int sample_planes, const char* cache_path,
+                           hipStream_t stream, acr_tune_result_t* out) {
+  const int sp = std::max(1, std::min(sample_planes > 0 ? sample_planes : 16, opt->nplanes));
+  const std::string key = tune_key(opt, sp);
+  std::memset(out, 0, sizeof(*out));
+  if (tune_cache_read(cache_path, key, out)) {
+    out->from_cache = 1;
+    return ACR_SUCCESS;
+  }
+  const int64_t M = (int64_t)opt->nx * opt->ny, Ns = M * sp, Nf = M * opt->nplanes;
+  // sample operator: the first sp planes of every stencil slot; the coupling
+  // from the last sample plane to the next (slot T) is dropped
+  double* d = nullptr;
+  hip_check(hipMalloc((void**)&d, sizeof(double) * (7 * Ns + 2 * Ns)), "hipMalloc(autotune)");
+  struct Free {
+    double* p;
+    ~Free() { (void)hipFree(p); }
+  } guard{d};
+  double* dcoef = d;
+  double* db = d + 7 * Ns;
+  double* dx = db + Ns;
+  for (int s = 0; s < 7; ++s)
+    hip_check(hipMemcpyAsync(dcoef + s * Ns, coef + s * Nf, sizeof(double) * Ns, hipMemcpyDeviceToDevice, stream),
+              "hipMemcpyAsync(sample)");
+  hip_check(hipMemsetAsync(dcoef + 6 * Ns + (sp - 1) * M, 0, sizeof(double) * M, stream), "hipMemsetAsync(sample)");
+  // right-hand side: the sample's diagonal coefficients (any non-zero vector)
+  hip_check(hipMemcpyAsync(db, dcoef, sizeof(double) * Ns, hipMemcpyDeviceToDevice, stream), "hipMemcpyAsync(rhs)");
+  std::vector<int> leaves;
+  for (int l : {32, 64, 128, opt->leaf})
+    if (l >= 1 && l <= M && std::find(leaves.begin(), leaves.end(), l) == leaves.end()) leaves.push_back(l);
+  const int fused[] = {-1, (int)kFusedLds, (int)kLdsBudget};
+  acr_options_t o = *opt;
+  o.nplanes = sp;
+  auto trial = [&](int leaf, int fl) -> double {
+    o.leaf = leaf;
+    o.svd_fused_lds = fl;
+    hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    const auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<FactorBase> f(o.precision == ACR_PREC_FP64 ? make_factor<double>(&o, dcoef, stream)
+                                                               : make_factor<float>(&o, dcoef, stream));
+    f->solve(1, db, Ns, dx, Ns, false, stream);   // records the plan
+    hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    const auto t1 = std::chrono::steady_clock::now();
+    for (int i = 0; i < 16; ++i) f->solve(1, db, Ns, dx, Ns, false, stream);
+    hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    const auto t2 = std::chrono::steady_clock::now();
+    return std::chrono::duration<double>(t1 - t0).count() + std::chrono::duration<double>(t2 - t1).count();
+  };
+  acr_status_t last = ACR_ERROR_NOT_SUPPORTED;
+  bool warm = false;
+  double best = 0;
+  for (int leaf : leaves)
+    for (int fl : fused) {
+      try {
+        if (!warm) {
+          (void)trial(leaf, fl);   // first-use costs (code objects, LDS attributes) out of the timing
+          warm = true;
+        }
+        const double t = trial(leaf, fl);
+        ++out->tried;
+        if (out->leaf == 0 || t < best) {
+          best = t;
+          out->leaf = leaf;
+          out->svd_fused_lds = fl;
+          out->seconds = t;
+        }
+      } catch (const Failure& e) {
+        last = to_status(e.status);
+        g_last_error = e.what();
+      }
+    }
+  if (out->leaf == 0) return last;
+  tune_cache_append(cache_path, key, out);
+  return ACR_SUCCESS;
+}
+
 }  // namespace
 
 extern "C" {
@@ -954,6 +1073,12 @@ acr_status_t acr_get_stats(acr_handle_t h, acr_stats_t* st) {
     h->impl->stats(st);
     return ACR_SUCCESS;
   });
+}
+
+acr_status_t acr_autotune(const acr_options_t* opt, const double* coef, int32_t sample_planes,
+                          const char* cache_path, hipStream_t stream, acr_tune_result_t* out) {
+  if (!out || !coef || !valid_opts(opt) || sample_planes < 0) return ACR_ERROR_INVALID_VALUE;
+  return guarded([&]() -> acr_status_t { return autotune_impl(opt, coef, sample_planes, cache_path, stream, out); });
 }
 
 acr_status_t acr_residual(acr_handle_t h, const double* x, const double* b, double* r, int32_t transpose,

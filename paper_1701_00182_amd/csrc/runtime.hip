@@ -253,8 +253,7 @@ void Exec::init(hipStream_t s, const Allocator& a) {
   trace = tr && tr[0] == '1';
   const char* gm = std::getenv("ACR_GRAM");
   gram_ok = !(gm && gm[0] == '0');
-  const char* fu = std::getenv("ACR_FUSED_LDS");
-  fused_lds = fu ? std::min<size_t>(std::strtoull(fu, nullptr, 10), kLdsBudget) : kFusedLds;
+  fused_lds = kFusedLds;
   stream = s;
   al = a;
   ring_bytes_ = size_t(64) << 20;

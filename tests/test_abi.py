@@ -54,3 +54,8 @@ def test_null_arguments_rejected():
     assert L.acr_solve_transpose(None, 1, None, 0, None, 0, None) == 1
     L.acr_free(None)
     assert L.acr_status_string(0) == b"success"
+    r = acr.TuneResult()
+    assert L.acr_autotune(None, ctypes.c_void_p(16), 8, None, None, ctypes.byref(r)) == 1
+    assert L.acr_autotune(ctypes.byref(_opts()), None, 8, None, None, ctypes.byref(r)) == 1
+    assert L.acr_autotune(ctypes.byref(_opts()), ctypes.c_void_p(16), -1, None, None, ctypes.byref(r)) == 1
+    assert L.acr_autotune(ctypes.byref(_opts()), ctypes.c_void_p(16), 8, None, None, None) == 1
