@@ -236,9 +236,13 @@ __device__ inline void tournament_pair(int pi, int round, int ne, int& ia, int& 
 // index i * st), handled by the G lanes of a group (gl = lane in group): the
 // three inner products, the rotation and its application.  Vectors of up to
 // G * kJR elements stay in registers between the products and the update.
-// Returns whether a rotation was applied.
+// Returns whether a rotation was applied; cmax takes the pair's |cos| (the
+// normalised inner product before the rotation).
 constexpr int kJR = 12;
-__device__ inline bool jacobi_pair(double* xa, double* xb, int st, int len, int G, int gl, double tol) {
+__device__ inline double pair_cos(double al, double be, double ga) {
+  return al > 0.0 && be > 0.0 ? fabs(ga) / sqrt(al * be) : 0.0;
+}
+__device__ inline bool jacobi_pair(double* xa, double* xb, int st, int len, int G, int gl, double tol, double& cmax) {
   double al = 0.0, be = 0.0, ga = 0.0;
   if (len <= G * kJR) {
     double xr[kJR], yr[kJR];
@@ -257,6 +261,7 @@ __device__ inline bool jacobi_pair(double* xa, double* xb, int st, int len, int 
     al = gsum2(al, G);
     be = gsum2(be, G);
     ga = gsum2(ga, G);
+    cmax = fmax(cmax, pair_cos(al, be, ga));
     double cs, sn;
     if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
 #pragma unroll
@@ -278,6 +283,7 @@ __device__ inline bool jacobi_pair(double* xa, double* xb, int st, int len, int 
   al = gsum2(al, G);
   be = gsum2(be, G);
   ga = gsum2(ga, G);
+  cmax = fmax(cmax, pair_cos(al, be, ga));
   double cs, sn;
   if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
   for (int i = gl; i < len; i += G) {
@@ -308,19 +314,27 @@ __device__ int jacobi_svd(double* V, int64_t vs, int64_t es, int n, int len, con
   const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   const double tol = fmax(1e-15, 2.3e-16 * (double)len);
   sweeps = 0;
+  // Sweeps end when one applies no rotation, or when its largest |cos| was at
+  // most sqrt(tol): convergence is quadratic there, so the pairs are left
+  // orthogonal to about tol and the confirming sweep is skipped.
+  const double stop_cos = sqrt(tol);
   for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
     ++sweeps;
     int rot = 0;
+    double cmax = 0.0;
     for (int round = 0; round < ne - 1; ++round) {
       for (int pi = gi; pi < npairs; pi += groups) {
         int ia, ib;
         tournament_pair(pi, round, ne, ia, ib);
         if (ib >= n) continue;
-        if (jacobi_pair(V + ia * vs, V + ib * vs, (int)es, len, G, gl, tol)) rot = 1;
+        if (jacobi_pair(V + ia * vs, V + ib * vs, (int)es, len, G, gl, tol, cmax)) rot = 1;
       }
       __syncthreads();
     }
     if (!__syncthreads_or(rot)) break;
+    int dummy = 0;
+    block_argmax<NT>(cmax, dummy, red, redi);
+    if (cmax <= stop_cos) break;
   }
   for (int i = gi; i < n; i += groups) {
     const double* x = V + i * vs;
