@@ -2,7 +2,8 @@
 """Benchmark of the ACR hot path on one MI355X.
 
 Default workload (the headline line): one step = factorisation (FP32 factors,
-eps = 1e-2, HODLR leaf 64) of the n = 128 nonsymmetric convection-diffusion
+eps = 1e-2, HODLR leaf size and core-SVD dispatch picked by the autotuner on an
+8-plane sample before the timed region) of the n = 128 nonsymmetric convection-diffusion
 operator (N = 2,097,152) plus an FP64 right-preconditioned GMRES(30) solve to
 relative residual 1e-8 with the factorisation as preconditioner.  Inputs are
 synthetic (seeded lognormal kappa, random divergence-free velocity at cell
@@ -132,7 +133,8 @@ def run_form(acr, coef_d, b, args, precision, timed_steps, warmup):
     for step in range(warmup + timed_steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        fac = acr.Factor(coef_d, eps=args.eps, leaf=args.leaf, precision=precision)
+        fac = acr.Factor(coef_d, eps=args.eps, leaf=args.leaf, precision=precision,
+                         svd_fused_lds=args.svd_fused_lds)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         x, info = fac.solve_refined(b, tol=args.tol, method="gmres", restart=30, maxit=300)
@@ -201,6 +203,15 @@ def headline(args, torch, acr):
     b = torch.from_numpy(f).to(dev)
     torch.cuda.synchronize()
     L = acr.lib()
+    tune = None
+    if not args.no_autotune:
+        # leaf size and core-SVD dispatch from a sample of the operator (untimed)
+        t0 = time.perf_counter()
+        tune = acr.autotune(coef_d, eps=args.eps, precision=args.precision, leaf=args.leaf,
+                            sample_planes=args.tune_planes)
+        tune["tuning_s"] = time.perf_counter() - t0
+        args.leaf, args.svd_fused_lds = tune["leaf"], tune["svd_fused_lds"]
+        log(f"autotune: leaf {args.leaf}, svd_fused_lds {args.svd_fused_lds} ({tune['tuning_s']:.1f} s)")
     log("warmup")
     run_form(acr, coef_d, b, args, args.precision, 0, args.warmup)
     # timed steps; the factorisation kernels carry HIP events on their stream
@@ -226,8 +237,9 @@ def headline(args, torch, acr):
         "config": {"workload": f"convection-diffusion n={n} (N={N}), lognormal kappa, divergence-free "
                                f"velocity at cell Peclet 1, eps={args.eps}, HODLR leaf {args.leaf}, "
                                f"{args.precision.upper()} factors + FP64 GMRES(30) to {args.tol:g}",
-                   "n": n, "N": N, "eps": args.eps, "leaf": args.leaf, "precision": args.precision,
-                   "refinement": "fp64 gmres(30)", "tol": args.tol},
+                   "n": n, "N": N, "eps": args.eps, "leaf": args.leaf, "svd_fused_lds": args.svd_fused_lds,
+                   "autotune": tune, "precision": args.precision, "refinement": "fp64 gmres(30)",
+                   "tol": args.tol},
         "value_definition": "N / (t_factor + t_solve) for one step (whole job, inputs resident)",
         "form": main_form,
         "kernel_table": brief_table(table, args.precision),
@@ -401,7 +413,10 @@ def main():
                     choices=["convdiff", "helmholtz_mrhs", "poisson_ir", "gradient", "copy_calibration"])
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--eps", type=float, default=1e-2)
-    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--leaf", type=int, default=64, help="leaf size (the autotuner's starting candidate)")
+    ap.add_argument("--svd-fused-lds", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true", help="use --leaf / --svd-fused-lds as given")
+    ap.add_argument("--tune-planes", type=int, default=8)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp32_bf16leaf", "fp32_fp16leaf"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--nrhs", type=int, default=256)

@@ -65,10 +65,10 @@ typedef struct {
   void* (*alloc)(size_t bytes, void* ctx, hipStream_t stream);
   void (*release)(void* ptr, void* ctx, hipStream_t stream);
   void* alloc_ctx;
-  int32_t svd_fused_lds;     /* cores whose pivoted QR + Jacobi working set needs at most this  */
-                             /* many bytes of LDS run both in one workgroup; 0 = default      */
-                             /* (64 KiB), < 0 = never (two-kernel path); capped at the LDS    */
-                             /* budget.  Tuned by acr_autotune.                                */
+  int32_t svd_fused_lds;     /* cores above 64 columns whose pivoted QR + Jacobi working set    */
+                             /* needs at most this many bytes of LDS run both in one          */
+                             /* workgroup; 0 = default (none), < 0 = never; capped at the     */
+                             /* LDS budget.  Tuned by acr_autotune.                            */
 } acr_options_t;
 
 /* Fills defaults: eps 1e-6, leaf 64, FP64, no rank cap, no allocator, default SVD
@@ -184,7 +184,8 @@ const char* acr_status_string(acr_status_t s);
  * sample_planes planes (0 -> 16, capped at nplanes), with the coupling out of
  * the last sample plane dropped -- for every candidate leaf size in
  * {32, 64, 128, opt->leaf} (those that fit the plane) and every SVD dispatch in
- * {never, 64 KiB, LDS budget}, times factorisation + 16 single-RHS solves
+ * {never, 64 KiB, LDS budget} (as svd_fused_lds: -1, 65536, 159744), times
+ * factorisation + 16 single-RHS solves
  * (the cost of a refined solve), and returns the fastest pair.  All other
  * options are taken from opt.  coef: DEVICE, as for acr_factor (read only).
  * cache_path (may be NULL): a text file of one result per line keyed by

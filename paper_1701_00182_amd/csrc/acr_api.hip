@@ -964,7 +964,7 @@ acr_status_t autotune_impl(const acr_options_t* opt, const double* coef, int sam
   std::vector<int> leaves;
   for (int l : {32, 64, 128, opt->leaf})
     if (l >= 1 && l <= M && std::find(leaves.begin(), leaves.end(), l) == leaves.end()) leaves.push_back(l);
-  const int fused[] = {-1, (int)kFusedLds, (int)kLdsBudget};
+  const int fused[] = {-1, 64 * 1024, (int)kLdsBudget};
   acr_options_t o = *opt;
   o.nplanes = sp;
   auto trial = [&](int leaf, int fl) -> double {

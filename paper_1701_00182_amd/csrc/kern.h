@@ -186,9 +186,11 @@ void launch_pchol(const PcholTask* d_tasks, int ntasks, double tol, hipStream_t 
 void launch_materialize_r(const PcholTask* d_tasks, int ntasks, hipStream_t s);
 template <class T> void launch_wtilde(const WtTask* d_tasks, int ntasks, int kc, int nchunks, size_t lds,
                                       hipStream_t s);
+// vec: the 16-byte vector kernels (every task's sizes, leading dimensions and
+// addresses multiples of 16 bytes; no transposed leaf)
 template <class T> void launch_inner(const InnerTask* d_tasks, const int* d_wave_task, const int* d_first_wave,
-                                    int nwaves, hipStream_t s);
-template <class T> void launch_apply_leaf(const LeafTask* d_tasks, int ntasks, hipStream_t s);
+                                    int nwaves, bool vec, hipStream_t s);
+template <class T> void launch_apply_leaf(const LeafTask* d_tasks, int ntasks, bool vec, hipStream_t s);
 constexpr size_t kLdsBudget = 156 * 1024;
 constexpr size_t kSmallLds = 32 * 1024;   // LDS-resident tasks up to this size use 256-thread workgroups
 inline size_t lds_bytes_qr(const QrTask& t, size_t w) { return (size_t)t.m * t.r * w; }
@@ -201,9 +203,10 @@ inline size_t lds_bytes_svd_wave(const SvdTask& t, size_t w) {
   const size_t lc = t.p | 1;
   return (lc * t.q + t.q) * 8 + (size_t)2 * t.q * 4 + (size_t)t.q * t.r * w;
 }
-// one-workgroup cores up to this LDS size (beyond it the Jacobi stage runs on
-// the smaller W^T in a kernel of its own, at higher occupancy)
-constexpr size_t kFusedLds = 64 * 1024;
+// default LDS limit of the one-workgroup path for cores beyond the wavefront
+// size (0: such cores take the two-kernel path, the faster one at the n = 128
+// benchmark shapes; acr_options_t.svd_fused_lds / acr_autotune change it)
+constexpr size_t kFusedLds = 0;
 inline size_t lds_bytes_qrcp(const SvdTask& t) { return ((size_t)(t.p | 1) * t.q + t.q) * 8 + (size_t)t.q * 4; }
 inline size_t lds_bytes_svd_block(const SvdTask& t) {
   const size_t lc = t.p | 1;

@@ -813,10 +813,15 @@ template <class T> void Exec::inner(const std::vector<InnerTask>& t) {
     w.flops += 2.0 * x.rows * x.k * (double)x.c;
     w.bytes += sizeof(T) * ((double)x.rows * x.k + (double)x.rows * x.c + (double)x.k * x.c);
   }
+  constexpr int VW = 16 / sizeof(T);
+  auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  bool vec = true;
+  for (auto& x : t)
+    vec = vec && x.rows % VW == 0 && x.ldv % VW == 0 && x.ldx % VW == 0 && al(x.V) && al(x.x);
   const InnerTask* dt = upload(t);
   const int* dwt = upload(wave_task);
   const int* dfw = upload(first);
-  submit([=](hipStream_t s) { launch_inner<T>(dt, dwt, dfw, nw, s); }, w);
+  submit([=](hipStream_t s) { launch_inner<T>(dt, dwt, dfw, nw, vec, s); }, w);
 }
 
 template <class T> void Exec::apply_leaf(const std::vector<LeafTask>& t) {
@@ -849,9 +854,20 @@ template <class T> void Exec::apply_leaf(const std::vector<LeafTask>& t) {
     }
     w.bytes += sizeof(T) * el;
   }
+  constexpr int VW = 16 / sizeof(T);
+  auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  bool vec = true;
+  for (auto& x : t) {
+    vec = vec && x.n > 0 && x.n % VW == 0 && x.n / VW <= 256 && x.ldy % VW == 0 && al(x.y) && (!x.yin || al(x.yin));
+    for (int q = 0; q < x.nterm && vec; ++q) {
+      const LeafTerm& m = x.term[q];
+      vec = !m.trans && m.ldx % VW == 0 && al(m.x) && (m.diag ? al(m.diag) : al(m.leaf));
+      for (int d = 0; d < m.nd && vec; ++d) vec = m.ldu[d] % VW == 0 && al(m.up[d]);
+    }
+  }
   const LeafTask* dt = upload(t);
   const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_apply_leaf<T>(dt, n, s); }, w);
+  submit([=](hipStream_t s) { launch_apply_leaf<T>(dt, n, vec, s); }, w);
 }
 
 #define ACR_EXEC_INST(T)                                              \
