@@ -3,7 +3,9 @@
 // across all planes of a reduction level goes into one launch).
 //
 // Each workgroup (4 wavefronts) computes one 64 x 64 output tile; wavefront w
-// owns the 32 x 32 quadrant (w & 1, w >> 1).  The matrix cores compute the
+// owns the 32 x 32 quadrant (w & 1, w >> 1).  Operand blocks are loaded with
+// 16-byte vectors into registers one block ahead (the next block's loads are
+// in flight while the current one is multiplied).  The matrix cores compute the
 // transposed quadrant (B-panel columns as the first operand), so that
 // consecutive lanes hold consecutive rows of the column-major C and the
 // stores coalesce.  K advances in blocks staged through LDS, converted to the
@@ -59,33 +61,100 @@ __device__ inline void store_tile(const GemmTask& t, int row0, int col0, int i, 
   *c = r;
 }
 
+// Register-staged operand tile: 64 positions p (rows of op(A) or columns of
+// op(B)) x KB values of k, element (p, k) at base[p * sp + k * sk] with one of
+// sp / sk equal to 1.  Each thread moves NV vectors of VEC consecutive elements
+// along the contiguous dimension (one 16-byte load when aligned and inside the
+// matrix, element loads with zero fill otherwise); the values are held in
+// registers while the previous block is multiplied, then written to LDS.
+template <class T, int KB> struct Stage {
+  static constexpr int VEC = 16 / sizeof(T);
+  static constexpr int NV = 64 * KB / (VEC * 256);
+  T v[NV][VEC];
+
+  __device__ inline void load(const T* base, int64_t sp, int64_t sk, int P, int K, int p0, int k0) {
+    const bool pc = sp == 1;
+#pragma unroll
+    for (int s = 0; s < NV; ++s) {
+      const int e = threadIdx.x + s * 256;
+      int p, k;
+      if (pc) { p = (e % (64 / VEC)) * VEC; k = e / (64 / VEC); }
+      else { k = (e % (KB / VEC)) * VEC; p = e / (KB / VEC); }
+      const int gp = p0 + p, gk = k0 + k;
+      const T* ptr = base + gp * sp + gk * sk;
+      const bool full = pc ? (gp + VEC <= P && gk < K) : (gp < P && gk + VEC <= K);
+      if (full && (((uintptr_t)ptr & 15) == 0)) {
+        typedef T V __attribute__((ext_vector_type(VEC)));
+        const V x = *reinterpret_cast<const V*>(ptr);
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) v[s][u] = x[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) {
+          const int qp = pc ? gp + u : gp, qk = pc ? gk : gk + u;
+          v[s][u] = (qp < P && qk < K) ? base[qp * sp + qk * sk] : T(0);
+        }
+      }
+    }
+  }
+  // into lds[k][p] (row stride LD)
+  template <int LD> __device__ inline void store(T (*lds)[LD], bool pc) const {
+#pragma unroll
+    for (int s = 0; s < NV; ++s) {
+      const int e = threadIdx.x + s * 256;
+      int p, k;
+      if (pc) { p = (e % (64 / VEC)) * VEC; k = e / (64 / VEC); }
+      else { k = (e % (KB / VEC)) * VEC; p = e / (KB / VEC); }
+#pragma unroll
+      for (int u = 0; u < VEC; ++u) {
+        if (pc) lds[k][p + u] = v[s][u];
+        else lds[k + u][p] = v[s][u];
+      }
+    }
+  }
+};
+
+// operand geometry of op(A) (rows p, inner k) and op(B) (columns p, inner k)
+__device__ inline void a_geom(const GemmTask& t, int64_t& sp, int64_t& sk) {
+  if (t.ta) { sp = t.lda; sk = 1; } else { sp = 1; sk = t.lda; }
+}
+__device__ inline void b_geom(const GemmTask& t, int64_t& sp, int64_t& sk) {
+  if (t.tb) { sp = 1; sk = t.ldb; } else { sp = t.ldb; sk = 1; }
+}
+
 // FP32 data, FP32 matrix cores.
 __global__ __launch_bounds__(256) void k_gemm_f32(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_task,
                                                   const int* __restrict__ first_tile) {
-  constexpr int KB = 16;
+  constexpr int KB = 32;
   const int ti = tile_task[blockIdx.x];
   const GemmTask t = tasks[ti];
   int row0, col0;
   tile_of(t, blockIdx.x - first_tile[ti], row0, col0);
   __shared__ float As[KB][64 + 4];
   __shared__ float Bs[KB][64 + 4];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
   const float* A = static_cast<const float*>(t.A);
   const float* B = static_cast<const float*>(t.B);
+  int64_t asp, ask, bsp, bsk;
+  a_geom(t, asp, ask);
+  b_geom(t, bsp, bsk);
   f32x16 acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  Stage<float, KB> sa, sb;
+  if (t.k > 0) {
+    sa.load(A, asp, ask, t.m, t.k, row0, 0);
+    sb.load(B, bsp, bsk, t.n, t.k, col0, 0);
+  }
   for (int k0 = 0; k0 < t.k; k0 += KB) {
-    for (int e = tid; e < 64 * KB; e += 256) {
-      int i, kk;
-      if (!t.ta) { i = e & 63; kk = e >> 6; } else { kk = e % KB; i = e / KB; }
-      As[kk][i] = load_a(t, A, row0 + i, k0 + kk);
-      int j, k2;
-      if (!t.tb) { k2 = e % KB; j = e / KB; } else { j = e & 63; k2 = e >> 6; }
-      Bs[k2][j] = load_b(t, B, k0 + k2, col0 + j);
-    }
+    sa.store(As, asp == 1);
+    sb.store(Bs, bsp == 1);
     __syncthreads();
+    if (k0 + KB < t.k) {   // next block in flight during the products
+      sa.load(A, asp, ask, t.m, t.k, row0, k0 + KB);
+      sb.load(B, bsp, bsk, t.n, t.k, col0, k0 + KB);
+    }
 #pragma unroll
     for (int kk = 0; kk < KB; kk += 2) {
       const float a = As[kk + (lane >> 5)][wr + (lane & 31)];
@@ -109,10 +178,13 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTask* __restrict__ t
   tile_of(t, blockIdx.x - first_tile[ti], row0, col0);
   __shared__ double As[KB][64 + 2];
   __shared__ double Bs[KB][64 + 2];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
   const double* A = static_cast<const double*>(t.A);
   const double* B = static_cast<const double*>(t.B);
+  int64_t asp, ask, bsp, bsk;
+  a_geom(t, asp, ask);
+  b_geom(t, bsp, bsk);
   f64x4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -120,16 +192,19 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTask* __restrict__ t
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.0;
+  Stage<double, KB> sa, sb;
+  if (t.k > 0) {
+    sa.load(A, asp, ask, t.m, t.k, row0, 0);
+    sb.load(B, bsp, bsk, t.n, t.k, col0, 0);
+  }
   for (int k0 = 0; k0 < t.k; k0 += KB) {
-    for (int e = tid; e < 64 * KB; e += 256) {
-      int i, kk;
-      if (!t.ta) { i = e & 63; kk = e >> 6; } else { kk = e % KB; i = e / KB; }
-      As[kk][i] = load_a(t, A, row0 + i, k0 + kk);
-      int j, k2;
-      if (!t.tb) { k2 = e % KB; j = e / KB; } else { j = e & 63; k2 = e >> 6; }
-      Bs[k2][j] = load_b(t, B, k0 + k2, col0 + j);
-    }
+    sa.store(As, asp == 1);
+    sb.store(Bs, bsp == 1);
     __syncthreads();
+    if (k0 + KB < t.k) {
+      sa.load(A, asp, ask, t.m, t.k, row0, k0 + KB);
+      sb.load(B, bsp, bsk, t.n, t.k, col0, k0 + KB);
+    }
 #pragma unroll
     for (int kk = 0; kk < KB; kk += 4) {
       double a[2], b[2];
