@@ -97,8 +97,8 @@ template <class T, int KB> struct Stage {
       }
     }
   }
-  // into lds[k][p] (row stride LD)
-  template <int LD> __device__ inline void store(T (*lds)[LD], bool pc) const {
+  // into lds[k][p] (row stride LD), converted to the LDS element type
+  template <class L, int LD> __device__ inline void store(L (*lds)[LD], bool pc) const {
 #pragma unroll
     for (int s = 0; s < NV; ++s) {
       const int e = threadIdx.x + s * 256;
@@ -107,8 +107,8 @@ template <class T, int KB> struct Stage {
       else { k = (e % (KB / VEC)) * VEC; p = e / (KB / VEC); }
 #pragma unroll
       for (int u = 0; u < VEC; ++u) {
-        if (pc) lds[k][p + u] = v[s][u];
-        else lds[k + u][p] = v[s][u];
+        if (pc) lds[k][p + u] = L(v[s][u]);
+        else lds[k + u][p] = L(v[s][u]);
       }
     }
   }
@@ -312,6 +312,82 @@ __global__ __launch_bounds__(256) void k_gemm_lowp(const GemmTask* __restrict__ 
                       (float)((double)acc[v] * inv));
 }
 
+// FP64 Gram partials on the FP64 matrix cores: for one chunk of rows of a
+// stack S (m x r, precision T) and one upper-triangle pair (bi <= bj) of 64-wide
+// column blocks, part[chunk][i + j r] = sum over the chunk's rows of
+// S[row, i] S[row, j] (FP64 products of the FP32 / FP64 entries).
+template <class T>
+__global__ __launch_bounds__(256) void k_gram_mfma(const GramTask* __restrict__ tasks,
+                                                   const int* __restrict__ tile_task,
+                                                   const int* __restrict__ first_tile) {
+  constexpr int KB = 16;
+  const int ti = tile_task[blockIdx.x];
+  const GramTask t = tasks[ti];
+  int local = blockIdx.x - first_tile[ti];
+  const int nb = (t.r + 63) / 64, ntri = nb * (nb + 1) / 2;
+  const int chunk = local / ntri;
+  int tri = local - chunk * ntri;
+  int bi = 0;
+  while (tri >= nb - bi) { tri -= nb - bi; ++bi; }
+  const int bj = bi + tri;
+  const int r0 = chunk * t.rows_per_chunk;
+  const int r1 = min(t.m, r0 + t.rows_per_chunk);
+  const T* S = static_cast<const T*>(t.A);
+  __shared__ double As[KB][64 + 2];
+  __shared__ double Bs[KB][64 + 2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.0;
+  // operand p = column of S inside the block, k = row of S (contiguous)
+  const T* Sa = S + (int64_t)(bi * 64) * t.lda + r0;
+  const T* Sb = S + (int64_t)(bj * 64) * t.lda + r0;
+  const int P_a = min(64, t.r - bi * 64), P_b = min(64, t.r - bj * 64), K = r1 - r0;
+  Stage<T, KB> sa, sb;
+  if (K > 0) {
+    sa.load(Sa, t.lda, 1, P_a, K, 0, 0);
+    sb.load(Sb, t.lda, 1, P_b, K, 0, 0);
+  }
+  for (int k0 = 0; k0 < K; k0 += KB) {
+    sa.store(As, false);
+    sb.store(Bs, false);
+    __syncthreads();
+    if (k0 + KB < K) {
+      sa.load(Sa, t.lda, 1, P_a, K, 0, k0 + KB);
+      sb.load(Sb, t.lda, 1, P_b, K, 0, k0 + KB);
+    }
+#pragma unroll
+    for (int kk = 0; kk < KB; kk += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        a[s] = As[kk + (lane >> 4)][wr + 16 * s + (lane & 15)];
+        b[s] = Bs[kk + (lane >> 4)][wc + 16 * s + (lane & 15)];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[y], a[x], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* P = t.part + (int64_t)chunk * t.r * t.r;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = bi * 64 + wr + 16 * x + (lane & 15), j = bj * 64 + wc + 16 * y + (lane >> 4) + 4 * v;
+        if (i < t.r && j < t.r) P[i + (int64_t)j * t.r] = acc[x][y][v];
+      }
+}
+
 }  // namespace
 
 template <>
@@ -334,4 +410,15 @@ void launch_gemm_mfma<double>(const GemmTask* d_tasks, const int* d_tile_task, c
   hipLaunchKernelGGL(k_gemm_f64, dim3(ntiles), dim3(256), 0, s, d_tasks, d_tile_task, d_first_tile);
 }
 
+}  // namespace acr
+
+namespace acr {
+template <class T>
+void launch_gram_mfma(const GramTask* d_tasks, const int* d_tile_task, const int* d_first_tile, int ntiles,
+                      hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_gram_mfma<T>, dim3(ntiles), dim3(256), 0, s, d_tasks, d_tile_task, d_first_tile);
+}
+template void launch_gram_mfma<float>(const GramTask*, const int*, const int*, int, hipStream_t);
+template void launch_gram_mfma<double>(const GramTask*, const int*, const int*, int, hipStream_t);
 }  // namespace acr

@@ -1,8 +1,9 @@
 // Gram-based compression of large stacked low-rank sums.
 //
 // For a stack S (m x r) too large for one workgroup's local memory, the
-// triangular factor is obtained from the FP64 Gram matrix S^T S (computed by
-// many workgroups, each over a chunk of rows, then reduced in a fixed order)
+// triangular factor is obtained from the FP64 Gram matrix S^T S (computed on
+// the FP64 matrix cores by many workgroups, each over a chunk of rows and a
+// pair of 64-column blocks -- gemm_mfma.hip -- then reduced in a fixed order)
 // and a pivoted Cholesky factorisation that stops at the numerical rank:
 //   S P = Q [L11^T L21^T],  Q = S P1 L11^{-T}.
 // The core (L-factors of both stacks) then goes through the same one-sided
@@ -15,56 +16,6 @@
 namespace acr {
 
 namespace {
-
-constexpr int kGT = 32;  // Gram tile
-
-template <class T>
-__global__ __launch_bounds__(256) void k_gram_partial(const GramTask* __restrict__ tasks,
-                                                      const int* __restrict__ tile_task,
-                                                      const int* __restrict__ first_tile) {
-  const int tile = blockIdx.x;
-  const int ti = tile_task[tile];
-  const GramTask t = tasks[ti];
-  int local = tile - first_tile[ti];
-  const int nb = (t.r + kGT - 1) / kGT;
-  const int ntri = nb * (nb + 1) / 2;
-  const int chunk = local / ntri;
-  int tri = local - chunk * ntri;
-  // tri -> (bi, bj) with bi <= bj
-  int bi = 0;
-  while (tri >= nb - bi) { tri -= nb - bi; ++bi; }
-  const int bj = bi + tri;
-  const int r0 = chunk * t.rows_per_chunk;
-  const int r1 = min(t.m, r0 + t.rows_per_chunk);
-  const T* A = static_cast<const T*>(t.A);
-  __shared__ double Ai[kGT][kGT + 1];
-  __shared__ double Aj[kGT][kGT + 1];
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // ty in 0..7
-  double acc[4] = {0, 0, 0, 0};
-  for (int row = r0; row < r1; row += kGT) {
-    for (int e = threadIdx.x; e < kGT * kGT; e += 256) {
-      const int rr = e & 31, cc = e >> 5;
-      const int gr = row + rr;
-      const int ci = bi * kGT + cc, cj = bj * kGT + cc;
-      Ai[rr][cc] = (gr < r1 && ci < t.r) ? (double)A[gr + (int64_t)ci * t.lda] : 0.0;
-      Aj[rr][cc] = (gr < r1 && cj < t.r) ? (double)A[gr + (int64_t)cj * t.lda] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < kGT; ++rr) {
-      const double b = Aj[rr][tx];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] += Ai[rr][ty + 8 * q] * b;
-    }
-    __syncthreads();
-  }
-  double* P = t.part + (int64_t)chunk * t.r * t.r;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int i = bi * kGT + ty + 8 * q, j = bj * kGT + tx;
-    if (i < t.r && j < t.r) P[i + (int64_t)j * t.r] = acc[q];
-  }
-}
 
 __global__ __launch_bounds__(256) void k_gram_reduce(const GramTask* __restrict__ tasks) {
   const GramTask t = tasks[blockIdx.x];
@@ -236,7 +187,7 @@ template <class T>
 void launch_gram(const GramTask* d_tasks, int ntasks, const int* d_tile_task, const int* d_first_tile, int ntiles,
                  hipStream_t s) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_gram_partial<T>, dim3(ntiles), dim3(256), 0, s, d_tasks, d_tile_task, d_first_tile);
+  launch_gram_mfma<T>(d_tasks, d_tile_task, d_first_tile, ntiles, s);
   hipLaunchKernelGGL(k_gram_reduce, dim3(ntasks, 16), dim3(256), 0, s, d_tasks);
 }
 

@@ -714,7 +714,7 @@ template <class T> void Exec::gram(const std::vector<GramTask>& t) {
       check_range(x.G, sizeof(double) * (size_t)x.r * x.r, "gram G");
     }
     first[i] = nt;
-    const int nb = (x.r + 31) / 32, nch = (x.m + x.rows_per_chunk - 1) / x.rows_per_chunk;
+    const int nb = (x.r + 63) / 64, nch = (x.m + x.rows_per_chunk - 1) / x.rows_per_chunk;
     const int tiles = nch * nb * (nb + 1) / 2;
     for (int j = 0; j < tiles; ++j) tile_task.push_back((int)i);
     nt += tiles;
