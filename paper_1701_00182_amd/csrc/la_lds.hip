@@ -46,53 +46,62 @@ __global__ __launch_bounds__(NT) void k_qr_lds(const QrTask* __restrict__ tasks)
   if (LDS)
     for (int e = threadIdx.x; e < m * r; e += NT) a[e] = A[(e % m) + (int64_t)(e / m) * t.lda];
   __shared__ double red[NT / 64];
-  __shared__ double sh_tau, sh_scale, sh_beta;
+  __shared__ double sh_sig[2];
   const int G = lanes_for_rows(m), groups = NT / G;
   const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   const int nref = m < r ? m : r;
   __syncthreads();
-  for (int j = 0; j < nref; ++j) {
-    T* col = a + j * la;
+  // sigma_j = squared norm of column j below the diagonal; for j > 0 it comes
+  // from the group that updated column j in the previous step
+  double sigma = 0.0;
+  {
     double ps = 0.0;
-    for (int i = j + 1 + threadIdx.x; i < m; i += NT) {
-      const double v = (double)col[i];
+    for (int i = 1 + threadIdx.x; i < m; i += NT) {
+      const double v = (double)a[i];
       ps += v * v;
     }
-    const double sigma = block_sum<NT>(ps, red);
-    if (threadIdx.x == 0) {
-      const double x0 = (double)col[j];
-      if (sigma == 0.0) {
-        sh_tau = 0.0;
-        sh_beta = x0;
-        sh_scale = 0.0;
-      } else {
-        const double nrm = sqrt(x0 * x0 + sigma);
-        const double beta = x0 >= 0.0 ? -nrm : nrm;
-        sh_tau = (beta - x0) / beta;
-        sh_scale = 1.0 / (x0 - beta);
-        sh_beta = beta;
-      }
-      tau[j] = T(sh_tau);
-    }
-    __syncthreads();
-    const double tj = sh_tau;
-    if (tj != 0.0) {
-      const T sc = T(sh_scale);
-      for (int i = j + 1 + threadIdx.x; i < m; i += NT) col[i] *= sc;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) col[j] = T(sh_beta);
-    if (tj != 0.0) {
-      for (int c = j + 1 + gi; c < r; c += groups) {
-        T* ac = a + c * la;
-        double w = 0.0;
-        for (int i = j + gl; i < m; i += G) w += (i == j ? 1.0 : (double)col[i]) * (double)ac[i];
-        w = gsum(w, G) * tj;
-        for (int i = j + gl; i < m; i += G) ac[i] = T((double)ac[i] - w * (i == j ? 1.0 : (double)col[i]));
-      }
-    }
-    __syncthreads();
+    sigma = block_sum<NT>(ps, red);
   }
+  for (int j = 0; j < nref; ++j) {
+    T* col = a + j * la;
+    const double x0 = (double)col[j];
+    double tj = 0.0, scale = 0.0, beta = x0;
+    if (sigma != 0.0) {
+      const double nrm = sqrt(x0 * x0 + sigma);
+      beta = x0 >= 0.0 ? -nrm : nrm;
+      tj = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    if (threadIdx.x == 0) tau[j] = T(tj);
+    // v = (1, x_{j+1..} * scale) rounded to T as it will be stored, applied to
+    // the trailing columns on the fly
+    for (int c = j + 1 + gi; c < r; c += groups) {
+      T* ac = a + c * la;
+      if (tj != 0.0) {
+        double w = 0.0;
+        for (int i = j + gl; i < m; i += G) w += (i == j ? 1.0 : (double)T((double)col[i] * scale)) * (double)ac[i];
+        w = gsum(w, G) * tj;
+        for (int i = j + gl; i < m; i += G)
+          ac[i] = T((double)ac[i] - w * (i == j ? 1.0 : (double)T((double)col[i] * scale)));
+      }
+      if (c == j + 1) {
+        double sn = 0.0;
+        for (int i = j + 2 + gl; i < m; i += G) {
+          const double v = (double)ac[i];
+          sn += v * v;
+        }
+        sn = gsum(sn, G);
+        if (gl == 0) sh_sig[j & 1] = sn;
+      }
+    }
+    __syncthreads();
+    // column j is no longer read: store its reflector and the diagonal of R
+    if (tj != 0.0)
+      for (int i = j + 1 + threadIdx.x; i < m; i += NT) col[i] = T((double)col[i] * scale);
+    if (threadIdx.x == 0) col[j] = T(beta);
+    sigma = sh_sig[j & 1];
+  }
+  __syncthreads();
   if (LDS)
     for (int e = threadIdx.x; e < m * r; e += NT) A[(e % m) + (int64_t)(e / m) * t.lda] = a[e];
 }

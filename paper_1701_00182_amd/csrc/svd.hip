@@ -96,7 +96,8 @@ __device__ inline double core_entry(const SvdTask& t, int a, int b) {
 // Householder QR with column pivoting of C (p x q, column stride lc), stopped
 // at the first pivot column whose remaining norm^2 is at most thr2 (see
 // callers); returns the number of reflectors t.  R is left in the upper
-// triangle of the first t rows, reflectors below it.  All threads call it.
+// triangle of the first t rows (the entries below it are left unspecified).
+// All threads call it.
 template <int NT>
 __device__ int qrcp_body(double* C, int64_t lc, int p, int q, double* nrm, int* perm, double delta, double* red,
                          int* redi) {
@@ -142,30 +143,28 @@ __device__ int qrcp_body(double* C, int64_t lc, int p, int q, double* nrm, int* 
       }
       __syncthreads();
     }
+    // Householder reflector of column j from its stored norm: nrm[j] holds the
+    // squared norm of rows j.. (recomputed exactly after the previous step), so
+    // the part below the diagonal is nrm[j] - x0^2 without another reduction.
+    // The reflector v = (1, x_{j+1..} * scale) is applied on the fly and not
+    // stored: only R is used afterwards.
     double* col = C + j * lc;
-    double ps = 0.0;
-    for (int i = j + 1 + threadIdx.x; i < p; i += NT) ps += col[i] * col[i];
-    const double sigma = block_sum<NT>(ps, red);
     const double x0 = col[j];
+    const double sigma = fmax(nrm[j] - x0 * x0, 0.0);
     double tj = 0.0, scale = 0.0, beta = x0;
-    if (sigma != 0.0) {
+    if (sigma > 0.0) {
       const double nr = sqrt(x0 * x0 + sigma);
       beta = x0 >= 0.0 ? -nr : nr;
       tj = (beta - x0) / beta;
       scale = 1.0 / (x0 - beta);
     }
-    __syncthreads();
-    if (tj != 0.0)
-      for (int i = j + 1 + threadIdx.x; i < p; i += NT) col[i] *= scale;
-    if (threadIdx.x == 0) col[j] = beta;
-    __syncthreads();
     for (int c = j + 1 + gi; c < q; c += groups) {
       double* ac = C + c * lc;
       if (tj != 0.0) {
         double w = 0.0;
-        for (int i = j + gl; i < p; i += G) w += (i == j ? 1.0 : col[i]) * ac[i];
+        for (int i = j + gl; i < p; i += G) w += (i == j ? 1.0 : col[i] * scale) * ac[i];
         w = gsum2(w, G) * tj;
-        for (int i = j + gl; i < p; i += G) ac[i] -= w * (i == j ? 1.0 : col[i]);
+        for (int i = j + gl; i < p; i += G) ac[i] -= w * (i == j ? 1.0 : col[i] * scale);
       }
       double s = 0.0;
       for (int i = j + 1 + gl; i < p; i += G) s += ac[i] * ac[i];
@@ -173,8 +172,11 @@ __device__ int qrcp_body(double* C, int64_t lc, int p, int q, double* nrm, int* 
       if (gl == 0) nrm[c] = s;
     }
     __syncthreads();
+    // every thread has read x0 and the column: the diagonal of R can be stored
+    if (threadIdx.x == 0) col[j] = beta;
     tcount = j + 1;
   }
+  __syncthreads();
   return tcount;
 }
 
