@@ -88,9 +88,12 @@ def measured_traffic(cls):
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)["classes"][cls]
-        with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest() != rec["sha256"]:
-                return None
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != rec["sha256"]:
+            return None
         return rec["bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
