@@ -127,7 +127,8 @@ typedef struct {
 acr_status_t acr_get_stats(acr_handle_t h, acr_stats_t* st);
 
 typedef struct {
-  int32_t method;      /* 0: iterative refinement x += M^{-1} r; 1: right-preconditioned GMRES */
+  int32_t method;      /* 0: iterative refinement x += M^{-1} r; 1: right-preconditioned GMRES; */
+                       /* 2: preconditioned (flexible) CG, for symmetric positive definite A   */
   int32_t restart;     /* GMRES restart length (default 30)                                  */
   int32_t maxit;       /* maximum preconditioner applications (default 200)                  */
   double tol;          /* stop when ||b - A x||_2 / ||b||_2 <= tol (FP64 residual)           */

@@ -178,7 +178,7 @@ class Factor:
         if b.dim() != 1:
             raise ValueError("refined solves take one right-hand side")
         x = torch.empty_like(b)
-        ro = RefineOptions(1 if method == "gmres" else 0, restart, maxit, tol, 1 if transpose else 0)
+        ro = RefineOptions({"ir": 0, "gmres": 1, "cg": 2}[method], restart, maxit, tol, 1 if transpose else 0)
         rr = RefineResult()
         hist = (ctypes.c_double * history)()
         code = lib().acr_solve_refined(self._h, ctypes.byref(ro), ctypes.c_void_p(b.data_ptr()),

@@ -738,7 +738,8 @@ struct Krylov {
 int refine(FactorBase& f, const acr_refine_options_t& ro, const double* b, double* x, hipStream_t s,
            acr_refine_result_t* res, double* hist, int hlen) {
   const int64_t N = f.grid.N();
-  const int m = ro.method == 1 ? std::max(1, ro.restart > 0 ? ro.restart : 30) : 1;
+  // Krylov basis vectors: GMRES(m) keeps m + 1, CG uses four (p, A p, z, r_old)
+  const int m = ro.method == 1 ? std::max(1, ro.restart > 0 ? ro.restart : 30) : (ro.method == 2 ? 3 : 1);
   const int maxit = ro.maxit > 0 ? ro.maxit : 200;
   const bool tr = ro.transpose != 0;
   const int nblk = 512;
@@ -772,7 +773,39 @@ int refine(FactorBase& f, const acr_refine_options_t& ro, const double* b, doubl
   double rel = std::sqrt(K.host_dot(r, r)) / bn;
   const double rel0 = rel;
   log(rel);
-  if (ro.method != 1) {
+  if (ro.method == 2) {
+    // flexible preconditioned conjugate gradients (beta from z^T (r_new - r_old),
+    // robust to the small asymmetry the truncation leaves in the preconditioner)
+    double* pv = V;
+    double* q = V + N;
+    double* z = V + 2 * N;
+    double* rold = V + 3 * N;
+    if (rel > ro.tol && it < maxit) {
+      K.precond(r, z, tr);
+      ++it;
+      double rz = K.host_dot(r, z);
+      launch_axpby(N, 1.0, z, 0.0, pv, s);
+      while (true) {
+        K.residual(pv, zero, q, tr);   // q = -A p
+        const double pq = -K.host_dot(pv, q);
+        if (!(pq > 0.0) || !std::isfinite(pq)) break;
+        const double alpha = rz / pq;
+        launch_axpby(N, alpha, pv, 1.0, x, s);
+        launch_axpby(N, 1.0, r, 0.0, rold, s);
+        launch_axpby(N, alpha, q, 1.0, r, s);
+        rel = std::sqrt(K.host_dot(r, r)) / bn;
+        log(rel);
+        if (!std::isfinite(rel) || rel <= ro.tol || it >= maxit) break;
+        K.precond(r, z, tr);
+        ++it;
+        const double beta = (K.host_dot(z, r) - K.host_dot(z, rold)) / rz;
+        rz = K.host_dot(r, z);
+        launch_axpby(N, 1.0, z, beta, pv, s);
+      }
+      K.residual(x, b, r, tr);   // the true residual decides convergence
+      rel = std::sqrt(K.host_dot(r, r)) / bn;
+    }
+  } else if (ro.method != 1) {
     while (rel > ro.tol && it < maxit) {
       K.precond(r, w, tr);
       ++it;
@@ -1114,7 +1147,7 @@ acr_status_t acr_kappa_gradient(int32_t nx, int32_t ny, int32_t nz, const double
 acr_status_t acr_solve_refined(acr_handle_t h, const acr_refine_options_t* ro, const double* b, double* x,
                                hipStream_t stream, acr_refine_result_t* res, double* history,
                                int32_t history_len) {
-  if (!h || !h->impl || !ro || !b || !x || b == x || !(ro->tol > 0.0) || ro->method < 0 || ro->method > 1)
+  if (!h || !h->impl || !ro || !b || !x || b == x || !(ro->tol > 0.0) || ro->method < 0 || ro->method > 2)
     return ACR_ERROR_INVALID_VALUE;
   return guarded([&]() -> acr_status_t {
     return to_status(refine(*h->impl, *ro, b, x, stream, res, history, history_len));

@@ -90,7 +90,7 @@ def test_multi_rhs_equals_single_solves():
     fac.free()
 
 
-@pytest.mark.parametrize("method", ["ir", "gmres"])
+@pytest.mark.parametrize("method", ["ir", "gmres", "cg"])
 def test_fp32_refined_to_1e8(method):
     n, leaf = 16, 32
     coef = problem("poisson", n)
