@@ -107,9 +107,17 @@ __global__ __launch_bounds__(NT) void k_pchol(const PcholTask* __restrict__ task
     while (Gl > 1 && Gl * rem > NT) Gl >>= 1;
     const int groups = NT / Gl, gi = threadIdx.x / Gl, gl = threadIdx.x % Gl;
     for (int i = j + 1 + gi; i < r; i += groups) {
-      double s = 0.0;
-      for (int l = gl; l < j; l += Gl) s += L[i + (int64_t)l * r] * L[j + (int64_t)l * r];
-      s = gsumw(s, Gl);
+      // four independent partial sums keep four loads of each row in flight
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int l = gl;
+      for (; l + 3 * Gl < j; l += 4 * Gl) {
+        s0 += L[i + (int64_t)l * r] * L[j + (int64_t)l * r];
+        s1 += L[i + (int64_t)(l + Gl) * r] * L[j + (int64_t)(l + Gl) * r];
+        s2 += L[i + (int64_t)(l + 2 * Gl) * r] * L[j + (int64_t)(l + 2 * Gl) * r];
+        s3 += L[i + (int64_t)(l + 3 * Gl) * r] * L[j + (int64_t)(l + 3 * Gl) * r];
+      }
+      for (; l < j; l += Gl) s0 += L[i + (int64_t)l * r] * L[j + (int64_t)l * r];
+      double s = gsumw((s0 + s1) + (s2 + s3), Gl);
       if (gl == 0) {
         const int pi = perm[i];
         const double lij = (G[pi + (int64_t)pj * r] - s) / ljj;

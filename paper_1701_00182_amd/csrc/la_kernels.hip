@@ -17,24 +17,6 @@ namespace acr {
 
 namespace {
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Sum over the 256 threads of a workgroup; every thread gets the result.
-__device__ inline double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = red[0] + red[1] + red[2] + red[3];
-  __syncthreads();
-  return s;
-}
-
 template <class T>
 __global__ __launch_bounds__(256) void k_copy(const CopyTask* __restrict__ tasks) {
   const CopyTask t = tasks[blockIdx.x];
@@ -57,8 +39,12 @@ __global__ __launch_bounds__(256) void k_copy(const CopyTask* __restrict__ tasks
 
 // Gauss-Jordan inversion with partial pivoting.  LDS=true stages the matrix in
 // shared memory (s * s elements), otherwise it works on the global copy.
-template <class T, bool LDS>
-__global__ __launch_bounds__(256) void k_inverse(const InvTask* __restrict__ tasks, int* flags) {
+// Gauss-Jordan inverse with partial pivoting, in place (LDS copy when it fits).
+// Per pivot: a wavefront-shuffle argmax, the row swap, the rank-1 update of
+// every entry outside row / column j (row j scaled on the fly), then row j and
+// column j: three workgroup barriers plus the argmax's two.
+template <class T, bool LDS, int NT>
+__global__ __launch_bounds__(NT) void k_inverse(const InvTask* __restrict__ tasks, int* flags) {
   extern __shared__ double smem_d[];
   const InvTask t = tasks[blockIdx.x];
   const int s = t.s;
@@ -71,43 +57,37 @@ __global__ __launch_bounds__(256) void k_inverse(const InvTask* __restrict__ tas
     a = reinterpret_cast<T*>(smem_d);
     la = s;
     piv = reinterpret_cast<int*>(a + (int64_t)s * s);
-    for (int e = threadIdx.x; e < s * s; e += 256) a[e] = g[(e % s) + (int64_t)(e / s) * t.lda];
+    for (int e = threadIdx.x; e < s * s; e += NT) a[e] = g[(e % s) + (int64_t)(e / s) * t.lda];
   } else {
     a = g;
     la = t.lda;
     piv = reinterpret_cast<int*>(smem_d);
   }
-  __shared__ double rv[256];
-  __shared__ int ri[256];
-  __shared__ int sh_p;
+  __shared__ double red[NT / 64];
+  __shared__ int redi[NT / 64];
   __syncthreads();
   bool bad = false;
   for (int j = 0; j < s; ++j) {
     double best = -1.0;
     int bi = j;
-    for (int i = j + threadIdx.x; i < s; i += 256) {
+    for (int i = j + threadIdx.x; i < s; i += NT) {
       const double v = fabs((double)a[i + j * la]);
       if (v > best) { best = v; bi = i; }
     }
-    rv[threadIdx.x] = best;
-    ri[threadIdx.x] = bi;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) {
-        const double o = rv[threadIdx.x + w];
-        const int oi = ri[threadIdx.x + w];
-        if (o > rv[threadIdx.x] || (o == rv[threadIdx.x] && oi < ri[threadIdx.x])) {
-          rv[threadIdx.x] = o;
-          ri[threadIdx.x] = oi;
-        }
-      }
-      __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (o > best || (o == best && oi < bi)) { best = o; bi = oi; }
     }
-    if (threadIdx.x == 0) { sh_p = ri[0]; piv[j] = ri[0]; }
+    if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = best; redi[threadIdx.x >> 6] = bi; }
     __syncthreads();
-    const int p = sh_p;
+    best = red[0];
+    int p = redi[0];
+    for (int w = 1; w < NT / 64; ++w)
+      if (red[w] > best || (red[w] == best && redi[w] < p)) { best = red[w]; p = redi[w]; }
+    if (threadIdx.x == 0) piv[j] = p;
     if (p != j) {
-      for (int c = threadIdx.x; c < s; c += 256) {
+      for (int c = threadIdx.x; c < s; c += NT) {
         const T tmp = a[j + c * la];
         a[j + c * la] = a[p + c * la];
         a[p + c * la] = tmp;
@@ -117,24 +97,23 @@ __global__ __launch_bounds__(256) void k_inverse(const InvTask* __restrict__ tas
     const T pv = a[j + j * la];
     if (!(pv != T(0)) || !isfinite((double)pv)) bad = true;
     const T inv = T(1) / pv;
-    __syncthreads();
-    for (int c = threadIdx.x; c < s; c += 256)
-      if (c != j) a[j + c * la] *= inv;
-    __syncthreads();
-    for (int64_t e = threadIdx.x; e < (int64_t)s * s; e += 256) {
+    for (int64_t e = threadIdx.x; e < (int64_t)s * s; e += NT) {
       const int i = (int)(e % s), c = (int)(e / s);
-      if (i != j && c != j) a[i + c * la] -= a[i + j * la] * a[j + c * la];
+      if (i != j && c != j) a[i + c * la] -= a[i + j * la] * (a[j + c * la] * inv);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < s; i += 256)
-      if (i != j) a[i + j * la] = -a[i + j * la] * inv;
+    for (int c = threadIdx.x; c < s; c += NT)
+      if (c != j) {
+        a[j + c * la] *= inv;
+        a[c + j * la] = -a[c + j * la] * inv;
+      }
     if (threadIdx.x == 0) a[j + j * la] = inv;
     __syncthreads();
   }
   for (int j = s - 1; j >= 0; --j) {
     const int p = piv[j];
     if (p != j) {
-      for (int r = threadIdx.x; r < s; r += 256) {
+      for (int r = threadIdx.x; r < s; r += NT) {
         const T tmp = a[r + j * la];
         a[r + j * la] = a[r + p * la];
         a[r + p * la] = tmp;
@@ -143,7 +122,7 @@ __global__ __launch_bounds__(256) void k_inverse(const InvTask* __restrict__ tas
     __syncthreads();
   }
   if (LDS) {
-    for (int e = threadIdx.x; e < s * s; e += 256) g[(e % s) + (int64_t)(e / s) * t.lda] = a[e];
+    for (int e = threadIdx.x; e < s * s; e += NT) g[(e % s) + (int64_t)(e / s) * t.lda] = a[e];
   }
   if (bad && threadIdx.x == 0) atomicOr(&flags[FLAG_SINGULAR], 1);
 }
@@ -161,10 +140,18 @@ template <class T>
 void launch_inverse(const InvTask* d_tasks, int ntasks, int max_s, int* d_flags, hipStream_t s) {
   if (ntasks <= 0) return;
   const size_t lds_bytes = (size_t)max_s * max_s * sizeof(T) + (size_t)max_s * sizeof(int);
-  if (lds_bytes <= 60 * 1024) {
-    hipLaunchKernelGGL((k_inverse<T, true>), dim3(ntasks), dim3(256), lds_bytes, s, d_tasks, d_flags);
+  if (lds_bytes <= kLdsBudget) {
+    if (max_s < 96) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_inverse<T, true, 256>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+      hipLaunchKernelGGL((k_inverse<T, true, 256>), dim3(ntasks), dim3(256), lds_bytes, s, d_tasks, d_flags);
+    } else {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_inverse<T, true, 1024>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+      hipLaunchKernelGGL((k_inverse<T, true, 1024>), dim3(ntasks), dim3(1024), lds_bytes, s, d_tasks, d_flags);
+    }
   } else {
-    hipLaunchKernelGGL((k_inverse<T, false>), dim3(ntasks), dim3(256), (size_t)max_s * sizeof(int), s,
+    hipLaunchKernelGGL((k_inverse<T, false, 1024>), dim3(ntasks), dim3(1024), (size_t)max_s * sizeof(int), s,
                        d_tasks, d_flags);
   }
 }
