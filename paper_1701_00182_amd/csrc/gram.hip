@@ -43,12 +43,14 @@ __device__ inline double gsumw(double v, int G) {
 // entries on and below the diagonal of the first `rank` columns are written.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_pchol(const PcholTask* __restrict__ tasks, double tol) {
+  extern __shared__ double smp[];
   const PcholTask t = tasks[blockIdx.x];
   const int r = t.r;
   const double* G = t.G;
   double* L = t.L;
-  int* perm = t.perm;
-  double* d = t.d;
+  // the remaining diagonal and the pivot order live in LDS during the loop
+  double* d = smp;
+  int* perm = reinterpret_cast<int*>(smp + r);
   __shared__ double red[NT / 64];
   __shared__ int redi[NT / 64];
   double mx = 0.0;
@@ -128,6 +130,11 @@ __global__ __launch_bounds__(NT) void k_pchol(const PcholTask* __restrict__ task
     __syncthreads();
     rank = j + 1;
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < r; i += NT) {
+    t.perm[i] = perm[i];
+    t.d[i] = d[i];
+  }
   if (threadIdx.x == 0) *t.rank_out = rank;
 }
 
@@ -199,9 +206,13 @@ void launch_gram(const GramTask* d_tasks, int ntasks, const int* d_tile_task, co
   hipLaunchKernelGGL(k_gram_reduce, dim3(ntasks, 16), dim3(256), 0, s, d_tasks);
 }
 
-void launch_pchol(const PcholTask* d_tasks, int ntasks, double tol, hipStream_t s) {
+void launch_pchol(const PcholTask* d_tasks, int ntasks, int max_r, double tol, hipStream_t s) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_pchol<1024>, dim3(ntasks), dim3(1024), 0, s, d_tasks, tol);
+  const size_t lds = (size_t)max_r * (sizeof(double) + sizeof(int));
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol<1024>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_pchol<1024>, dim3(ntasks), dim3(1024), lds, s, d_tasks, tol);
 }
 
 void launch_materialize_r(const PcholTask* d_tasks, int ntasks, hipStream_t s) {

@@ -186,7 +186,7 @@ template <class T> void launch_gram(const GramTask* d_tasks, int ntasks, const i
 // pairs of 64-column blocks)
 template <class T> void launch_gram_mfma(const GramTask* d_tasks, const int* d_tile_task, const int* d_first_tile,
                                         int ntiles, hipStream_t s);
-void launch_pchol(const PcholTask* d_tasks, int ntasks, double tol, hipStream_t s);
+void launch_pchol(const PcholTask* d_tasks, int ntasks, int max_r, double tol, hipStream_t s);
 void launch_materialize_r(const PcholTask* d_tasks, int ntasks, hipStream_t s);
 template <class T> void launch_wtilde(const WtTask* d_tasks, int ntasks, int kc, int nchunks, size_t lds,
                                       hipStream_t s);

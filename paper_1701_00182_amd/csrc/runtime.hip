@@ -749,9 +749,13 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
     w.flops += (double)x.r * x.r * x.r / 3.0;
     w.bytes += 16.0 * x.r * x.r;
   }
+  int max_r = 1;
+  for (auto& x : t) max_r = std::max(max_r, x.r);
+  if ((size_t)max_r * (sizeof(double) + sizeof(int)) > kLdsBudget)
+    throw Failure(ST_NOT_SUPPORTED, "stack too wide for the pivoted Cholesky kernel");
   const PcholTask* dt = upload(t);
   const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_pchol(dt, n, tol, s); }, w);
+  submit([=](hipStream_t s) { launch_pchol(dt, n, max_r, tol, s); }, w);
 }
 
 void Exec::materialize_r(const std::vector<PcholTask>& t) {
