@@ -312,6 +312,107 @@ __global__ __launch_bounds__(256) void k_gemm_lowp(const GemmTask* __restrict__ 
                       (float)((double)acc[v] * inv));
 }
 
+// Segmented GEMM: the inner dimension runs over the task's (A_s, B_s) pairs,
+// each in K blocks (zero-padded at a segment's end), with the same register
+// prefetch; FP32 data on 32x32x2 FP32 MFMA, FP64 data on 16x16x4 FP64 MFMA.
+template <class T>
+__global__ __launch_bounds__(256) void k_seg_gemm(const SegGemmTask* __restrict__ tasks,
+                                                  const int* __restrict__ tile_task,
+                                                  const int* __restrict__ first_tile) {
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int KB = F32 ? 32 : 16;
+  constexpr int PAD = F32 ? 4 : 2;
+  const int ti = tile_task[blockIdx.x];
+  const SegGemmTask& t = tasks[ti];
+  const int local = blockIdx.x - first_tile[ti];
+  const int ntn = (t.n + 63) >> 6;
+  const int row0 = (local / ntn) * 64, col0 = (local % ntn) * 64;
+  __shared__ T As[KB][64 + PAD];
+  __shared__ T Bs[KB][64 + PAD];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+  f32x16 accf;
+  f64x4 accd[2][2];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) accf[v] = 0.f;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) accd[a][b][v] = 0.0;
+  // cursor over (segment, k block)
+  int cs = 0, ck = 0;
+  while (cs < t.nseg && t.k[cs] <= 0) ++cs;
+  Stage<T, KB> sa, sb;
+  auto load = [&](int seg, int k0) {
+    const int64_t asp = ((t.ta >> seg) & 1) ? t.lda[seg] : 1, ask = ((t.ta >> seg) & 1) ? 1 : t.lda[seg];
+    sa.load(static_cast<const T*>(t.A[seg]), asp, ask, t.m, t.k[seg], row0, k0);
+    sb.load(static_cast<const T*>(t.B[seg]), t.ldb[seg], 1, t.n, t.k[seg], col0, k0);
+  };
+  if (cs < t.nseg) load(cs, 0);
+  while (cs < t.nseg) {
+    // the same contiguity test as in load()
+    const bool apc = (((t.ta >> cs) & 1) ? t.lda[cs] : 1) == 1;
+    sa.store(As, apc);
+    sb.store(Bs, t.ldb[cs] == 1);
+    __syncthreads();
+    // advance the cursor and prefetch the next block
+    int ns = cs, nk = ck + KB;
+    if (nk >= t.k[ns]) {
+      ++ns;
+      nk = 0;
+      while (ns < t.nseg && t.k[ns] <= 0) ++ns;
+    }
+    if (ns < t.nseg) load(ns, nk);
+    if constexpr (F32) {
+#pragma unroll
+      for (int kk = 0; kk < KB; kk += 2) {
+        const float a = As[kk + (lane >> 5)][wr + (lane & 31)];
+        const float b = Bs[kk + (lane >> 5)][wc + (lane & 31)];
+        accf = __builtin_amdgcn_mfma_f32_32x32x2f32(b, a, accf, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KB; kk += 4) {
+        double a[2], b[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          a[s] = As[kk + (lane >> 4)][wr + 16 * s + (lane & 15)];
+          b[s] = Bs[kk + (lane >> 4)][wc + 16 * s + (lane & 15)];
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            accd[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[y], a[x], accd[x][y], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    cs = ns;
+    ck = nk;
+  }
+  auto put = [&](int i, int j, T v) {
+    const int gi = row0 + i, gj = col0 + j;
+    if (gi >= t.m || gj >= t.n) return;
+    T* c = static_cast<T*>(t.C) + gi + (int64_t)gj * t.ldc;
+    T r = T(t.alpha) * v;
+    if (t.beta != 0.0) r += T(t.beta) * *c;
+    *c = r;
+  };
+  if constexpr (F32) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) put(wr + (lane & 31), wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), accf[v]);
+  } else {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) put(wr + 16 * x + (lane & 15), wc + 16 * y + (lane >> 4) + 4 * v, accd[x][y][v]);
+  }
+}
+
 // FP64 Gram partials on the FP64 matrix cores: for one chunk of rows of a
 // stack S (m x r, precision T) and one upper-triangle pair (bi <= bj) of 64-wide
 // column blocks, part[chunk][i + j r] = sum over the chunk's rows of
@@ -354,8 +455,8 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const GramTask* __restrict__ 
     sb.load(Sb, t.lda, 1, P_b, K, 0, 0);
   }
   for (int k0 = 0; k0 < K; k0 += KB) {
-    sa.store(As, false);
-    sb.store(Bs, false);
+    sa.store(As, t.lda == 1);
+    sb.store(Bs, t.lda == 1);
     __syncthreads();
     if (k0 + KB < K) {
       sa.load(Sa, t.lda, 1, P_a, K, 0, k0 + KB);
@@ -421,4 +522,15 @@ void launch_gram_mfma(const GramTask* d_tasks, const int* d_tile_task, const int
 }
 template void launch_gram_mfma<float>(const GramTask*, const int*, const int*, int, hipStream_t);
 template void launch_gram_mfma<double>(const GramTask*, const int*, const int*, int, hipStream_t);
+}  // namespace acr
+
+namespace acr {
+template <class T>
+void launch_seg_gemm(const SegGemmTask* d_tasks, const int* d_tile_task, const int* d_first_tile, int ntiles,
+                     hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_seg_gemm<T>, dim3(ntiles), dim3(256), 0, s, d_tasks, d_tile_task, d_first_tile);
+}
+template void launch_seg_gemm<float>(const SegGemmTask*, const int*, const int*, int, hipStream_t);
+template void launch_seg_gemm<double>(const SegGemmTask*, const int*, const int*, int, hipStream_t);
 }  // namespace acr

@@ -124,6 +124,7 @@ class Exec {
   void clear_flags();
 
   template <class T> void gemm(const std::vector<GemmTask>& t);
+  template <class T> void seg_gemm(const std::vector<SegGemmTask>& t);
   template <class T> void copy(const std::vector<CopyTask>& t);
   template <class T> void inverse(const std::vector<InvTask>& t);
   template <class T> void qr(const std::vector<QrTask>& t);

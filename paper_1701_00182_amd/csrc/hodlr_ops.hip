@@ -335,6 +335,62 @@ void hodlr_multivec(Exec& ex, const Tree& tr, const std::vector<MVJob<T>>& jobs,
     }
   }
   ex.gemm<T>(inner);
+  // Without correction terms each leaf's rows of Y are formed in one pass: the
+  // leaf times X plus every ancestor block's U-slice (V-slice transposed) times
+  // its t, concatenated along the inner dimension (Y read and written once).
+  bool seg = tr.L - dmin + 1 <= kMaxSeg;
+  for (const auto& j : jobs) seg = seg && !j.corr && (j.beta == 0.0 || j.beta == 1.0);
+  if (seg) {
+    std::vector<SegGemmTask> sg;
+    std::vector<CopyTask> dg;
+    for (size_t ji = 0; ji < jobs.size(); ++ji) {
+      const auto& j = jobs[ji];
+      if (j.H->kind == HMat<T>::DIAG) {
+        dg.push_back(ctk<T>(j.X, j.ldx, j.Y, j.ldy, tr.M, j.c, j.alpha, j.beta != 0.0, j.H->diag));
+        continue;
+      }
+      if (j.H->kind == HMat<T>::ABSENT) {
+        if (j.beta == 0.0) dg.push_back(ctk<T>(nullptr, 0, j.Y, j.ldy, tr.M, j.c, 0.0, 0));
+        continue;
+      }
+      for (int s = 0; s < nseg(L); ++s) {
+        const int o = tr.off[L][s], n = tr.sz[L][s];
+        SegGemmTask g{};
+        g.C = j.Y + o;
+        g.ldc = j.ldy;
+        g.m = n;
+        g.n = j.c;
+        g.alpha = j.alpha;
+        g.beta = j.beta;
+        g.A[0] = j.H->leaf[s];
+        g.lda[0] = n;
+        g.B[0] = j.X + o;
+        g.ldb[0] = j.ldx;
+        g.k[0] = n;
+        g.ta = trans ? 1u : 0u;
+        g.nseg = 1;
+        for (int d = dmin; d < L; ++d) {
+          // the leaf lies in segment sd of depth d + 1; its rows of H X come from
+          // block (d, sd) (U rows) or, transposed, block (d, sd ^ 1) (V rows)
+          const int sd = s >> (L - (d + 1));
+          const int bs = trans ? (sd ^ 1) : sd;
+          const LR<T>& b = j.H->blk[Tree::bid(d, bs)];
+          if (b.k == 0) continue;
+          const int so = tr.off[d + 1][sd], sn = tr.sz[d + 1][sd];
+          g.A[g.nseg] = (trans ? b.V : b.U) + (o - so);
+          g.lda[g.nseg] = sn;
+          g.B[g.nseg] = tb[ji][Tree::bid(d, bs)];
+          g.ldb[g.nseg] = b.k;
+          g.k[g.nseg] = b.k;
+          ++g.nseg;
+        }
+        sg.push_back(g);
+      }
+    }
+    ex.seg_gemm<T>(sg);
+    ex.copy<T>(dg);
+    return;
+  }
   std::vector<GemmTask> lv;
   std::vector<CopyTask> dg;
   for (const auto& j : jobs) {

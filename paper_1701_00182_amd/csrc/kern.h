@@ -22,6 +22,25 @@ struct GemmTask {
   int lowp;   // FP32 data only: 1 = BF16, 2 = FP16 matrix-core inputs with panel scaling
 };
 
+// C = alpha * sum_s op_s(A_s) B_s + beta * C: one output block with the inner
+// dimension concatenated from up to kMaxSeg (A, B) segment pairs -- a leaf's
+// rows of H X in one pass (the dense leaf times the leaf's part of X, then each
+// ancestor block's U-slice times that block's V^T X).  op_s transposes A_s when
+// ta has bit s set.
+constexpr int kMaxSeg = 21;
+struct SegGemmTask {
+  void* C;
+  int64_t ldc;
+  int m, n;
+  double alpha, beta;
+  int nseg;
+  unsigned ta;
+  const void* A[kMaxSeg];
+  const void* B[kMaxSeg];
+  int64_t lda[kMaxSeg], ldb[kMaxSeg];
+  int k[kMaxSeg];
+};
+
 // dst = alpha * diag(rs) * src * diag(cs) (+ dst if accumulate); rs / cs may be
 // null; a null src stands for the identity (alpha on the diagonal, 0 elsewhere)
 struct CopyTask {
@@ -161,6 +180,8 @@ enum : int { FLAG_SINGULAR = 0, FLAG_RANK = 1, FLAG_NONFINITE = 2, FLAG_INVALID 
 // variant for FP32 data (0 = FP32 / FP64 inputs)
 template <class T> void launch_gemm_mfma(const GemmTask* d_tasks, const int* d_tile_task, const int* d_first_tile,
                                          int ntiles, int lowp, hipStream_t s);
+template <class T> void launch_seg_gemm(const SegGemmTask* d_tasks, const int* d_tile_task, const int* d_first_tile,
+                                        int ntiles, hipStream_t s);
 template <class T> void launch_copy(const CopyTask* d_tasks, int ntasks, hipStream_t s);
 template <class T> void launch_inverse(const InvTask* d_tasks, int ntasks, int max_s,
                                        int* d_flags, hipStream_t s);

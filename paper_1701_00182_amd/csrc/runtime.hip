@@ -467,6 +467,45 @@ template <class T> void Exec::gemm(const std::vector<GemmTask>& t) {
   }
 }
 
+template <class T> void Exec::seg_gemm(const std::vector<SegGemmTask>& t) {
+  if (t.empty()) return;
+  std::vector<int> first, tile_task;
+  int nt = 0;
+  Work w;
+  w.cls = "seg_gemm";
+  for (size_t i = 0; i < t.size(); ++i) {
+    const SegGemmTask& x = t[i];
+    if (x.nseg < 0 || x.nseg > kMaxSeg || x.m < 0 || x.n < 0) throw Failure(ST_HIP, "bounds check: seg gemm shape");
+    const size_t e = sizeof(T);
+    double ktot = 0;
+    for (int q = 0; q < x.nseg; ++q) {
+      if (x.k[q] < 0) throw Failure(ST_HIP, "bounds check: seg gemm k");
+      const bool ta = (x.ta >> q) & 1;
+      if (checking) {
+        check_range(x.A[q], e * (ta ? ext(x.k[q], x.m, x.lda[q]) : ext(x.m, x.k[q], x.lda[q])), "seg gemm A");
+        check_range(x.B[q], e * ext(x.k[q], x.n, x.ldb[q]), "seg gemm B");
+      }
+      if ((ta ? x.lda[q] < x.k[q] : x.lda[q] < x.m) && x.m * x.k[q] > 0) throw Failure(ST_HIP, "bounds check: seg lda");
+      if (x.ldb[q] < x.k[q] && x.k[q] * x.n > 0) throw Failure(ST_HIP, "bounds check: seg ldb");
+      ktot += x.k[q];
+    }
+    if (checking) check_range(x.C, e * ext(x.m, x.n, x.ldc), "seg gemm C");
+    if (x.ldc < x.m && x.m * x.n > 0) throw Failure(ST_HIP, "bounds check: seg ldc");
+    first.push_back(nt);
+    const int tiles = ((x.m + 63) / 64) * ((x.n + 63) / 64);
+    for (int j = 0; j < tiles; ++j) tile_task.push_back((int)i);
+    nt += tiles;
+    w.flops += 2.0 * x.m * x.n * ktot;
+    w.bytes += e * ((double)x.m * ktot + ktot * x.n + (double)x.m * x.n * (x.beta != 0.0 ? 2 : 1));
+  }
+  flops_gemm += w.flops;
+  if (nt == 0) return;
+  const SegGemmTask* dt = upload(t);
+  const int* dtt = upload(tile_task);
+  const int* dft = upload(first);
+  submit([=](hipStream_t s) { launch_seg_gemm<T>(dt, dtt, dft, nt, s); }, w);
+}
+
 template <class T> void Exec::copy(const std::vector<CopyTask>& t) {
   if (t.empty()) return;
   if (checking)
@@ -877,6 +916,7 @@ template <class T> void Exec::apply_leaf(const std::vector<LeafTask>& t) {
 #define ACR_EXEC_INST(T)                                              \
   template void Exec::gemm<T>(const std::vector<GemmTask>&);          \
   template void Exec::copy<T>(const std::vector<CopyTask>&);          \
+  template void Exec::seg_gemm<T>(const std::vector<SegGemmTask>&);   \
   template void Exec::inverse<T>(const std::vector<InvTask>&);        \
   template void Exec::qr<T>(const std::vector<QrTask>&);              \
   template void Exec::svd<T>(std::vector<SvdTask>&, double, int*);   \
