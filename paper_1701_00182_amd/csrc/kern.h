@@ -182,7 +182,8 @@ template <class T> void launch_gemm_mfma(const GemmTask* d_tasks, const int* d_t
                                          int ntiles, int lowp, hipStream_t s);
 template <class T> void launch_seg_gemm(const SegGemmTask* d_tasks, const int* d_tile_task, const int* d_first_tile,
                                         int ntiles, hipStream_t s);
-template <class T> void launch_copy(const CopyTask* d_tasks, int ntasks, hipStream_t s);
+// units: workgroups per task (each takes (column, 2048-row chunk) units in turn)
+template <class T> void launch_copy(const CopyTask* d_tasks, int ntasks, int units, hipStream_t s);
 template <class T> void launch_inverse(const InvTask* d_tasks, int ntasks, int max_s,
                                        int* d_flags, hipStream_t s);
 // LDS-resident variants; `lds` is the dynamic shared memory per workgroup

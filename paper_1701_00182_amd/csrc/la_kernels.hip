@@ -26,14 +26,23 @@ __global__ __launch_bounds__(256) void k_copy(const CopyTask* __restrict__ tasks
   const T* rs = static_cast<const T*>(t.rs);
   const T* cs = static_cast<const T*>(t.cs);
   const T alpha = T(t.alpha);
-  for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.y * 256) {
-    const int i = (int)(e % t.m), j = (int)(e / t.m);
-    T v = src ? alpha * src[i + (int64_t)j * t.lds] : (i == j ? alpha : T(0));
-    if (rs) v *= rs[i];
-    if (cs) v *= cs[j];
-    T* d = dst + i + (int64_t)j * t.ldd;
-    if (t.accumulate) v += *d;
-    *d = v;
+  // units of (column, 2048-row chunk): one division per unit, none per element
+  const int ich = (t.m + 2047) / 2048;
+  const int64_t units = (int64_t)t.n * ich;
+  (void)total;
+  for (int64_t u = blockIdx.y; u < units; u += gridDim.y) {
+    const int j = (int)(u / ich), i0 = (int)(u % ich) * 2048;
+    const int i1 = t.m < i0 + 2048 ? t.m : i0 + 2048;
+    const T csj = cs ? cs[j] : T(1);
+    const T* sc = src ? src + (int64_t)j * t.lds : nullptr;
+    T* dc = dst + (int64_t)j * t.ldd;
+    for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+      T v = sc ? alpha * sc[i] : (i == j ? alpha : T(0));
+      if (rs) v *= rs[i];
+      v *= csj;
+      if (t.accumulate) v += dc[i];
+      dc[i] = v;
+    }
   }
 }
 
@@ -131,9 +140,9 @@ __global__ __launch_bounds__(NT) void k_inverse(const InvTask* __restrict__ task
 
 
 template <class T>
-void launch_copy(const CopyTask* d_tasks, int ntasks, hipStream_t s) {
+void launch_copy(const CopyTask* d_tasks, int ntasks, int units, hipStream_t s) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_copy<T>, dim3(ntasks, 8), dim3(256), 0, s, d_tasks);
+  hipLaunchKernelGGL(k_copy<T>, dim3(ntasks, units), dim3(256), 0, s, d_tasks);
 }
 
 template <class T>
@@ -157,7 +166,7 @@ void launch_inverse(const InvTask* d_tasks, int ntasks, int max_s, int* d_flags,
 }
 
 #define ACR_INST(T)                                                                              \
-  template void launch_copy<T>(const CopyTask*, int, hipStream_t);                              \
+  template void launch_copy<T>(const CopyTask*, int, int, hipStream_t);                         \
   template void launch_inverse<T>(const InvTask*, int, int, int*, hipStream_t);
 
 ACR_INST(float)

@@ -520,9 +520,12 @@ template <class T> void Exec::copy(const std::vector<CopyTask>& t) {
   Work w;
   w.cls = "copy";
   for (auto& x : t) w.bytes += sizeof(T) * (double)x.m * x.n * ((x.src ? 1 : 0) + 1 + (x.accumulate ? 1 : 0));
+  int64_t units = 1;
+  for (auto& x : t) units = std::max<int64_t>(units, (int64_t)x.n * ((x.m + 2047) / 2048));
+  const int gy = (int)std::min<int64_t>(units, 64);
   const CopyTask* dt = upload(t);
   const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_copy<T>(dt, n, s); }, w);
+  submit([=](hipStream_t s) { launch_copy<T>(dt, n, gy, s); }, w);
 }
 
 template <class T> void Exec::inverse(const std::vector<InvTask>& t) {
