@@ -334,7 +334,40 @@ void hodlr_multivec(Exec& ex, const Tree& tr, const std::vector<MVJob<T>>& jobs,
         }
     }
   }
-  ex.gemm<T>(inner);
+  // Inner products with a long inner dimension (the top blocks: rows = M/2)
+  // and several right-hand sides are split into 512-row pieces whose partial
+  // products are summed in a fixed order, so that the launch has enough tiles.
+  {
+    constexpr int kPiece = 512;
+    std::vector<GemmTask> direct, pieces;
+    std::vector<std::vector<CopyTask>> sums;
+    for (const GemmTask& g : inner) {
+      const int np = (g.k + kPiece - 1) / kPiece;
+      if (np < 2 || g.n < 8 || g.beta != 0.0) {
+        direct.push_back(g);
+        continue;
+      }
+      T* part = scratch.get_n<T>((size_t)np * g.m * g.n);
+      if ((int)sums.size() < np) sums.resize(np);
+      for (int q = 0; q < np; ++q) {
+        const int k0 = q * kPiece, kq = std::min(kPiece, g.k - k0);
+        GemmTask h = g;
+        h.A = static_cast<const T*>(g.A) + (g.ta ? (int64_t)k0 : (int64_t)k0 * g.lda);
+        h.B = static_cast<const T*>(g.B) + (g.tb ? (int64_t)k0 * g.ldb : (int64_t)k0);
+        h.k = kq;
+        h.C = part + (size_t)q * g.m * g.n;
+        h.ldc = g.m;
+        h.alpha = 1.0;
+        h.beta = 0.0;
+        pieces.push_back(h);
+        sums[q].push_back(ctk<T>(part + (size_t)q * g.m * g.n, g.m, static_cast<T*>(g.C), g.ldc, g.m, g.n,
+                                 g.alpha, q > 0 ? 1 : 0));
+      }
+    }
+    direct.insert(direct.end(), pieces.begin(), pieces.end());
+    ex.gemm<T>(direct);
+    for (auto& c : sums) ex.copy<T>(c);   // piece q added after piece q - 1: fixed order
+  }
   // Without correction terms each leaf's rows of Y are formed in one pass: the
   // leaf times X plus every ancestor block's U-slice (V-slice transposed) times
   // its t, concatenated along the inner dimension (Y read and written once).
