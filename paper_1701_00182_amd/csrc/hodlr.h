@@ -162,6 +162,8 @@ class Exec {
   std::vector<void*> oversized_;
   char* h_ring_ = nullptr;
   char* d_ring_ = nullptr;
+  hipStream_t side_ = nullptr;    // second in-order stream for long independent stages
+  hipEvent_t ev_[3] = {nullptr, nullptr, nullptr};
   size_t ring_bytes_ = 0, ring_off_ = 0;
 };
 

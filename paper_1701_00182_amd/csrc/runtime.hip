@@ -261,6 +261,9 @@ void Exec::init(hipStream_t s, const Allocator& a) {
   d_ring_ = static_cast<char*>(dev_alloc(ring_bytes_));
   d_flags = static_cast<int*>(dev_alloc(NFLAGS * sizeof(int)));
   hip_check(hipHostMalloc((void**)&h_flags, NFLAGS * sizeof(int), hipHostMallocDefault), "hipHostMalloc(flags)");
+  // side stream (default priority) for the long global-memory SVD stages
+  if (hipStreamCreateWithFlags(&side_, hipStreamNonBlocking) != hipSuccess) side_ = nullptr;
+  for (hipEvent_t& e : ev_) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
   d_svd_flops = static_cast<unsigned long long*>(dev_alloc(sizeof(unsigned long long)));
   hip_check(hipMemsetAsync(d_svd_flops, 0, sizeof(unsigned long long), stream), "hipMemsetAsync(svd flops)");
   clear_flags();
@@ -287,6 +290,12 @@ void Exec::destroy() {
   if (d_flags) dev_free(d_flags);
   if (d_svd_flops) dev_free(d_svd_flops);
   d_svd_flops = nullptr;
+  if (side_) (void)hipStreamDestroy(side_);
+  side_ = nullptr;
+  for (hipEvent_t& e : ev_) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   h_ring_ = nullptr; h_flags = nullptr; d_ring_ = nullptr; d_flags = nullptr;
 }
 
@@ -314,6 +323,7 @@ void Exec::dev_free(void* p) {
 
 void Exec::sync() {
   hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  if (side_) hip_check(hipStreamSynchronize(side_), "hipStreamSynchronize(side)");
   if (!pending_.empty()) resolve_timings();
 }
 
@@ -653,69 +663,110 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
     else
       submit([=](hipStream_t s) { launch_svd_block<T>(dt, n, delta, eps, fl, lds, s); }, w);
   };
+  // Two-phase cores (pivoted QR, host read of the ranks t, Jacobi on W^T):
+  // those whose C fits in LDS stay on the main stream; the global-memory ones
+  // (few per launch, each one long) run on the side stream so that they overlap
+  // the many small and mid-size cores instead of idling most of the chip.
+  std::vector<SvdTask> two[2];
+  std::vector<int> two_idx[2];
+  for (size_t i = 0; i < big.size(); ++i) {
+    const int g = (side_ && lds_bytes_qrcp(big[i]) > kLdsBudget) ? 1 : 0;
+    two[g].push_back(big[i]);
+    two_idx[g].push_back(big_idx[i]);
+  }
+  for (auto& x : big) flops_svd += 2.0 * x.p * x.q * (double)x.r;
+  auto qrcp_batch = [this, delta](const std::vector<SvdTask>& b, size_t lds) {
+    Work w;
+    w.cls = lds ? "qrcp_lds" : "qrcp";
+    for (auto& x : b) {
+      w.flops += 2.0 * x.p * x.q * (double)x.r;  // forming the core (pivoted QR added below)
+      w.bytes += 8.0 * ((double)x.p + x.q) * x.r + 8.0 * x.q * std::min(x.p, x.q);
+    }
+    const SvdTask* dt = upload(b);
+    const int n = (int)b.size();
+    submit([=](hipStream_t s) { launch_qrcp<T>(dt, n, delta, lds, s); }, w);
+  };
+  auto jacobi_batch = [this, eps, fl](const std::vector<SvdTask>& b, size_t lds) {
+    Work w;
+    w.cls = lds ? "jacobi_lds" : "jacobi";
+    unsigned long long* ctr = g_timing ? counter_slot() : nullptr;
+    std::vector<SvdTask> bb = b;
+    for (auto& x : bb) x.sweep_ctr = ctr;
+    // one pair visit reads two columns of `rows` values, 3 dot products and a
+    // rotation of both: 12 * rows flops (the counter sums rows per visit)
+    w.counter = ctr;
+    w.flops_per_count = 12.0;
+    w.bytes_per_count = 32.0;
+    const SvdTask* dt = upload(bb);
+    const int n = (int)bb.size();
+    submit([=](hipStream_t s) { launch_jacobi<T>(dt, n, eps, fl, lds, s); }, w);
+  };
+  // numerical ranks found by the pivoted QR, read back per stream
+  std::vector<int> tv[2];
+  auto read_ranks = [&](int g) {
+    tv[g].resize(t.size());
+    hip_check(hipMemcpyAsync(tv[g].data(), d_tvals, t.size() * sizeof(int), hipMemcpyDeviceToHost, stream),
+              "hipMemcpyAsync(core ranks)");
+    hip_check(hipEventRecord(ev_[g], stream), "hipEventRecord");
+  };
+  auto rank_stage = [&](int g) {
+    hip_check(hipEventSynchronize(ev_[g]), "hipEventSynchronize(core ranks)");
+    double qf = 0;
+    for (size_t i = 0; i < two[g].size(); ++i) {
+      const int k = tv[g][two_idx[g][i]];
+      two[g][i].tc = k;
+      const double p = two[g][i].p, q = two[g][i].q;
+      qf += 4.0 * p * q * k - 2.0 * (double)k * k * (p + q) + 4.0 / 3.0 * (double)k * k * k;
+    }
+    flops_svd += qf;
+    // the pivoted QR stopped at rank t: add its Householder work to the timing record
+    for (auto it = pending_.rbegin(); it != pending_.rend(); ++it)
+      if (it->w.cls && std::strncmp(it->w.cls, "qrcp", 4) == 0) { it->w.flops += qf; break; }
+  };
+  const bool split = !two[1].empty();
+  if (split) {
+    // side stream: starts after everything submitted so far (the stack QRs)
+    hip_check(hipEventRecord(ev_[2], stream), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(side_, ev_[2], 0), "hipStreamWaitEvent");
+    std::swap(stream, side_);
+    qrcp_batch(two[1], 0);
+    read_ranks(1);
+    std::swap(stream, side_);
+  }
+  // main stream: pivoted QR of the LDS cores first (their ranks come back
+  // early), then the one-workgroup cores
+  bucketed(two[0], [](const SvdTask& x) { return lds_bytes_qrcp(x); }, qrcp_batch);
+  if (!two[0].empty()) read_ranks(0);
   bucketed(small, [](const SvdTask& x) { return lds_bytes_svd_wave(x, sizeof(T)); },
            [&](const std::vector<SvdTask>& b, size_t lds) { fused(b, lds, true); });
   bucketed(mid, [](const SvdTask& x) { return lds_bytes_svd_block(x); },
            [&](const std::vector<SvdTask>& b, size_t lds) { fused(b, lds, false); });
   small.insert(small.end(), mid.begin(), mid.end());
   left(small);
-  if (big.empty()) return;
-  for (auto& x : big) flops_svd += 2.0 * x.p * x.q * (double)x.r;
-  bucketed(big, [](const SvdTask& x) { return lds_bytes_qrcp(x); },
-           [this, delta](const std::vector<SvdTask>& b, size_t lds) {
-             Work w;
-             w.cls = lds ? "qrcp_lds" : "qrcp";
-             for (auto& x : b) {
-               w.flops += 2.0 * x.p * x.q * (double)x.r;  // forming the core (pivoted QR added below)
-               w.bytes += 8.0 * ((double)x.p + x.q) * x.r + 8.0 * x.q * std::min(x.p, x.q);
-             }
-             const SvdTask* dt = upload(b);
-             const int n = (int)b.size();
-             submit([=](hipStream_t s) { launch_qrcp<T>(dt, n, delta, lds, s); }, w);
-           });
-  // numerical ranks of the cores size the Jacobi stage
-  std::vector<int> tv(t.size());
-  hip_check(hipMemcpyAsync(tv.data(), d_tvals, tv.size() * sizeof(int), hipMemcpyDeviceToHost, stream),
-            "hipMemcpyAsync(core ranks)");
-  sync();
-  double qf = 0;
-  for (size_t i = 0; i < big.size(); ++i) {
-    const int k = tv[big_idx[i]];
-    big[i].tc = k;
-    const double p = big[i].p, q = big[i].q;
-    qf += 4.0 * p * q * k - 2.0 * (double)k * k * (p + q) + 4.0 / 3.0 * (double)k * k * k;
+  if (!two[0].empty()) {
+    rank_stage(0);
+    bucketed(two[0], [](const SvdTask& x) { return lds_bytes_jacobi(x); }, jacobi_batch);
+    left(two[0]);
   }
-  flops_svd += qf;
+  if (split) {
+    rank_stage(1);
+    std::swap(stream, side_);
+    bucketed(two[1], [](const SvdTask& x) { return lds_bytes_jacobi(x); }, jacobi_batch);
+    left(two[1]);
+    hip_check(hipEventRecord(ev_[2], stream), "hipEventRecord");
+    std::swap(stream, side_);
+    hip_check(hipStreamWaitEvent(stream, ev_[2], 0), "hipStreamWaitEvent");
+  }
   if (trace) {
-    int mq = 0, mt = 0, nl = 0;
-    for (auto& x : big) {
-      mq = std::max(mq, x.q);
-      mt = std::max(mt, x.tc);
-      nl += lds_bytes_jacobi(x) <= kLdsBudget;
-    }
-    std::fprintf(stderr, "[acr] svd %s fused=%zu big=%zu (jacobi in lds %d) max_q=%d max_t=%d\n", trace_tag, small.size(),
-                 big.size(), nl, mq, mt);
+    int mq = 0, mt = 0;
+    for (int g = 0; g < 2; ++g)
+      for (auto& x : two[g]) {
+        mq = std::max(mq, x.q);
+        mt = std::max(mt, x.tc);
+      }
+    std::fprintf(stderr, "[acr] svd %s fused=%zu two-kernel lds=%zu global=%zu max_q=%d max_t=%d\n", trace_tag,
+                 small.size(), two[0].size(), two[1].size(), mq, mt);
   }
-  // the pivoted QR stopped at rank t: add its Householder work to the timing record
-  for (auto it = pending_.rbegin(); it != pending_.rend(); ++it)
-    if (it->w.cls && std::strncmp(it->w.cls, "qrcp", 4) == 0) { it->w.flops += qf; break; }
-  bucketed(big, [](const SvdTask& x) { return lds_bytes_jacobi(x); },
-           [this, eps, fl](const std::vector<SvdTask>& b, size_t lds) {
-             Work w;
-             w.cls = lds ? "jacobi_lds" : "jacobi";
-             unsigned long long* ctr = g_timing ? counter_slot() : nullptr;
-             std::vector<SvdTask> bb = b;
-             for (auto& x : bb) x.sweep_ctr = ctr;
-             // one pair visit reads two columns of `rows` values, 3 dot products and a
-             // rotation of both: 12 * rows flops (the counter sums rows per visit)
-             w.counter = ctr;
-             w.flops_per_count = 12.0;
-             w.bytes_per_count = 32.0;
-             const SvdTask* dt = upload(bb);
-             const int n = (int)bb.size();
-             submit([=](hipStream_t s) { launch_jacobi<T>(dt, n, eps, fl, lds, s); }, w);
-           });
-  left(big);
 }
 
 template <class T> void Exec::applyq(const std::vector<ApplyQTask>& t) {
