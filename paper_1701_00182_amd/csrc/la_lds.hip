@@ -27,10 +27,15 @@ template <int NT> __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-// lanes per column group for a column length of m
-__device__ inline int lanes_for_rows(int m) {
+// Lanes per column group for one step over `cols` columns of `rows` live rows
+// with nt threads: enough groups to take every column at once (short shuffle
+// reductions, no column queue per group), and enough lanes that a column slice
+// fits kRC registers.
+constexpr int kRC = 16;
+__device__ inline int step_lanes(int rows, int cols, int nt) {
   int G = 4;
-  while (G < 64 && G * 4 < m) G <<= 1;
+  while (G < 64 && 2 * G * cols <= nt) G <<= 1;
+  while (G < 64 && rows > G * kRC) G <<= 1;
   return G;
 }
 
@@ -47,8 +52,6 @@ __global__ __launch_bounds__(NT) void k_qr_lds(const QrTask* __restrict__ tasks)
     for (int e = threadIdx.x; e < m * r; e += NT) a[e] = A[(e % m) + (int64_t)(e / m) * t.lda];
   __shared__ double red[NT / 64];
   __shared__ double sh_sig[2];
-  const int G = lanes_for_rows(m), groups = NT / G;
-  const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   const int nref = m < r ? m : r;
   __syncthreads();
   // sigma_j = squared norm of column j below the diagonal; for j > 0 it comes
@@ -74,24 +77,64 @@ __global__ __launch_bounds__(NT) void k_qr_lds(const QrTask* __restrict__ tasks)
     }
     if (threadIdx.x == 0) tau[j] = T(tj);
     // v = (1, x_{j+1..} * scale) rounded to T as it will be stored, applied to
-    // the trailing columns on the fly
-    for (int c = j + 1 + gi; c < r; c += groups) {
-      T* ac = a + c * la;
-      if (tj != 0.0) {
-        double w = 0.0;
-        for (int i = j + gl; i < m; i += G) w += (i == j ? 1.0 : (double)T((double)col[i] * scale)) * (double)ac[i];
-        w = gsum(w, G) * tj;
-        for (int i = j + gl; i < m; i += G)
-          ac[i] = T((double)ac[i] - w * (i == j ? 1.0 : (double)T((double)col[i] * scale)));
+    // the trailing columns on the fly; each lane's slice of v and of the column
+    // sits in registers when it fits
+    const int G = step_lanes(m - j, r - j - 1, NT), groups = NT / G;
+    const int gi = threadIdx.x / G, gl = threadIdx.x % G;
+    if (m - j <= G * kRC) {
+      double v[kRC];
+#pragma unroll
+      for (int u = 0; u < kRC; ++u) {
+        const int i = j + gl + u * G;
+        v[u] = i < m ? (i == j ? 1.0 : (double)T((double)col[i] * scale)) : 0.0;
       }
-      if (c == j + 1) {
-        double sn = 0.0;
-        for (int i = j + 2 + gl; i < m; i += G) {
-          const double v = (double)ac[i];
-          sn += v * v;
+      for (int c = j + 1 + gi; c < r; c += groups) {
+        T* ac = a + c * la;
+        double x[kRC];
+#pragma unroll
+        for (int u = 0; u < kRC; ++u) {
+          const int i = j + gl + u * G;
+          x[u] = i < m ? (double)ac[i] : 0.0;
         }
-        sn = gsum(sn, G);
-        if (gl == 0) sh_sig[j & 1] = sn;
+        if (tj != 0.0) {
+          double w = 0.0;
+#pragma unroll
+          for (int u = 0; u < kRC; ++u) w += v[u] * x[u];
+          w = gsum(w, G) * tj;
+#pragma unroll
+          for (int u = 0; u < kRC; ++u) {
+            const int i = j + gl + u * G;
+            x[u] = (double)T(x[u] - w * v[u]);
+            if (i < m) ac[i] = T(x[u]);
+          }
+        }
+        if (c == j + 1) {
+          double sn = 0.0;
+#pragma unroll
+          for (int u = 0; u < kRC; ++u) sn += (gl + u * G >= 2) ? x[u] * x[u] : 0.0;
+          sn = gsum(sn, G);
+          if (gl == 0) sh_sig[j & 1] = sn;
+        }
+      }
+    } else {
+      for (int c = j + 1 + gi; c < r; c += groups) {
+        T* ac = a + c * la;
+        if (tj != 0.0) {
+          double w = 0.0;
+          for (int i = j + gl; i < m; i += G) w += (i == j ? 1.0 : (double)T((double)col[i] * scale)) * (double)ac[i];
+          w = gsum(w, G) * tj;
+          for (int i = j + gl; i < m; i += G)
+            ac[i] = T((double)ac[i] - w * (i == j ? 1.0 : (double)T((double)col[i] * scale)));
+        }
+        if (c == j + 1) {
+          double sn = 0.0;
+          for (int i = j + 2 + gl; i < m; i += G) {
+            const double v = (double)ac[i];
+            sn += v * v;
+          }
+          sn = gsum(sn, G);
+          if (gl == 0) sh_sig[j & 1] = sn;
+        }
       }
     }
     __syncthreads();
@@ -126,19 +169,45 @@ __global__ __launch_bounds__(NT) void k_applyq_lds(const ApplyQTask* __restrict_
     const int i = e % m, c = e / m;
     o[i + c * lo] = i < p ? T(t.Z[i + (int64_t)c * t.ldz]) : T(0);
   }
-  const int G = lanes_for_rows(m), groups = NT / G;
-  const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   __syncthreads();
   for (int j = p - 1; j >= 0; --j) {
     const double tj = (double)tau[j];
     if (tj == 0.0) continue;
     const T* vj = v + j * lv;
-    for (int c = gi; c < k; c += groups) {
-      T* oc = o + c * lo;
-      double w = 0.0;
-      for (int i = j + gl; i < m; i += G) w += (i == j ? 1.0 : (double)vj[i]) * (double)oc[i];
-      w = gsum(w, G) * tj;
-      for (int i = j + gl; i < m; i += G) oc[i] = T((double)oc[i] - w * (i == j ? 1.0 : (double)vj[i]));
+    const int G = step_lanes(m - j, k, NT), groups = NT / G;
+    const int gi = threadIdx.x / G, gl = threadIdx.x % G;
+    if (m - j <= G * kRC) {
+      double vr[kRC];
+#pragma unroll
+      for (int u = 0; u < kRC; ++u) {
+        const int i = j + gl + u * G;
+        vr[u] = i < m ? (i == j ? 1.0 : (double)vj[i]) : 0.0;
+      }
+      for (int c = gi; c < k; c += groups) {
+        T* oc = o + c * lo;
+        double x[kRC];
+        double w = 0.0;
+#pragma unroll
+        for (int u = 0; u < kRC; ++u) {
+          const int i = j + gl + u * G;
+          x[u] = i < m ? (double)oc[i] : 0.0;
+          w += vr[u] * x[u];
+        }
+        w = gsum(w, G) * tj;
+#pragma unroll
+        for (int u = 0; u < kRC; ++u) {
+          const int i = j + gl + u * G;
+          if (i < m) oc[i] = T(x[u] - w * vr[u]);
+        }
+      }
+    } else {
+      for (int c = gi; c < k; c += groups) {
+        T* oc = o + c * lo;
+        double w = 0.0;
+        for (int i = j + gl; i < m; i += G) w += (i == j ? 1.0 : (double)vj[i]) * (double)oc[i];
+        w = gsum(w, G) * tj;
+        for (int i = j + gl; i < m; i += G) oc[i] = T((double)oc[i] - w * (i == j ? 1.0 : (double)vj[i]));
+      }
     }
     __syncthreads();
   }

@@ -758,14 +758,21 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
     hip_check(hipStreamWaitEvent(stream, ev_[2], 0), "hipStreamWaitEvent");
   }
   if (trace) {
+    // sweep work of the two-kernel cores (rows q times t^2 columns pairs),
+    // split by the ratio q / t of their rows to their pivoted-QR rank
     int mq = 0, mt = 0;
+    double wk[4] = {0, 0, 0, 0};
     for (int g = 0; g < 2; ++g)
       for (auto& x : two[g]) {
         mq = std::max(mq, x.q);
         mt = std::max(mt, x.tc);
+        const double ratio = x.tc > 0 ? (double)x.q / x.tc : 0.0;
+        wk[ratio < 1.5 ? 0 : ratio < 2.0 ? 1 : ratio < 3.0 ? 2 : 3] += (double)x.q * x.tc * x.tc;
       }
-    std::fprintf(stderr, "[acr] svd %s fused=%zu two-kernel lds=%zu global=%zu max_q=%d max_t=%d\n", trace_tag,
-                 small.size(), two[0].size(), two[1].size(), mq, mt);
+    std::fprintf(stderr,
+                 "[acr] svd %s fused=%zu two-kernel lds=%zu global=%zu max_q=%d max_t=%d "
+                 "sweep work q/t<1.5:%.3g 1.5-2:%.3g 2-3:%.3g >3:%.3g\n",
+                 trace_tag, small.size(), two[0].size(), two[1].size(), mq, mt, wk[0], wk[1], wk[2], wk[3]);
   }
 }
 

@@ -29,6 +29,46 @@ __device__ inline double gsum2(double v, int G) {
   return v;
 }
 
+// Lane exchange inside a row of 16 lanes through the DPP operand modifier
+// (no trip through the LDS crossbar): CTRL 0xB1 / 0x4E swap lanes 1 / 2 apart
+// within a quad, 0x141 mirrors each half row, 0x140 the whole row.
+template <int CTRL> __device__ inline double dpp_mov(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over aligned groups of G lanes (a power of two up to 64); every lane of
+// a group ends with the same bits (each step adds a lane's partial to its
+// partner's, which is commutative).
+__device__ inline double gsum_dpp(double v, int G) {
+  if (G >= 2) v += dpp_mov<0xB1>(v);
+  if (G >= 4) v += dpp_mov<0x4E>(v);
+  if (G >= 8) v += dpp_mov<0x141>(v);
+  if (G >= 16) v += dpp_mov<0x140>(v);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// 1 / sqrt(x) for x > 0 from the hardware estimate and two Newton steps
+// (each squares the relative error).
+__device__ inline double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * fma(-0.5 * x * r, r, 1.5);
+  r = r * fma(-0.5 * x * r, r, 1.5);
+  return r;
+}
+
+// 1 / x from the hardware estimate and two Newton steps.
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
 __device__ inline double wsum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -71,9 +111,15 @@ template <int NT> __device__ inline void block_argmax(double& v, int& i, double*
     if (red[w] > v || (red[w] == v && redi[w] < i)) { v = red[w]; i = redi[w]; }
 }
 
-__device__ inline int lanes_for(int m) {
+// Lanes per column group for one step of a Householder sweep over `cols`
+// trailing columns of `rows` live rows with nt threads: enough groups to take
+// every column at once (short shuffle reductions, no column queue per group),
+// and enough lanes that a column slice fits kQC registers.
+constexpr int kQC = 16;
+__device__ inline int step_lanes(int rows, int cols, int nt) {
   int G = 4;
-  while (G < 64 && G * 4 < m) G <<= 1;
+  while (G < 64 && 2 * G * cols <= nt) G <<= 1;
+  while (G < 64 && rows > G * kQC) G <<= 1;
   return G;
 }
 
@@ -99,18 +145,20 @@ __device__ inline double core_entry(const SvdTask& t, int a, int b) {
 // triangle of the first t rows (the entries below it are left unspecified).
 // All threads call it.
 template <int NT>
-__device__ int qrcp_body(double* C, int64_t lc, int p, int q, double* nrm, int* perm, double delta, double* red,
-                         int* redi) {
+__device__ __forceinline__ int qrcp_body(double* C, int64_t lc, int p, int q, double* nrm, int* perm, double delta,
+                                         double* red, int* redi) {
   const int mn = p < q ? p : q;
-  const int G = lanes_for(p), groups = NT / G;
-  const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   double mx = 0.0;
-  for (int c = gi; c < q; c += groups) {
-    double s = 0.0;
-    for (int i = gl; i < p; i += G) s += C[i + c * lc] * C[i + c * lc];
-    s = gsum2(s, G);
-    if (gl == 0) { nrm[c] = s; perm[c] = c; }
-    mx = fmax(mx, s);
+  {
+    const int G = step_lanes(p, q, NT), groups = NT / G;
+    const int gi = threadIdx.x / G, gl = threadIdx.x % G;
+    for (int c = gi; c < q; c += groups) {
+      double s = 0.0;
+      for (int i = gl; i < p; i += G) s += C[i + c * lc] * C[i + c * lc];
+      s = gsum2(s, G);
+      if (gl == 0) { nrm[c] = s; perm[c] = c; }
+      mx = fmax(mx, s);
+    }
   }
   {
     int dummy = 0;
@@ -158,18 +206,57 @@ __device__ int qrcp_body(double* C, int64_t lc, int p, int q, double* nrm, int* 
       tj = (beta - x0) / beta;
       scale = 1.0 / (x0 - beta);
     }
-    for (int c = j + 1 + gi; c < q; c += groups) {
-      double* ac = C + c * lc;
-      if (tj != 0.0) {
-        double w = 0.0;
-        for (int i = j + gl; i < p; i += G) w += (i == j ? 1.0 : col[i] * scale) * ac[i];
-        w = gsum2(w, G) * tj;
-        for (int i = j + gl; i < p; i += G) ac[i] -= w * (i == j ? 1.0 : col[i] * scale);
+    // trailing columns: group size for this step, each lane's slice of the
+    // reflector and of the column held in registers when it fits
+    const int G = step_lanes(p - j, q - j - 1, NT), groups = NT / G;
+    const int gi = threadIdx.x / G, gl = threadIdx.x % G;
+    if (p - j <= G * kQC) {
+      double v[kQC];
+#pragma unroll
+      for (int u = 0; u < kQC; ++u) {
+        const int i = j + gl + u * G;
+        v[u] = i < p ? (i == j ? 1.0 : col[i] * scale) : 0.0;
       }
-      double s = 0.0;
-      for (int i = j + 1 + gl; i < p; i += G) s += ac[i] * ac[i];
-      s = gsum2(s, G);
-      if (gl == 0) nrm[c] = s;
+      for (int c = j + 1 + gi; c < q; c += groups) {
+        double* ac = C + c * lc;
+        double a[kQC];
+#pragma unroll
+        for (int u = 0; u < kQC; ++u) {
+          const int i = j + gl + u * G;
+          a[u] = i < p ? ac[i] : 0.0;
+        }
+        if (tj != 0.0) {
+          double w = 0.0;
+#pragma unroll
+          for (int u = 0; u < kQC; ++u) w += v[u] * a[u];
+          w = gsum2(w, G) * tj;
+#pragma unroll
+          for (int u = 0; u < kQC; ++u) {
+            const int i = j + gl + u * G;
+            a[u] -= w * v[u];
+            if (i < p) ac[i] = a[u];
+          }
+        }
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < kQC; ++u) s += (j + gl + u * G > j) ? a[u] * a[u] : 0.0;
+        s = gsum2(s, G);
+        if (gl == 0) nrm[c] = s;
+      }
+    } else {
+      for (int c = j + 1 + gi; c < q; c += groups) {
+        double* ac = C + c * lc;
+        if (tj != 0.0) {
+          double w = 0.0;
+          for (int i = j + gl; i < p; i += G) w += (i == j ? 1.0 : col[i] * scale) * ac[i];
+          w = gsum2(w, G) * tj;
+          for (int i = j + gl; i < p; i += G) ac[i] -= w * (i == j ? 1.0 : col[i] * scale);
+        }
+        double s = 0.0;
+        for (int i = j + 1 + gl; i < p; i += G) s += ac[i] * ac[i];
+        s = gsum2(s, G);
+        if (gl == 0) nrm[c] = s;
+      }
     }
     __syncthreads();
     // every thread has read x0 and the column: the diagonal of R can be stored
@@ -212,88 +299,154 @@ __global__ __launch_bounds__(NT) void k_qrcp(const SvdTask* __restrict__ tasks, 
   if (threadIdx.x == 0) *t.t_out = tcount;
 }
 
-// Jacobi rotation of the vector pair (x, y) that zeroes their inner product;
-// false when the pair is already orthogonal to the tolerance.
+// Jacobi rotation of the vector pair (x, y) with squared norms al, be and
+// inner product ga that zeroes the inner product; false when the pair is
+// already orthogonal to the tolerance, |ga| <= tol sqrt(al be).  The tangent
+// of the smaller angle, t = sign(z) / (|z| + sqrt(1 + z^2)) with
+// z = (be - al) / (2 ga), is t = s w / (|d| + h) with d = be - al, w = 2 |ga|,
+// h = sqrt(d^2 + w^2) and s = sign(z); so cos = c' / r and sin = s w / r with
+// c' = |d| + h and r = sqrt(c'^2 + w^2).  d and w are first scaled by a power
+// of two that brings the larger to [0.5, 1), which keeps every square in range
+// and both roots away from zero.
 __device__ inline bool jacobi_rotation(double al, double be, double ga, double tol, double& cs, double& sn) {
-  if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al * be))) return false;
-  const double zeta = (be - al) / (2.0 * ga);
-  double tt;
-  if (fabs(zeta) > 1e150) tt = 0.5 / zeta;
-  else tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  cs = 1.0 / sqrt(1.0 + tt * tt);
-  sn = cs * tt;
+  if (ga == 0.0 || !(ga * ga > tol * tol * (al * be))) return false;
+  const double dd = be - al, w0 = 2.0 * fabs(ga);
+  int e;
+  (void)frexp(fmax(fabs(dd), w0), &e);
+  const double d = ldexp(fabs(dd), -e), w = ldexp(w0, -e);
+  const double h2 = fma(d, d, w * w);
+  const double cp = d + h2 * rsqrt_nr(h2);
+  const double r = rsqrt_nr(fma(cp, cp, w * w));
+  // sign(z) = sign(d) sign(ga), and +1 for d = 0
+  const bool neg = (dd < 0.0) != (ga < 0.0) && dd != 0.0;
+  cs = cp * r;
+  sn = neg ? -(w * r) : w * r;
   return true;
 }
 
 // Indices of pair pi in round `round` of the cyclic tournament over ne (even)
-// vectors: vector 0 stays, the others shift by one position per round.
+// vectors: vector 0 stays at position 0, position p >= 1 holds vector
+// ((p - 1 + round) mod (ne - 1)) + 1; the sum is below 2 (ne - 1), so the
+// modulo is one conditional subtraction.
 __device__ inline void tournament_pair(int pi, int round, int ne, int& ia, int& ib) {
-  const int pa = pi, pb = ne - 1 - pi;
-  ia = pa == 0 ? 0 : ((pa - 1 + round) % (ne - 1)) + 1;
-  ib = pb == 0 ? 0 : ((pb - 1 + round) % (ne - 1)) + 1;
-  if (ia > ib) { const int tmp = ia; ia = ib; ib = tmp; }
+  const int m = ne - 1;
+  int xa = pi - 1 + round, xb = ne - 2 - pi + round;
+  xa -= xa >= m ? m : 0;
+  xb -= xb >= m ? m : 0;
+  const int a = pi == 0 ? 0 : xa + 1, b = xb + 1;
+  ia = a < b ? a : b;
+  ib = a < b ? b : a;
+}
+
+// Squared |cos| of a pair (its normalised inner product), for the stopping rule.
+__device__ inline double pair_cos2(double al, double be, double ga) {
+  const double ab = al * be;
+  return ab > 0.0 ? ga * ga * rcp_nr(ab) : 0.0;
 }
 
 // One Jacobi step on the vector pair (xa, xb) of length len (element i at
 // index i * st), handled by the G lanes of a group (gl = lane in group): the
-// three inner products, the rotation and its application.  Vectors of up to
-// G * kJR elements stay in registers between the products and the update.
-// Returns whether a rotation was applied; cmax takes the pair's |cos| (the
-// normalised inner product before the rotation).
-constexpr int kJR = 12;
-__device__ inline double pair_cos(double al, double be, double ga) {
-  return al > 0.0 && be > 0.0 ? fabs(ga) / sqrt(al * be) : 0.0;
-}
-__device__ inline bool jacobi_pair(double* xa, double* xb, int st, int len, int G, int gl, double tol, double& cmax) {
+// three inner products, the rotation and its application.  With NU > 0 every
+// lane holds NU = ceil(len / G) elements of each vector in registers between
+// the products and the update, and the loops unroll without branches: rows of
+// lanes before the last are full, the last one loads through a clamped index
+// and stores under a mask.  NU = 0 streams the vectors twice.  Returns whether
+// a rotation was applied; cmax2 takes the pair's squared |cos| before it.
+template <int NU>
+__device__ __forceinline__ bool jacobi_pair(double* xa, double* xb, int st, int len, int G, int gl, double tol,
+                                   double& cmax2) {
   double al = 0.0, be = 0.0, ga = 0.0;
-  if (len <= G * kJR) {
-    double xr[kJR], yr[kJR];
-#pragma unroll
-    for (int u = 0; u < kJR; ++u) {
-      const int i = gl + u * G;
-      xr[u] = i < len ? xa[i * st] : 0.0;
-      yr[u] = i < len ? xb[i * st] : 0.0;
+  if (NU == 0) {
+    for (int i = gl; i < len; i += G) {
+      const double x = xa[i * st], y = xb[i * st];
+      al += x * x;
+      be += y * y;
+      ga += x * y;
     }
-#pragma unroll
-    for (int u = 0; u < kJR; ++u) {
-      al += xr[u] * xr[u];
-      be += yr[u] * yr[u];
-      ga += xr[u] * yr[u];
-    }
-    al = gsum2(al, G);
-    be = gsum2(be, G);
-    ga = gsum2(ga, G);
-    cmax = fmax(cmax, pair_cos(al, be, ga));
+    al = gsum_dpp(al, G);
+    be = gsum_dpp(be, G);
+    ga = gsum_dpp(ga, G);
+    cmax2 = fmax(cmax2, pair_cos2(al, be, ga));
     double cs, sn;
     if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
-#pragma unroll
-    for (int u = 0; u < kJR; ++u) {
-      const int i = gl + u * G;
-      if (i < len) {
-        xa[i * st] = cs * xr[u] - sn * yr[u];
-        xb[i * st] = sn * xr[u] + cs * yr[u];
-      }
+    for (int i = gl; i < len; i += G) {
+      const double x = xa[i * st], y = xb[i * st];
+      xa[i * st] = cs * x - sn * y;
+      xb[i * st] = sn * x + cs * y;
     }
     return true;
   }
-  for (int i = gl; i < len; i += G) {
-    const double x = xa[i * st], y = xb[i * st];
-    al += x * x;
-    be += y * y;
-    ga += x * y;
+  constexpr int R = NU > 0 ? NU : 1;
+  double xr[R], yr[R];
+  const int il = gl + (R - 1) * G;
+  const bool tail_ok = il < len;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    if (u + 1 < R) {
+      xr[u] = xa[(gl + u * G) * st];
+      yr[u] = xb[(gl + u * G) * st];
+    } else {
+      const int ic = tail_ok ? il : len - 1;
+      const double x = xa[ic * st], y = xb[ic * st];
+      xr[u] = tail_ok ? x : 0.0;
+      yr[u] = tail_ok ? y : 0.0;
+    }
   }
-  al = gsum2(al, G);
-  be = gsum2(be, G);
-  ga = gsum2(ga, G);
-  cmax = fmax(cmax, pair_cos(al, be, ga));
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    al = fma(xr[u], xr[u], al);
+    be = fma(yr[u], yr[u], be);
+    ga = fma(xr[u], yr[u], ga);
+  }
+  al = gsum_dpp(al, G);
+  be = gsum_dpp(be, G);
+  ga = gsum_dpp(ga, G);
+  cmax2 = fmax(cmax2, pair_cos2(al, be, ga));
   double cs, sn;
   if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
-  for (int i = gl; i < len; i += G) {
-    const double x = xa[i * st], y = xb[i * st];
-    xa[i * st] = cs * x - sn * y;
-    xb[i * st] = sn * x + cs * y;
+#pragma unroll
+  for (int u = 0; u + 1 < R; ++u) {
+    xa[(gl + u * G) * st] = cs * xr[u] - sn * yr[u];
+    xb[(gl + u * G) * st] = sn * xr[u] + cs * yr[u];
+  }
+  if (tail_ok) {
+    xa[il * st] = cs * xr[R - 1] - sn * yr[R - 1];
+    xb[il * st] = sn * xr[R - 1] + cs * yr[R - 1];
   }
   return true;
+}
+
+// The sweeps of jacobi_svd for NU elements per lane (0: streamed); returns
+// the number of sweeps run.
+template <int NT, int NU>
+__device__ __forceinline__ int jacobi_sweeps(double* V, int64_t vs, int64_t es, int n, int len, int G, double tol, double* red,
+                             int* redi) {
+  const int ne = n + (n & 1), npairs = ne / 2;
+  const int groups = NT / G;
+  const int gi = threadIdx.x / G, gl = threadIdx.x % G;
+  int sweeps = 0;
+  // Sweeps end when one applies no rotation, or when its largest |cos| was at
+  // most sqrt(tol): convergence is quadratic there, so the pairs are left
+  // orthogonal to about tol and the confirming sweep is skipped.
+  for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
+    ++sweeps;
+    int rot = 0;
+    double cmax2 = 0.0;
+    for (int round = 0; round < ne - 1; ++round) {
+      for (int pi = gi; pi < npairs; pi += groups) {
+        int ia, ib;
+        tournament_pair(pi, round, ne, ia, ib);
+        if (ib >= n) continue;
+        if (jacobi_pair<NU>(V + ia * vs, V + ib * vs, (int)es, len, G, gl, tol, cmax2)) rot = 1;
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rot)) break;
+    int dummy = 0;
+    block_argmax<NT>(cmax2, dummy, red, redi);
+    if (cmax2 <= tol) break;
+  }
+  return sweeps;
 }
 
 // One-sided Jacobi SVD of n vectors of length len: vector i starts at V + i * vs
@@ -304,39 +457,34 @@ __device__ inline bool jacobi_pair(double* xa, double* xb, int st, int len, int 
 // is n ints of scratch, red / redi one slot per wavefront.  Groups have at
 // least min_g lanes (16 keeps global-memory vectors coalesced).  Returns k;
 // all threads call it.
-template <int NT>
-__device__ int jacobi_svd(double* V, int64_t vs, int64_t es, int n, int len, const int* perm, double* sig, int* ord,
-                          double eps, const SvdTask& t, int* flags, double* red, int* redi, int& sweeps,
-                          int min_g = 1) {
+template <int NT, int min_g = 1>
+__device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int n, int len, const int* perm,
+                                          double* sig, int* ord, double eps, const SvdTask& t, int* flags,
+                                          double* red, int* redi, int& sweeps) {
   const int ne = n + (n & 1), npairs = ne / 2;
-  int G = 64;
+  // lanes per pair: up to one row of 16 (sums through DPP), fewer when that
+  // takes every pair of a round in one pass; min_g keeps global-memory
+  // vectors coalesced
+  int G = min_g > 16 ? min_g : 16;
   while (G > min_g && G * npairs > NT) G >>= 1;
   while (G > 1 && G > 2 * len) G >>= 1;
   const int groups = NT / G;
   const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   const double tol = fmax(1e-15, 2.3e-16 * (double)len);
-  sweeps = 0;
-  // Sweeps end when one applies no rotation, or when its largest |cos| was at
-  // most sqrt(tol): convergence is quadratic there, so the pairs are left
-  // orthogonal to about tol and the confirming sweep is skipped.
-  const double stop_cos = sqrt(tol);
-  for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
-    ++sweeps;
-    int rot = 0;
-    double cmax = 0.0;
-    for (int round = 0; round < ne - 1; ++round) {
-      for (int pi = gi; pi < npairs; pi += groups) {
-        int ia, ib;
-        tournament_pair(pi, round, ne, ia, ib);
-        if (ib >= n) continue;
-        if (jacobi_pair(V + ia * vs, V + ib * vs, (int)es, len, G, gl, tol, cmax)) rot = 1;
-      }
-      __syncthreads();
-    }
-    if (!__syncthreads_or(rot)) break;
-    int dummy = 0;
-    block_argmax<NT>(cmax, dummy, red, redi);
-    if (cmax <= stop_cos) break;
+  // register-resident slices of up to 12 elements per lane in workgroups of
+  // 256 or more threads (at most 128 registers, so that several workgroups
+  // share a compute unit; 8 when the vectors are in global memory), 16 in a
+  // single wavefront
+  constexpr int kCap = NT >= 256 ? (min_g > 1 ? 8 : 12) : 16;
+  const int nu = (len + G - 1) / G;
+  switch (nu <= kCap ? nu : 0) {
+#define ACR_JAC_NU(k) \
+  case k: sweeps = jacobi_sweeps<NT, (k <= kCap ? k : 0)>(V, vs, es, n, len, G, tol, red, redi); break;
+    ACR_JAC_NU(1) ACR_JAC_NU(2) ACR_JAC_NU(3) ACR_JAC_NU(4) ACR_JAC_NU(5) ACR_JAC_NU(6) ACR_JAC_NU(7)
+    ACR_JAC_NU(8) ACR_JAC_NU(9) ACR_JAC_NU(10) ACR_JAC_NU(11) ACR_JAC_NU(12) ACR_JAC_NU(13) ACR_JAC_NU(14)
+    ACR_JAC_NU(15) ACR_JAC_NU(16)
+#undef ACR_JAC_NU
+    default: sweeps = jacobi_sweeps<NT, 0>(V, vs, es, n, len, G, tol, red, redi); break;
   }
   for (int i = gi; i < n; i += groups) {
     const double* x = V + i * vs;
@@ -407,8 +555,8 @@ __global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks
   __syncthreads();
   int sweeps = 0;
   // the pivot order is no longer needed: its workspace holds the sigma ranks
-  const int k = jacobi_svd<NT>(A, rows, 1, n, rows, nullptr, t.sig, t.perm, eps, t, flags, red, redi, sweeps,
-                               LDS ? 1 : 16);
+  const int k = jacobi_svd<NT, LDS ? 1 : 16>(A, rows, 1, n, rows, nullptr, t.sig, t.perm, eps, t, flags, red,
+                                             redi, sweeps);
   if (threadIdx.x == 0) {
     *t.rank_out = k;
     const unsigned long long visits =
