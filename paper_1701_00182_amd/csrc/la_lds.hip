@@ -6,15 +6,11 @@
 #include <cmath>
 
 #include "kern.h"
+#include "wave.h"
 
 namespace acr {
 
 namespace {
-
-__device__ inline double gsum(double v, int G) {
-  for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
-  return v;
-}
 
 template <int NT> __device__ inline double block_sum(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -30,14 +26,134 @@ template <int NT> __device__ inline double block_sum(double v, double* red) {
 // Lanes per column group for one step over `cols` columns of `rows` live rows
 // with nt threads: enough groups to take every column at once (short shuffle
 // reductions, no column queue per group), and enough lanes that a column slice
-// fits kRC registers.
-constexpr int kRC = 16;
-__device__ inline int step_lanes(int rows, int cols, int nt) {
+// fits `cap` registers (16 for panels in LDS, 8 in global memory, whose 64-bit
+// addresses take more registers).
+__device__ inline int step_lanes(int rows, int cols, int nt, int cap) {
   int G = 4;
   while (G < 64 && 2 * G * cols <= nt) G <<= 1;
-  while (G < 64 && rows > G * kRC) G <<= 1;
+  while (G < 64 && rows > G * cap) G <<= 1;
   return G;
 }
+
+// Reflector j, v = (1, T(x_{j+1..} * scale)) with factor tj, applied to the
+// trailing columns j+1.. of the panel a (m rows, column stride la) by groups
+// of G lanes; the group that updates column j+1 also leaves the squared norm
+// of its rows j+2.. in *sig_next.  With NU > 0 each lane holds
+// NU = ceil((m - j) / G) rows of v and of the column in registers and the
+// loops unroll without branches (rows of lanes before the last are full, the
+// last loads through a clamped index and stores under a mask); NU = 0
+// streams the rows.
+template <class T, int NT, int NU>
+__device__ __forceinline__ void qr_update(T* a, int64_t la, int m, int r, int j, const T* col, double scale,
+                                          double tj, int G, double* sig_next) {
+  const int groups = NT / G, gi = threadIdx.x / G, gl = threadIdx.x % G;
+  if (NU == 0) {
+    for (int c = j + 1 + gi; c < r; c += groups) {
+      T* ac = a + c * la;
+      if (tj != 0.0) {
+        double w = 0.0;
+        for (int i = j + gl; i < m; i += G) w += (i == j ? 1.0 : (double)T((double)col[i] * scale)) * (double)ac[i];
+        w = gsum_dpp(w, G) * tj;
+        for (int i = j + gl; i < m; i += G)
+          ac[i] = T((double)ac[i] - w * (i == j ? 1.0 : (double)T((double)col[i] * scale)));
+      }
+      if (c == j + 1) {
+        double sn = 0.0;
+        for (int i = j + 2 + gl; i < m; i += G) {
+          const double v = (double)ac[i];
+          sn += v * v;
+        }
+        sn = gsum_dpp(sn, G);
+        if (gl == 0) *sig_next = sn;
+      }
+    }
+    return;
+  }
+  constexpr int R = NU > 0 ? NU : 1;
+  const int il = j + gl + (R - 1) * G;
+  const bool tail_ok = il < m;
+  const int ic = tail_ok ? il : j;
+  double v[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const double x = (double)(u + 1 < R ? col[j + gl + u * G] : col[ic]);
+    const double vv = (u == 0 && gl == 0) ? 1.0 : (double)T(x * scale);
+    v[u] = (u + 1 < R || tail_ok) ? vv : 0.0;
+  }
+  for (int c = j + 1 + gi; c < r; c += groups) {
+    T* ac = a + c * la;
+    double x[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const double y = (double)(u + 1 < R ? ac[j + gl + u * G] : ac[ic]);
+      x[u] = (u + 1 < R || tail_ok) ? y : 0.0;
+    }
+    if (tj != 0.0) {
+      double w = 0.0;
+#pragma unroll
+      for (int u = 0; u < R; ++u) w = fma(v[u], x[u], w);
+      w = gsum_dpp(w, G) * tj;
+#pragma unroll
+      for (int u = 0; u < R; ++u) x[u] = (double)T(x[u] - w * v[u]);
+#pragma unroll
+      for (int u = 0; u + 1 < R; ++u) ac[j + gl + u * G] = T(x[u]);
+      if (tail_ok) ac[il] = T(x[R - 1]);
+    }
+    if (c == j + 1) {
+      double sn = 0.0;
+#pragma unroll
+      for (int u = 0; u < R; ++u) sn = (u == 0 && gl < 2) ? sn : fma(x[u], x[u], sn);
+      sn = gsum_dpp(sn, G);
+      if (gl == 0) *sig_next = sn;
+    }
+  }
+}
+
+// Reflector j (vj, factor tj) applied to the k columns of o (m rows, column
+// stride lo), rows j..m-1; same register scheme as qr_update.
+template <class T, int NT, int NU>
+__device__ __forceinline__ void applyq_update(T* o, int64_t lo, int m, int k, int j, const T* vj, double tj,
+                                              int G) {
+  const int groups = NT / G, gi = threadIdx.x / G, gl = threadIdx.x % G;
+  if (NU == 0) {
+    for (int c = gi; c < k; c += groups) {
+      T* oc = o + c * lo;
+      double w = 0.0;
+      for (int i = j + gl; i < m; i += G) w += (i == j ? 1.0 : (double)vj[i]) * (double)oc[i];
+      w = gsum_dpp(w, G) * tj;
+      for (int i = j + gl; i < m; i += G) oc[i] = T((double)oc[i] - w * (i == j ? 1.0 : (double)vj[i]));
+    }
+    return;
+  }
+  constexpr int R = NU > 0 ? NU : 1;
+  const int il = j + gl + (R - 1) * G;
+  const bool tail_ok = il < m;
+  const int ic = tail_ok ? il : j;
+  double v[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const double x = (double)(u + 1 < R ? vj[j + gl + u * G] : vj[ic]);
+    const double vv = (u == 0 && gl == 0) ? 1.0 : x;
+    v[u] = (u + 1 < R || tail_ok) ? vv : 0.0;
+  }
+  for (int c = gi; c < k; c += groups) {
+    T* oc = o + c * lo;
+    double x[R];
+    double w = 0.0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const double y = (double)(u + 1 < R ? oc[j + gl + u * G] : oc[ic]);
+      x[u] = (u + 1 < R || tail_ok) ? y : 0.0;
+      w = fma(v[u], x[u], w);
+    }
+    w = gsum_dpp(w, G) * tj;
+#pragma unroll
+    for (int u = 0; u + 1 < R; ++u) oc[j + gl + u * G] = T(x[u] - w * v[u]);
+    if (tail_ok) oc[il] = T(x[R - 1] - w * v[R - 1]);
+  }
+}
+
+#define ACR_NU_CASES(M) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16)
 
 template <class T, bool LDS, int NT>
 __global__ __launch_bounds__(NT) void k_qr_lds(const QrTask* __restrict__ tasks) {
@@ -77,65 +193,17 @@ __global__ __launch_bounds__(NT) void k_qr_lds(const QrTask* __restrict__ tasks)
     }
     if (threadIdx.x == 0) tau[j] = T(tj);
     // v = (1, x_{j+1..} * scale) rounded to T as it will be stored, applied to
-    // the trailing columns on the fly; each lane's slice of v and of the column
-    // sits in registers when it fits
-    const int G = step_lanes(m - j, r - j - 1, NT), groups = NT / G;
-    const int gi = threadIdx.x / G, gl = threadIdx.x % G;
-    if (m - j <= G * kRC) {
-      double v[kRC];
-#pragma unroll
-      for (int u = 0; u < kRC; ++u) {
-        const int i = j + gl + u * G;
-        v[u] = i < m ? (i == j ? 1.0 : (double)T((double)col[i] * scale)) : 0.0;
-      }
-      for (int c = j + 1 + gi; c < r; c += groups) {
-        T* ac = a + c * la;
-        double x[kRC];
-#pragma unroll
-        for (int u = 0; u < kRC; ++u) {
-          const int i = j + gl + u * G;
-          x[u] = i < m ? (double)ac[i] : 0.0;
-        }
-        if (tj != 0.0) {
-          double w = 0.0;
-#pragma unroll
-          for (int u = 0; u < kRC; ++u) w += v[u] * x[u];
-          w = gsum(w, G) * tj;
-#pragma unroll
-          for (int u = 0; u < kRC; ++u) {
-            const int i = j + gl + u * G;
-            x[u] = (double)T(x[u] - w * v[u]);
-            if (i < m) ac[i] = T(x[u]);
-          }
-        }
-        if (c == j + 1) {
-          double sn = 0.0;
-#pragma unroll
-          for (int u = 0; u < kRC; ++u) sn += (gl + u * G >= 2) ? x[u] * x[u] : 0.0;
-          sn = gsum(sn, G);
-          if (gl == 0) sh_sig[j & 1] = sn;
-        }
-      }
-    } else {
-      for (int c = j + 1 + gi; c < r; c += groups) {
-        T* ac = a + c * la;
-        if (tj != 0.0) {
-          double w = 0.0;
-          for (int i = j + gl; i < m; i += G) w += (i == j ? 1.0 : (double)T((double)col[i] * scale)) * (double)ac[i];
-          w = gsum(w, G) * tj;
-          for (int i = j + gl; i < m; i += G)
-            ac[i] = T((double)ac[i] - w * (i == j ? 1.0 : (double)T((double)col[i] * scale)));
-        }
-        if (c == j + 1) {
-          double sn = 0.0;
-          for (int i = j + 2 + gl; i < m; i += G) {
-            const double v = (double)ac[i];
-            sn += v * v;
-          }
-          sn = gsum(sn, G);
-          if (gl == 0) sh_sig[j & 1] = sn;
-        }
-      }
+    // the trailing columns on the fly
+    constexpr int kCap = LDS ? 16 : 8;
+    const int G = step_lanes(m - j, r - j - 1, NT, kCap);
+    double* sn = &sh_sig[j & 1];
+    const int nu = (m - j + G - 1) / G;
+    switch (nu <= kCap ? nu : 0) {
+#define ACR_QR_CASE(k) \
+  case k: qr_update<T, NT, (k <= kCap ? k : 0)>(a, la, m, r, j, col, scale, tj, G, sn); break;
+      ACR_NU_CASES(ACR_QR_CASE)
+#undef ACR_QR_CASE
+      default: qr_update<T, NT, 0>(a, la, m, r, j, col, scale, tj, G, sn); break;
     }
     __syncthreads();
     // column j is no longer read: store its reflector and the diagonal of R
@@ -174,40 +242,15 @@ __global__ __launch_bounds__(NT) void k_applyq_lds(const ApplyQTask* __restrict_
     const double tj = (double)tau[j];
     if (tj == 0.0) continue;
     const T* vj = v + j * lv;
-    const int G = step_lanes(m - j, k, NT), groups = NT / G;
-    const int gi = threadIdx.x / G, gl = threadIdx.x % G;
-    if (m - j <= G * kRC) {
-      double vr[kRC];
-#pragma unroll
-      for (int u = 0; u < kRC; ++u) {
-        const int i = j + gl + u * G;
-        vr[u] = i < m ? (i == j ? 1.0 : (double)vj[i]) : 0.0;
-      }
-      for (int c = gi; c < k; c += groups) {
-        T* oc = o + c * lo;
-        double x[kRC];
-        double w = 0.0;
-#pragma unroll
-        for (int u = 0; u < kRC; ++u) {
-          const int i = j + gl + u * G;
-          x[u] = i < m ? (double)oc[i] : 0.0;
-          w += vr[u] * x[u];
-        }
-        w = gsum(w, G) * tj;
-#pragma unroll
-        for (int u = 0; u < kRC; ++u) {
-          const int i = j + gl + u * G;
-          if (i < m) oc[i] = T(x[u] - w * vr[u]);
-        }
-      }
-    } else {
-      for (int c = gi; c < k; c += groups) {
-        T* oc = o + c * lo;
-        double w = 0.0;
-        for (int i = j + gl; i < m; i += G) w += (i == j ? 1.0 : (double)vj[i]) * (double)oc[i];
-        w = gsum(w, G) * tj;
-        for (int i = j + gl; i < m; i += G) oc[i] = T((double)oc[i] - w * (i == j ? 1.0 : (double)vj[i]));
-      }
+    constexpr int kCap = LDS ? 16 : 8;
+    const int G = step_lanes(m - j, k, NT, kCap);
+    const int nu = (m - j + G - 1) / G;
+    switch (nu <= kCap ? nu : 0) {
+#define ACR_AQ_CASE(kk) \
+  case kk: applyq_update<T, NT, (kk <= kCap ? kk : 0)>(o, lo, m, k, j, vj, tj, G); break;
+      ACR_NU_CASES(ACR_AQ_CASE)
+#undef ACR_AQ_CASE
+      default: applyq_update<T, NT, 0>(o, lo, m, k, j, vj, tj, G); break;
     }
     __syncthreads();
   }

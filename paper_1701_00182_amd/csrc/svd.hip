@@ -19,6 +19,7 @@
 #include <cmath>
 
 #include "kern.h"
+#include "wave.h"
 
 namespace acr {
 
@@ -26,29 +27,6 @@ namespace {
 
 __device__ inline double gsum2(double v, int G) {
   for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
-  return v;
-}
-
-// Lane exchange inside a row of 16 lanes through the DPP operand modifier
-// (no trip through the LDS crossbar): CTRL 0xB1 / 0x4E swap lanes 1 / 2 apart
-// within a quad, 0x141 mirrors each half row, 0x140 the whole row.
-template <int CTRL> __device__ inline double dpp_mov(double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
-// Sum over aligned groups of G lanes (a power of two up to 64); every lane of
-// a group ends with the same bits (each step adds a lane's partial to its
-// partner's, which is commutative).
-__device__ inline double gsum_dpp(double v, int G) {
-  if (G >= 2) v += dpp_mov<0xB1>(v);
-  if (G >= 4) v += dpp_mov<0x4E>(v);
-  if (G >= 8) v += dpp_mov<0x141>(v);
-  if (G >= 16) v += dpp_mov<0x140>(v);
-  if (G >= 32) v += __shfl_xor(v, 16, 64);
-  if (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
@@ -114,12 +92,11 @@ template <int NT> __device__ inline void block_argmax(double& v, int& i, double*
 // Lanes per column group for one step of a Householder sweep over `cols`
 // trailing columns of `rows` live rows with nt threads: enough groups to take
 // every column at once (short shuffle reductions, no column queue per group),
-// and enough lanes that a column slice fits kQC registers.
-constexpr int kQC = 16;
-__device__ inline int step_lanes(int rows, int cols, int nt) {
+// and enough lanes that a column slice fits `cap` registers.
+__device__ inline int step_lanes(int rows, int cols, int nt, int cap) {
   int G = 4;
   while (G < 64 && 2 * G * cols <= nt) G <<= 1;
-  while (G < 64 && rows > G * kQC) G <<= 1;
+  while (G < 64 && rows > G * cap) G <<= 1;
   return G;
 }
 
@@ -139,18 +116,84 @@ __device__ inline double core_entry(const SvdTask& t, int a, int b) {
   return acc;
 }
 
+// Reflector j of the pivoted QR, v = (1, x_{j+1..} * scale) with factor tj,
+// applied to the trailing columns j+1.. of C (groups of G lanes, one column
+// per group at a time), and the squared norms of their rows j+1.. written to
+// nrm.  With NU > 0 each lane holds NU = ceil((p - j) / G) rows of v and of
+// the column in registers and the loops unroll without branches: rows of
+// lanes before the last are full, the last one loads through a clamped index
+// and stores under a mask.  NU = 0 streams the rows.
+template <int NT, int NU>
+__device__ __forceinline__ void qrcp_update(double* C, int64_t lc, int p, int q, int j, const double* col,
+                                            double scale, double tj, int G, double* nrm) {
+  const int groups = NT / G, gi = threadIdx.x / G, gl = threadIdx.x % G;
+  if (NU == 0) {
+    for (int c = j + 1 + gi; c < q; c += groups) {
+      double* ac = C + c * lc;
+      if (tj != 0.0) {
+        double w = 0.0;
+        for (int i = j + gl; i < p; i += G) w += (i == j ? 1.0 : col[i] * scale) * ac[i];
+        w = gsum_dpp(w, G) * tj;
+        for (int i = j + gl; i < p; i += G) ac[i] -= w * (i == j ? 1.0 : col[i] * scale);
+      }
+      double s = 0.0;
+      for (int i = j + 1 + gl; i < p; i += G) s += ac[i] * ac[i];
+      s = gsum_dpp(s, G);
+      if (gl == 0) nrm[c] = s;
+    }
+    return;
+  }
+  constexpr int R = NU > 0 ? NU : 1;
+  const int il = j + gl + (R - 1) * G;
+  const bool tail_ok = il < p;
+  const int ic = tail_ok ? il : j;
+  double v[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const double x = u + 1 < R ? col[j + gl + u * G] : col[ic];
+    const double vv = (u == 0 && gl == 0) ? 1.0 : x * scale;
+    v[u] = (u + 1 < R || tail_ok) ? vv : 0.0;
+  }
+  for (int c = j + 1 + gi; c < q; c += groups) {
+    double* ac = C + c * lc;
+    double a[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const double x = u + 1 < R ? ac[j + gl + u * G] : ac[ic];
+      a[u] = (u + 1 < R || tail_ok) ? x : 0.0;
+    }
+    if (tj != 0.0) {
+      double w = 0.0;
+#pragma unroll
+      for (int u = 0; u < R; ++u) w = fma(v[u], a[u], w);
+      w = gsum_dpp(w, G) * tj;
+#pragma unroll
+      for (int u = 0; u < R; ++u) a[u] = fma(-w, v[u], a[u]);
+#pragma unroll
+      for (int u = 0; u + 1 < R; ++u) ac[j + gl + u * G] = a[u];
+      if (tail_ok) ac[il] = a[R - 1];
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) s = (u == 0 && gl == 0) ? s : fma(a[u], a[u], s);
+    s = gsum_dpp(s, G);
+    if (gl == 0) nrm[c] = s;
+  }
+}
+
 // Householder QR with column pivoting of C (p x q, column stride lc), stopped
 // at the first pivot column whose remaining norm^2 is at most thr2 (see
 // callers); returns the number of reflectors t.  R is left in the upper
 // triangle of the first t rows (the entries below it are left unspecified).
-// All threads call it.
-template <int NT>
+// All threads call it.  Column slices of up to CAP rows per lane are held in
+// registers.
+template <int NT, int CAP>
 __device__ __forceinline__ int qrcp_body(double* C, int64_t lc, int p, int q, double* nrm, int* perm, double delta,
                                          double* red, int* redi) {
   const int mn = p < q ? p : q;
   double mx = 0.0;
   {
-    const int G = step_lanes(p, q, NT), groups = NT / G;
+    const int G = step_lanes(p, q, NT, CAP), groups = NT / G;
     const int gi = threadIdx.x / G, gl = threadIdx.x % G;
     for (int c = gi; c < q; c += groups) {
       double s = 0.0;
@@ -208,55 +251,16 @@ __device__ __forceinline__ int qrcp_body(double* C, int64_t lc, int p, int q, do
     }
     // trailing columns: group size for this step, each lane's slice of the
     // reflector and of the column held in registers when it fits
-    const int G = step_lanes(p - j, q - j - 1, NT), groups = NT / G;
-    const int gi = threadIdx.x / G, gl = threadIdx.x % G;
-    if (p - j <= G * kQC) {
-      double v[kQC];
-#pragma unroll
-      for (int u = 0; u < kQC; ++u) {
-        const int i = j + gl + u * G;
-        v[u] = i < p ? (i == j ? 1.0 : col[i] * scale) : 0.0;
-      }
-      for (int c = j + 1 + gi; c < q; c += groups) {
-        double* ac = C + c * lc;
-        double a[kQC];
-#pragma unroll
-        for (int u = 0; u < kQC; ++u) {
-          const int i = j + gl + u * G;
-          a[u] = i < p ? ac[i] : 0.0;
-        }
-        if (tj != 0.0) {
-          double w = 0.0;
-#pragma unroll
-          for (int u = 0; u < kQC; ++u) w += v[u] * a[u];
-          w = gsum2(w, G) * tj;
-#pragma unroll
-          for (int u = 0; u < kQC; ++u) {
-            const int i = j + gl + u * G;
-            a[u] -= w * v[u];
-            if (i < p) ac[i] = a[u];
-          }
-        }
-        double s = 0.0;
-#pragma unroll
-        for (int u = 0; u < kQC; ++u) s += (j + gl + u * G > j) ? a[u] * a[u] : 0.0;
-        s = gsum2(s, G);
-        if (gl == 0) nrm[c] = s;
-      }
-    } else {
-      for (int c = j + 1 + gi; c < q; c += groups) {
-        double* ac = C + c * lc;
-        if (tj != 0.0) {
-          double w = 0.0;
-          for (int i = j + gl; i < p; i += G) w += (i == j ? 1.0 : col[i] * scale) * ac[i];
-          w = gsum2(w, G) * tj;
-          for (int i = j + gl; i < p; i += G) ac[i] -= w * (i == j ? 1.0 : col[i] * scale);
-        }
-        double s = 0.0;
-        for (int i = j + 1 + gl; i < p; i += G) s += ac[i] * ac[i];
-        s = gsum2(s, G);
-        if (gl == 0) nrm[c] = s;
-      }
+    const int G = step_lanes(p - j, q - j - 1, NT, CAP);
+    const int nu = (p - j + G - 1) / G;
+    switch (nu <= CAP ? nu : 0) {
+#define ACR_QRCP_NU(k) \
+  case k: qrcp_update<NT, (k <= CAP ? k : 0)>(C, lc, p, q, j, col, scale, tj, G, nrm); break;
+      ACR_QRCP_NU(1) ACR_QRCP_NU(2) ACR_QRCP_NU(3) ACR_QRCP_NU(4) ACR_QRCP_NU(5) ACR_QRCP_NU(6)
+      ACR_QRCP_NU(7) ACR_QRCP_NU(8) ACR_QRCP_NU(9) ACR_QRCP_NU(10) ACR_QRCP_NU(11) ACR_QRCP_NU(12)
+      ACR_QRCP_NU(13) ACR_QRCP_NU(14) ACR_QRCP_NU(15) ACR_QRCP_NU(16)
+#undef ACR_QRCP_NU
+      default: qrcp_update<NT, 0>(C, lc, p, q, j, col, scale, tj, G, nrm); break;
     }
     __syncthreads();
     // every thread has read x0 and the column: the diagonal of R can be stored
@@ -290,7 +294,7 @@ __global__ __launch_bounds__(NT) void k_qrcp(const SvdTask* __restrict__ tasks, 
     C[a + (int64_t)c * lc] = core_entry<T>(t, a, c);
   }
   __syncthreads();
-  const int tcount = qrcp_body<NT>(C, lc, p, q, nrm, perm, delta, red, redi);
+  const int tcount = qrcp_body<NT, LDS ? 16 : 8>(C, lc, p, q, nrm, perm, delta, red, redi);
   double* Wt = t.Y;
   for (int64_t e = threadIdx.x; e < (int64_t)q * tcount; e += NT) {
     const int c = (int)(e % q), a = (int)(e / q);
@@ -475,7 +479,7 @@ __device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int
   // 256 or more threads (at most 128 registers, so that several workgroups
   // share a compute unit; 8 when the vectors are in global memory), 16 in a
   // single wavefront
-  constexpr int kCap = NT >= 256 ? (min_g > 1 ? 8 : 12) : 16;
+  constexpr int kCap = NT >= 256 ? 12 : 16;
   const int nu = (len + G - 1) / G;
   switch (nu <= kCap ? nu : 0) {
 #define ACR_JAC_NU(k) \
@@ -624,7 +628,7 @@ __global__ __launch_bounds__(NT) void k_svd_block(const SvdTask* __restrict__ ta
     C[a + c * lc] = core_entry<T>(t, a, c);
   }
   __syncthreads();
-  const int n = qrcp_body<NT>(C, lc, p, q, nrm, perm, delta, red, redi);
+  const int n = qrcp_body<NT, 12>(C, lc, p, q, nrm, perm, delta, red, redi);
   // W^T = P R^T (q x n) through the global workspace back into the C region:
   // the sweeps then run on contiguous columns
   double* Wt = t.Y;
