@@ -1,8 +1,8 @@
 // Truncated SVD of the compression core C = Ru Rv^T (FP64).
 //
-// Stage 1: Householder QR with column pivoting of C, stopped when the largest
-// remaining column norm drops below delta times the largest initial one;
-// C P ~= Q R with R = [R11 R12] (t x q).  Stage 2: one-sided Jacobi on the t
+// Stage 1: Householder QR with column pivoting of C, stopped when the
+// Frobenius norm of the remaining block drops below delta times the largest
+// initial column norm; C P ~= Q R with R = [R11 R12] (t x q).  Stage 2: one-sided Jacobi on the t
 // rows of R, whose singular values are those of C up to the dropped tail.  QR
 // with column pivoting both removes the directions far below the truncation
 // level and preconditions the Jacobi iteration, which then converges in a few
@@ -47,10 +47,7 @@ __device__ inline double rcp_nr(double x) {
   return r;
 }
 
-__device__ inline double wsum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+__device__ inline double wsum(double v) { return gsum_dpp(v, 64); }
 
 __device__ inline double wmax(double v) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -58,13 +55,7 @@ __device__ inline double wmax(double v) {
 }
 
 // wavefront argmax of (v, i); ties go to the smaller index
-__device__ inline void wargmax(double& v, int& i) {
-  for (int off = 32; off > 0; off >>= 1) {
-    const double o = __shfl_xor(v, off, 64);
-    const int oi = __shfl_xor(i, off, 64);
-    if (o > v || (o == v && oi < i)) { v = o; i = oi; }
-  }
-}
+__device__ inline void wargmax(double& v, int& i) { wave_argmax(v, i); }
 
 // workgroup reductions: shuffles inside each wavefront, then one slot per
 // wavefront in LDS read back by every thread (all threads must call them)
@@ -87,6 +78,28 @@ template <int NT> __device__ inline void block_argmax(double& v, int& i, double*
   i = redi[0];
   for (int w = 1; w < NT / 64; ++w)
     if (red[w] > v || (red[w] == v && redi[w] < i)) { v = red[w]; i = redi[w]; }
+}
+
+// Workgroup argmax of (v, i) and sum of s in one exchange (ties go to the
+// smaller index; all threads must call it).
+template <int NT>
+__device__ inline void block_argmax_sum(double& v, int& i, double& s, double* red, int* redi, double* reds) {
+  wargmax(v, i);
+  s = wsum(s);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = v;
+    redi[threadIdx.x >> 6] = i;
+    reds[threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
+  v = red[0];
+  i = redi[0];
+  s = reds[0];
+  for (int w = 1; w < NT / 64; ++w) {
+    if (red[w] > v || (red[w] == v && redi[w] < i)) { v = red[w]; i = redi[w]; }
+    s += reds[w];
+  }
 }
 
 // Lanes per column group for one step of a Householder sweep over `cols`
@@ -182,8 +195,9 @@ __device__ __forceinline__ void qrcp_update(double* C, int64_t lc, int p, int q,
 }
 
 // Householder QR with column pivoting of C (p x q, column stride lc), stopped
-// at the first pivot column whose remaining norm^2 is at most thr2 (see
-// callers); returns the number of reflectors t.  R is left in the upper
+// before step j once the trailing block (rows and columns j..) has Frobenius
+// norm at most delta times the largest column norm of C; returns the number of
+// reflectors t.  R is left in the upper
 // triangle of the first t rows (the entries below it are left unspecified).
 // All threads call it.  Column slices of up to CAP rows per lane are held in
 // registers.
@@ -207,16 +221,20 @@ __device__ __forceinline__ int qrcp_body(double* C, int64_t lc, int p, int q, do
     int dummy = 0;
     block_argmax<NT>(mx, dummy, red, redi);
   }
-  // dropped tail: Frobenius norm <= sqrt(q) * sqrt(thr2) = delta * (largest column norm)
-  const double thr2 = delta * delta * mx / (double)q;
+  // stop when the Frobenius norm of the remaining block (rows and columns j..)
+  // is at most delta * (largest column norm): nrm holds its column norms
+  const double thr2 = delta * delta * mx;
+  __shared__ double reds[NT / 64];
   int tcount = 0;
   for (int j = 0; j < mn; ++j) {
-    double best = -1.0;
+    double best = -1.0, rest = 0.0;
     int bc = j;
-    for (int c = j + threadIdx.x; c < q; c += NT)
+    for (int c = j + threadIdx.x; c < q; c += NT) {
+      rest += nrm[c];
       if (nrm[c] > best) { best = nrm[c]; bc = c; }
-    block_argmax<NT>(best, bc, red, redi);
-    if (!(best > thr2) || !(best > 0.0)) break;
+    }
+    block_argmax_sum<NT>(best, bc, rest, red, redi, reds);
+    if (!(rest > thr2) || !(best > 0.0)) break;
     const int pc = bc;
     if (pc != j) {
       for (int i = threadIdx.x; i < p; i += NT) {
@@ -694,15 +712,19 @@ __global__ __launch_bounds__(64) void k_svd_wave(const SvdTask* __restrict__ tas
     nrm[lane] = nc;
     perm[lane] = lane;
   }
-  const double thr2 = delta * delta * wmax(nc) / (double)q;
+  // stop when the remaining block's Frobenius norm is at most delta times the
+  // largest column norm (nrm holds its column norms)
+  const double thr2 = delta * delta * wmax(nc);
   __syncthreads();
   const int mn = p < q ? p : q;
   int tcount = 0;
   for (int j = 0; j < mn; ++j) {
-    double best = (lane >= j && lane < q) ? nrm[lane] : -1.0;
+    const bool live = lane >= j && lane < q;
+    double best = live ? nrm[lane] : -1.0;
+    const double rest = wsum(live ? nrm[lane] : 0.0);
     int bi = lane;
     wargmax(best, bi);
-    if (!(best > thr2) || !(best > 0.0)) break;
+    if (!(rest > thr2) || !(best > 0.0)) break;
     if (bi != j) {
       if (lane < p) {
         const double a = C[lane + j * lc];

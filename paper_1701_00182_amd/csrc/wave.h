@@ -28,4 +28,28 @@ __device__ inline double gsum_dpp(double v, int G) {
   return v;
 }
 
+template <int CTRL> __device__ inline int dpp_mov_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+
+// One exchange step of a wavefront argmax: keep the larger value, the smaller
+// index on ties (both partners end with the same pair).
+__device__ inline void argmax_step(double& v, int& i, double o, int oi) {
+  if (o > v || (o == v && oi < i)) {
+    v = o;
+    i = oi;
+  }
+}
+
+// Argmax of (v, i) over the 64 lanes of a wavefront: DPP exchanges inside
+// rows of 16 lanes, then two cross-row shuffles.
+__device__ inline void wave_argmax(double& v, int& i) {
+  argmax_step(v, i, dpp_mov<0xB1>(v), dpp_mov_i<0xB1>(i));
+  argmax_step(v, i, dpp_mov<0x4E>(v), dpp_mov_i<0x4E>(i));
+  argmax_step(v, i, dpp_mov<0x141>(v), dpp_mov_i<0x141>(i));
+  argmax_step(v, i, dpp_mov<0x140>(v), dpp_mov_i<0x140>(i));
+  argmax_step(v, i, __shfl_xor(v, 16, 64), __shfl_xor(i, 16, 64));
+  argmax_step(v, i, __shfl_xor(v, 32, 64), __shfl_xor(i, 32, 64));
+}
+
 }  // namespace acr
