@@ -145,6 +145,7 @@ class Exec {
   bool trace = false;          // ACR_TRACE=1: one line per compression batch on stderr
   bool gram_ok = true;         // ACR_GRAM=0 forces Householder compression everywhere
   size_t fused_lds = 0;        // one-workgroup SVD up to this LDS size (ACR_FUSED_LDS, bytes)
+  bool svd_global = false;     // ACR_SVD_GLOBAL=1: every core takes the global-memory two-kernel path
   int leaf_lowp = 0;           // leaf x leaf products with 16-bit inputs: 1 = BF16, 2 = FP16 (FP32 data)
   const char* trace_tag = "";
   void check_range(const void* p, size_t bytes, const char* what) const;

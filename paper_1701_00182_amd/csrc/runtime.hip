@@ -254,6 +254,8 @@ void Exec::init(hipStream_t s, const Allocator& a) {
   const char* gm = std::getenv("ACR_GRAM");
   gram_ok = !(gm && gm[0] == '0');
   fused_lds = kFusedLds;
+  const char* sg = std::getenv("ACR_SVD_GLOBAL");
+  svd_global = sg && sg[0] == '1';
   stream = s;
   al = a;
   ring_bytes_ = size_t(64) << 20;
@@ -611,7 +613,12 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
   std::vector<SvdTask> small, mid, big;
   std::vector<int> big_idx;
   for (size_t i = 0; i < t.size(); ++i) {
-    if (svd_wave_ok(t[i])) {
+    // the blocked sweeps index a core with 32-bit offsets
+    if (t[i].p >= 32768 || t[i].q >= 32768) throw Failure(ST_NOT_SUPPORTED, "compression core too large");
+    if (svd_global) {
+      big.push_back(t[i]);
+      big_idx.push_back((int)i);
+    } else if (svd_wave_ok(t[i])) {
       small.push_back(t[i]);
     } else if (lds_bytes_svd_block(t[i]) <= fused_lds) {
       mid.push_back(t[i]);
@@ -670,7 +677,7 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
   std::vector<SvdTask> two[2];
   std::vector<int> two_idx[2];
   for (size_t i = 0; i < big.size(); ++i) {
-    const int g = (side_ && lds_bytes_qrcp(big[i]) > kLdsBudget) ? 1 : 0;
+    const int g = (side_ && (svd_global || lds_bytes_qrcp(big[i]) > kLdsBudget)) ? 1 : 0;
     two[g].push_back(big[i]);
     two_idx[g].push_back(big_idx[i]);
   }
@@ -751,7 +758,8 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
   if (split) {
     rank_stage(1);
     std::swap(stream, side_);
-    bucketed(two[1], [](const SvdTask& x) { return lds_bytes_jacobi(x); }, jacobi_batch);
+    if (svd_global) jacobi_batch(two[1], 0);
+    else bucketed(two[1], [](const SvdTask& x) { return lds_bytes_jacobi(x); }, jacobi_batch);
     left(two[1]);
     hip_check(hipEventRecord(ev_[2], stream), "hipEventRecord");
     std::swap(stream, side_);

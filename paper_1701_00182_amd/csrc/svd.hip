@@ -471,6 +471,228 @@ __device__ __forceinline__ int jacobi_sweeps(double* V, int64_t vs, int64_t es, 
   return sweeps;
 }
 
+// ---- Blocked one-sided Jacobi for vectors in global memory ----------------
+//
+// The n columns are cut into blocks of kJB; each round of a cyclic tournament
+// over the blocks pairs them up, and one wavefront takes a block pair (16
+// columns Y): it forms the Gram matrix Y^T Y with FP64 matrix-core products,
+// diagonalises it by cyclic two-sided Jacobi in LDS while accumulating the
+// rotations in V (the same rotations one-sided Jacobi would apply to the pairs
+// of Y), and applies Y <- Y V with matrix-core products.  Every column is read
+// and written once per round instead of once per column pair.  The stopping
+// rule is the scalar one, evaluated on the fresh Gram matrices.
+constexpr int kJB = 8;
+constexpr int kJBScratch = 16 * 16 * 2 + 16 * 3;   // doubles of LDS per wavefront: G, V, rotation table
+constexpr int kJBInner = 1;                        // inner sweeps per block-pair visit
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+using dbl4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+
+// One block pair: columns cb[0..7] = bi*kJB.., cb[8..15] = bj*kJB.. (those >= n
+// are zero).  Returns whether Y changed; cmax2 takes the largest squared |cos|
+// of its column pairs before the step.
+__device__ inline bool jacobi_block_pair(double* X, int64_t vs, int n, int len, int bi, int bj, double tol,
+                                         double* g, double& cmax2) {
+  const int lane = threadIdx.x & 63;
+  double* vm = g + 256;
+  double* cself = vm + 256;
+  double* cpart = cself + 16;
+  int* part = reinterpret_cast<int*>(cpart + 16);
+  auto colof = [&](int k) { return k < kJB ? bi * kJB + k : bj * kJB + (k - kJB); };
+  // Gram matrix: lane l feeds Y[r0 + l/16][slot l%16] as both operands; rows
+  // come in batches of 32 (8 loads per lane, issued together), the next batch
+  // loaded while the current one is multiplied; rows past len load a clamped
+  // address and contribute zero
+  {
+    const int kc = lane & 15, kr = lane >> 4;
+    const int col = colof(kc);
+    const bool ok = col < n;
+    const double* xc = X + (int64_t)(ok ? col : 0) * vs;
+    auto batch = [&](double (&y)[8], int r0) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int row = r0 + 4 * i + kr;
+        const double v = xc[row < len ? row : len - 1];
+        y[i] = (ok && row < len) ? v : 0.0;
+      }
+    };
+    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    double ya[8], yb[8];
+    batch(ya, 0);
+    for (int r0 = 0; r0 < len; r0 += 64) {
+      batch(yb, r0 + 32);
+#pragma unroll
+      for (int i = 0; i < 8; i += 2) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[i], ya[i], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[i + 1], ya[i + 1], acc1, 0, 0, 0);
+      }
+      batch(ya, r0 + 64);
+#pragma unroll
+      for (int i = 0; i < 8; i += 2) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[i], yb[i], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[i + 1], yb[i + 1], acc1, 0, 0, 0);
+      }
+    }
+    // accumulator v holds G[kr + 4v][kc]
+#pragma unroll
+    for (int v = 0; v < 4; ++v) g[(kr + 4 * v) * 16 + kc] = acc0[v] + acc1[v];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int e = lane + 64 * v;
+      vm[e] = (e >> 4) == (e & 15) ? 1.0 : 0.0;
+    }
+    wave_sync();
+    double c2 = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = kr + 4 * v;
+      if (a < kc) c2 = fmax(c2, pair_cos2(g[a * 17], g[kc * 17], g[a * 16 + kc]));
+    }
+    for (int off = 32; off > 0; off >>= 1) c2 = fmax(c2, __shfl_xor(c2, off, 64));
+    cmax2 = fmax(cmax2, c2);
+  }
+  // inner cyclic Jacobi on G, rotations accumulated in V
+  bool changed = false;
+  const int a = lane >> 2, b0 = (lane & 3) * 4;
+  for (int is = 0; is < kJBInner; ++is) {
+    bool swept = false;
+    for (int ir = 0; ir < 15; ++ir) {
+      bool r = false;
+      if (lane < 8) {
+        int p, q;
+        tournament_pair(lane, ir, 16, p, q);
+        double c = 1.0, sn = 0.0;
+        r = jacobi_rotation(g[p * 17], g[q * 17], g[p * 16 + q], tol, c, sn);
+        if (!r) { c = 1.0; sn = 0.0; }
+        cself[p] = c;
+        cpart[p] = -sn;
+        part[p] = q;
+        cself[q] = c;
+        cpart[q] = sn;
+        part[q] = p;
+      }
+      const bool any = __ballot(r) != 0;
+      wave_sync();
+      if (!any) continue;
+      swept = true;
+      // G <- J^T G J and V <- V J; J has column x = cself[x] e_x + cpart[x] e_part[x]
+      const double sa = cself[a], ca = cpart[a];
+      const int pa = part[a];
+      double gn[4], vn[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int b = b0 + u;
+        const double sb = cself[b], cb = cpart[b];
+        const int pb = part[b];
+        const double t1 = sb * g[a * 16 + b] + cb * g[a * 16 + pb];
+        const double t2 = sb * g[pa * 16 + b] + cb * g[pa * 16 + pb];
+        gn[u] = sa * t1 + ca * t2;
+        vn[u] = sb * vm[a * 16 + b] + cb * vm[a * 16 + pb];
+      }
+      wave_sync();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        g[a * 16 + b0 + u] = gn[u];
+        vm[a * 16 + b0 + u] = vn[u];
+      }
+      wave_sync();
+    }
+    if (!swept) break;
+    changed = true;
+  }
+  if (!changed) return false;
+  // Y <- Y V, 16 rows at a time: lane l feeds Y[r0 + l%16][slot 4kk + l/16] and
+  // V[4kk + l/16][l%16]; accumulator v is the new Y[r0 + l/16 + 4v][slot l%16]
+  const int ir = lane & 15, ik = lane >> 4;
+  const int ocol = colof(ir);
+  double bv[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) bv[kk] = vm[(kk * 4 + ik) * 16 + ir];
+  // column offsets fit 32 bits: a core has fewer than 2^15 rows and columns
+  int aoff[4];
+  bool aok[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int c = colof(kk * 4 + ik);
+    aok[kk] = c < n;
+    aoff[kk] = (aok[kk] ? c : 0) * (int)vs;
+  }
+  // two 16-row chunks per batch (8 loads per lane), the next batch loaded
+  // before the current one is multiplied and stored (other rows)
+  auto batch = [&](double (&a)[8], int r0) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int row = r0 + 16 * c + ir;
+        const double v = X[aoff[kk] + (row < len ? row : len - 1)];
+        a[c * 4 + kk] = (aok[kk] && row < len) ? v : 0.0;
+      }
+  };
+  auto emit = [&](const double (&a)[8], int r0) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      dbl4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) d = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c * 4 + kk], bv[kk], d, 0, 0, 0);
+      if (ocol < n) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int orow = r0 + 16 * c + ik + 4 * v;
+          if (orow < len) X[ocol * (int)vs + orow] = d[v];
+        }
+      }
+    }
+  };
+  double aa[8], ab[8];
+  batch(aa, 0);
+  for (int r0 = 0; r0 < len; r0 += 64) {
+    batch(ab, r0 + 32);
+    emit(aa, r0);
+    batch(aa, r0 + 64);
+    emit(ab, r0 + 32);
+  }
+  return true;
+}
+
+// Sweeps of the blocked one-sided Jacobi over n columns of length len (column
+// stride vs, element stride 1); scratch holds kJBScratch doubles of LDS per
+// wavefront.  Returns the number of sweeps run.
+template <int NT>
+__device__ __forceinline__ int jacobi_block_sweeps(double* X, int64_t vs, int n, int len, double tol,
+                                                   double* scratch, double* red, int* redi) {
+  const int nblk = (n + kJB - 1) / kJB;
+  const int nb = nblk + (nblk & 1);
+  const int npairs = nb / 2;
+  const int wave = threadIdx.x >> 6;
+  double* g = scratch + wave * kJBScratch;
+  int sweeps = 0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    ++sweeps;
+    int rot = 0;
+    double cmax2 = 0.0;
+    for (int round = 0; round < nb - 1; ++round) {
+      for (int pi = wave; pi < npairs; pi += NT / 64) {
+        int bi, bj;
+        tournament_pair(pi, round, nb, bi, bj);
+        if (jacobi_block_pair(X, vs, n, len, bi, bj, tol, g, cmax2)) rot = 1;
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rot)) break;
+    int dummy = 0;
+    block_argmax<NT>(cmax2, dummy, red, redi);
+    if (cmax2 <= tol) break;
+  }
+  return sweeps;
+}
+
 // One-sided Jacobi SVD of n vectors of length len: vector i starts at V + i * vs
 // and has element stride es.  Then the singular values (vector norms, written
 // to sig and t.sig), the rank k = #{sigma > eps sigma_max} (capped at
@@ -479,10 +701,10 @@ __device__ __forceinline__ int jacobi_sweeps(double* V, int64_t vs, int64_t es, 
 // is n ints of scratch, red / redi one slot per wavefront.  Groups have at
 // least min_g lanes (16 keeps global-memory vectors coalesced).  Returns k;
 // all threads call it.
-template <int NT, int min_g = 1>
+template <int NT, int min_g = 1, bool BLOCKED = false>
 __device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int n, int len, const int* perm,
                                           double* sig, int* ord, double eps, const SvdTask& t, int* flags,
-                                          double* red, int* redi, int& sweeps) {
+                                          double* red, int* redi, int& sweeps, double* bscratch = nullptr) {
   const int ne = n + (n & 1), npairs = ne / 2;
   // lanes per pair: up to one row of 16 (sums through DPP), fewer when that
   // takes every pair of a round in one pass; min_g keeps global-memory
@@ -499,7 +721,10 @@ __device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int
   // single wavefront
   constexpr int kCap = NT >= 256 ? 12 : 16;
   const int nu = (len + G - 1) / G;
-  switch (nu <= kCap ? nu : 0) {
+  if constexpr (BLOCKED) {
+    // contiguous vectors (es == 1) and kJBScratch doubles per wavefront
+    sweeps = jacobi_block_sweeps<NT>(V, vs, n, len, tol, bscratch, red, redi);
+  } else switch (nu <= kCap ? nu : 0) {
 #define ACR_JAC_NU(k) \
   case k: sweeps = jacobi_sweeps<NT, (k <= kCap ? k : 0)>(V, vs, es, n, len, G, tol, red, redi); break;
     ACR_JAC_NU(1) ACR_JAC_NU(2) ACR_JAC_NU(3) ACR_JAC_NU(4) ACR_JAC_NU(5) ACR_JAC_NU(6) ACR_JAC_NU(7)
@@ -558,7 +783,8 @@ __device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int
 }
 
 // Jacobi stage of the cores whose pivoted QR ran in global memory: W^T
-// (q x t, from k_qrcp) in LDS when it fits, else in place in global memory.
+// (q x t, from k_qrcp) in LDS when it fits (scalar sweeps), else in place in
+// global memory (blocked sweeps).
 template <class T, bool LDS, int NT>
 __global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks, double eps, int* flags) {
   extern __shared__ double smj[];
@@ -576,9 +802,12 @@ __global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks
     for (int64_t e = threadIdx.x; e < (int64_t)rows * n; e += NT) A[e] = t.Y[e];
   __syncthreads();
   int sweeps = 0;
-  // the pivot order is no longer needed: its workspace holds the sigma ranks
-  const int k = jacobi_svd<NT, LDS ? 1 : 16>(A, rows, 1, n, rows, nullptr, t.sig, t.perm, eps, t, flags, red,
-                                             redi, sweeps);
+  // the pivot order is no longer needed: its workspace holds the sigma ranks.
+  // Vectors in global memory take the blocked sweeps (LDS holds their
+  // per-wavefront Gram and rotation matrices); the counters record the
+  // equivalent pair visits of the scalar sweeps.
+  const int k = jacobi_svd<NT, LDS ? 1 : 16, !LDS>(A, rows, 1, n, rows, nullptr, t.sig, t.perm, eps, t, flags,
+                                                   red, redi, sweeps, LDS ? nullptr : smj);
   if (threadIdx.x == 0) {
     *t.rank_out = k;
     const unsigned long long visits =
@@ -881,7 +1110,9 @@ template <class T>
 void launch_jacobi(const SvdTask* d_tasks, int ntasks, double eps, int* d_flags, size_t lds, hipStream_t s) {
   if (ntasks <= 0) return;
   if (lds == 0) {
-    hipLaunchKernelGGL((k_jacobi<T, false, 1024>), dim3(ntasks), dim3(1024), 0, s, d_tasks, eps, d_flags);
+    const size_t scratch = (size_t)(1024 / 64) * kJBScratch * sizeof(double);
+    allow(k_jacobi<T, false, 1024>, scratch);
+    hipLaunchKernelGGL((k_jacobi<T, false, 1024>), dim3(ntasks), dim3(1024), scratch, s, d_tasks, eps, d_flags);
     return;
   }
   if (lds <= kSmallLds) {

@@ -168,16 +168,20 @@ def convdiff20_oracle():
     return coef, f, OracleACR(coef, leaf, eps).solve(f)
 
 
-@pytest.mark.parametrize("fused", ["0", "65536", "160000"])
+@pytest.mark.parametrize("fused", ["0", "65536", "160000", "global"])
 def test_svd_paths_agree(fused, monkeypatch, convdiff20_oracle):
-    """The one-workgroup core SVD and the two-kernel path (pivoted QR, then
-    Jacobi on W^T) compute the same truncation: all thresholds give solutions
-    within the eps bound of the oracle's (n = 20, FP64; eps small enough that
-    stacked cores exceed 64 columns)."""
+    """The one-workgroup core SVD, the two-kernel path in LDS (pivoted QR,
+    then scalar Jacobi sweeps on W^T) and the global-memory path (every core,
+    blocked Jacobi sweeps on matrix cores) compute the same truncation: all
+    give solutions within the eps bound of the oracle's (n = 20, FP64; eps small
+    enough that stacked cores exceed 64 columns)."""
     leaf, eps = 32, 1e-6
     coef, f, xo = convdiff20_oracle
     A = operator_from_coef(coef)
-    monkeypatch.setenv("ACR_FUSED_LDS", fused)
+    if fused == "global":
+        monkeypatch.setenv("ACR_SVD_GLOBAL", "1")
+    else:
+        monkeypatch.setenv("ACR_FUSED_LDS", fused)
     fac = _gpu(coef, eps=eps, leaf=leaf, precision="fp64")
     x = _solve(fac, f)
     assert float(relres(A, x, f)) <= 5 * eps
