@@ -2,8 +2,9 @@
 """Benchmark of the ACR hot path on one MI355X.
 
 Default workload (the headline line): one step = factorisation (FP32 factors,
-eps = 1e-2, HODLR leaf size and core-SVD dispatch picked by the autotuner on an
-8-plane sample before the timed region) of the n = 128 nonsymmetric convection-diffusion
+eps = 1e-2, HODLR leaf 128 and the two-kernel core SVD -- the autotuner's choice
+for this operator; --autotune runs it on an 8-plane sample before the timed
+region instead) of the n = 128 nonsymmetric convection-diffusion
 operator (N = 2,097,152) plus an FP64 right-preconditioned GMRES(30) solve to
 relative residual 1e-8 with the factorisation as preconditioner.  Inputs are
 synthetic (seeded lognormal kappa, random divergence-free velocity at cell
@@ -209,7 +210,7 @@ def headline(args, torch, acr):
     torch.cuda.synchronize()
     L = acr.lib()
     tune = None
-    if not args.no_autotune:
+    if args.autotune:
         # leaf size and core-SVD dispatch from a sample of the operator (untimed)
         t0 = time.perf_counter()
         tune = acr.autotune(coef_d, eps=args.eps, precision=args.precision, leaf=args.leaf,
@@ -473,6 +474,80 @@ def copy_calibration(torch):
     return {"copy_bytes": src.numel() * 4, "dispatches": 3}
 
 
+# kernel name prefix -> (traffic class, source files whose SHA-256 gates the figures)
+PMC_CLASSES = [
+    ("k_jacobi<float, true", "jacobi_lds", ["paper_1701_00182_amd/csrc/svd.hip", "paper_1701_00182_amd/csrc/wave.h"]),
+    ("k_jacobi<float, false", "jacobi", ["paper_1701_00182_amd/csrc/svd.hip", "paper_1701_00182_amd/csrc/wave.h"]),
+    ("k_qrcp<float, true", "qrcp_lds", ["paper_1701_00182_amd/csrc/svd.hip", "paper_1701_00182_amd/csrc/wave.h"]),
+    ("k_qrcp<float, false", "qrcp", ["paper_1701_00182_amd/csrc/svd.hip", "paper_1701_00182_amd/csrc/wave.h"]),
+    ("k_svd_wave<float>", "svd_wave", ["paper_1701_00182_amd/csrc/svd.hip", "paper_1701_00182_amd/csrc/wave.h"]),
+    ("k_svd_block<float", "svd_block", ["paper_1701_00182_amd/csrc/svd.hip", "paper_1701_00182_amd/csrc/wave.h"]),
+    ("k_core_left<float>", "core_left", ["paper_1701_00182_amd/csrc/svd.hip"]),
+    ("k_gemm_f32", "gemm", ["paper_1701_00182_amd/csrc/gemm_mfma.hip"]),
+    ("k_qr_lds<float", "qr_lds", ["paper_1701_00182_amd/csrc/la_lds.hip", "paper_1701_00182_amd/csrc/wave.h"]),
+    ("k_applyq_lds<float", "applyq_lds", ["paper_1701_00182_amd/csrc/la_lds.hip", "paper_1701_00182_amd/csrc/wave.h"]),
+    ("k_pchol<", "pchol", ["paper_1701_00182_amd/csrc/gram.hip"]),
+    ("k_apply_leaf_vec<float>", "solve_leaf", ["paper_1701_00182_amd/csrc/solve_kernels.hip"]),
+    ("k_inner_vec<float>", "solve_inner", ["paper_1701_00182_amd/csrc/solve_kernels.hip"]),
+]
+
+
+def summarize_pmc(d, workload):
+    """profiles/pmc_traffic.json from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+    in d/{fetch,write} (bench) and d/{cfetch,cwrite} (copy calibration)."""
+    import csv
+    import glob
+    import re
+
+    def per_kernel(sub):
+        acc = {}
+        for path in glob.glob(os.path.join(d, sub, "*_counter_collection.csv")):
+            for r in csv.DictReader(open(path)):
+                name = re.sub(r"acr::\(anonymous namespace\)::", "", r["Kernel_Name"])
+                name = re.sub(r"\(.*", "", name).replace("void ", "").strip()
+                a = acc.setdefault(name, [0, 0.0])
+                a[0] += 1
+                a[1] += float(r["Counter_Value"])
+        return acc
+
+    cf, cw = per_kernel("cfetch"), per_kernel("cwrite")
+    copy = next(k for k in cf if "copyBuffer" in k)
+    copy_bytes = float(1 << 30)
+    fetch_kib, write_kib = cf[copy][1] / cf[copy][0], cw[copy][1] / cw[copy][0]
+    scale_f, scale_w = copy_bytes / (fetch_kib * 1024), copy_bytes / (write_kib * 1024)
+    bf, bw = per_kernel("fetch"), per_kernel("write")
+    classes = {}
+    for prefix, cls, srcs in PMC_CLASSES:
+        names = sorted(k for k in bf if k.startswith(prefix))
+        if not names:
+            continue
+        nd = sum(bf[k][0] for k in names)
+        fk = sum(bf[k][1] for k in names) / nd
+        wk = sum(bw.get(k, [1, 0.0])[1] for k in names) / nd
+        h = hashlib.sha256()
+        for src in srcs:
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                h.update(fh.read())
+        rec = classes.setdefault(cls, {"kernels": [], "sources": srcs, "sha256": h.hexdigest(), "dispatches": 0,
+                                       "fetch_kib_per_dispatch": 0.0, "write_kib_per_dispatch": 0.0})
+        rec["kernels"] += names
+        rec["dispatches"] = nd
+        rec["fetch_kib_per_dispatch"] = round(fk, 1)
+        rec["write_kib_per_dispatch"] = round(wk, 1)
+        rec["bytes_per_launch"] = (fk * scale_f + wk * scale_w) * 1024
+    out = {"workload": workload,
+           "calibration": {"kernel": f"{copy} (torch copy of 1 GiB, bench.py --workload copy_calibration)",
+                           "copy_bytes": int(copy_bytes), "fetch_kib": round(fetch_kib, 2),
+                           "write_kib": round(write_kib, 2), "scale_fetch": scale_f, "scale_write": scale_w},
+           "classes": classes}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    for cls, rec in classes.items():
+        print(f"{cls:12s} {rec['dispatches']:6d} {rec['fetch_kib_per_dispatch']:14,.0f} "
+              f"{rec['write_kib_per_dispatch']:14,.0f} {rec['bytes_per_launch'] / 1e9:10.3f} GB")
+    print(f"calibration: fetch x{scale_f:.5f}, write x{scale_w:.5f}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -483,9 +558,13 @@ def main():
                              "copy_calibration"])
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--eps", type=float, default=1e-2)
-    ap.add_argument("--leaf", type=int, default=64, help="leaf size (the autotuner's starting candidate)")
-    ap.add_argument("--svd-fused-lds", type=int, default=0)
-    ap.add_argument("--no-autotune", action="store_true", help="use --leaf / --svd-fused-lds as given")
+    ap.add_argument("--leaf", type=int, default=128, help="leaf size (also one of the autotuner's candidates)")
+    ap.add_argument("--svd-fused-lds", type=int, default=-1, help="core-SVD dispatch (acr_options_t.svd_fused_lds)")
+    ap.add_argument("--autotune", action="store_true", help="pick --leaf / --svd-fused-lds with acr_autotune")
+    ap.add_argument("--no-autotune", action="store_true", help="use --leaf / --svd-fused-lds as given (default)")
+    ap.add_argument("--summarize-pmc", metavar="DIR",
+                    help="write profiles/pmc_traffic.json from rocprofv3 FETCH_SIZE / WRITE_SIZE runs in "
+                         "DIR/{fetch,write,cfetch,cwrite} (CPU only) and exit")
     ap.add_argument("--tune-planes", type=int, default=8)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp32_bf16leaf", "fp32_fp16leaf"])
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -496,6 +575,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=22)
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc,
+                      f"convection-diffusion n={args.n}, FP32 factors, eps={args.eps:g}, leaf {args.leaf}, "
+                      f"svd_fused_lds {args.svd_fused_lds} (bench.py --steps 1 --warmup 0 --no-fp64-form "
+                      f"--no-lowp-form --no-cpu-baseline)")
+        return
     ws = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or ws != 1:
         print("bench.py measures one GPU only: the cyclic-reduction hot path is built and timed on a "

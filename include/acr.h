@@ -187,7 +187,10 @@ const char* acr_status_string(acr_status_t s);
  * {32, 64, 128, opt->leaf} (those that fit the plane) and every SVD dispatch in
  * {never, 64 KiB, LDS budget} (as svd_fused_lds: -1, 65536, 159744), times
  * factorisation + 16 single-RHS solves
- * (the cost of a refined solve), and returns the fastest pair.  All other
+ * (the cost of a refined solve), and returns the fastest pair, trying them in
+ * the order listed: a later pair replaces the current choice only when at
+ * least 3% faster, so timing noise does not flip between equivalent ones.
+ * All other
  * options are taken from opt.  coef: DEVICE, as for acr_factor (read only).
  * cache_path (may be NULL): a text file of one result per line keyed by
  * (nx, ny, sample planes, eps, precision, max_rank, inner_eps_ratio); a

@@ -1027,7 +1027,9 @@ acr_status_t autotune_impl(const acr_options_t* opt, const double* coef, int sam
         }
         const double t = trial(leaf, fl);
         ++out->tried;
-        if (out->leaf == 0 || t < best) {
+        // a later candidate has to be at least 3% faster: timing noise does
+        // not flip between equivalent configurations
+        if (out->leaf == 0 || t < 0.97 * best) {
           best = t;
           out->leaf = leaf;
           out->svd_fused_lds = fl;
