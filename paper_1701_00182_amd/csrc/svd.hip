@@ -385,9 +385,7 @@ __device__ __forceinline__ bool jacobi_pair(double* xa, double* xb, int st, int 
       be += y * y;
       ga += x * y;
     }
-    al = gsum_dpp(al, G);
-    be = gsum_dpp(be, G);
-    ga = gsum_dpp(ga, G);
+    gsum3_dpp(al, be, ga, G);
     cmax2 = fmax(cmax2, pair_cos2(al, be, ga));
     double cs, sn;
     if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
@@ -420,9 +418,7 @@ __device__ __forceinline__ bool jacobi_pair(double* xa, double* xb, int st, int 
     be = fma(yr[u], yr[u], be);
     ga = fma(xr[u], yr[u], ga);
   }
-  al = gsum_dpp(al, G);
-  be = gsum_dpp(be, G);
-  ga = gsum_dpp(ga, G);
+  gsum3_dpp(al, be, ga, G);
   cmax2 = fmax(cmax2, pair_cos2(al, be, ga));
   double cs, sn;
   if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;

@@ -28,6 +28,35 @@ __device__ inline double gsum_dpp(double v, int G) {
   return v;
 }
 
+// Three group sums at once: every exchange step is taken for all three values
+// inside one (uniform) branch, so the three dependency chains overlap.
+__device__ inline void gsum3_dpp(double& a, double& b, double& c, int G) {
+  if (G >= 2) {
+    const double x = dpp_mov<0xB1>(a), y = dpp_mov<0xB1>(b), z = dpp_mov<0xB1>(c);
+    a += x; b += y; c += z;
+  }
+  if (G >= 4) {
+    const double x = dpp_mov<0x4E>(a), y = dpp_mov<0x4E>(b), z = dpp_mov<0x4E>(c);
+    a += x; b += y; c += z;
+  }
+  if (G >= 8) {
+    const double x = dpp_mov<0x141>(a), y = dpp_mov<0x141>(b), z = dpp_mov<0x141>(c);
+    a += x; b += y; c += z;
+  }
+  if (G >= 16) {
+    const double x = dpp_mov<0x140>(a), y = dpp_mov<0x140>(b), z = dpp_mov<0x140>(c);
+    a += x; b += y; c += z;
+  }
+  if (G >= 32) {
+    const double x = __shfl_xor(a, 16, 64), y = __shfl_xor(b, 16, 64), z = __shfl_xor(c, 16, 64);
+    a += x; b += y; c += z;
+  }
+  if (G >= 64) {
+    const double x = __shfl_xor(a, 32, 64), y = __shfl_xor(b, 32, 64), z = __shfl_xor(c, 32, 64);
+    a += x; b += y; c += z;
+  }
+}
+
 template <int CTRL> __device__ inline int dpp_mov_i(int v) {
   return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
