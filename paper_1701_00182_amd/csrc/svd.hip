@@ -25,6 +25,8 @@ namespace acr {
 
 namespace {
 
+using dbl4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+
 __device__ inline double gsum2(double v, int G) {
   for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
   return v;
@@ -64,9 +66,8 @@ template <int NT> __device__ inline double block_sum(double v, double* red) {
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  double s = 0.0;
-  for (int w = 0; w < NT / 64; ++w) s += red[w];
-  return s;
+  const int l = threadIdx.x & 63;
+  return wsum(l < NT / 64 ? red[l] : 0.0);
 }
 
 template <int NT> __device__ inline void block_argmax(double& v, int& i, double* red, int* redi) {
@@ -74,10 +75,11 @@ template <int NT> __device__ inline void block_argmax(double& v, int& i, double*
   __syncthreads();
   if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = v; redi[threadIdx.x >> 6] = i; }
   __syncthreads();
-  v = red[0];
-  i = redi[0];
-  for (int w = 1; w < NT / 64; ++w)
-    if (red[w] > v || (red[w] == v && redi[w] < i)) { v = red[w]; i = redi[w]; }
+  // every wavefront combines the per-wavefront results in parallel
+  const int l = threadIdx.x & 63;
+  v = l < NT / 64 ? red[l] : -INFINITY;
+  i = l < NT / 64 ? redi[l] : 0x7fffffff;
+  wargmax(v, i);
 }
 
 // Workgroup argmax of (v, i) and sum of s in one exchange (ties go to the
@@ -93,13 +95,13 @@ __device__ inline void block_argmax_sum(double& v, int& i, double& s, double* re
     reds[threadIdx.x >> 6] = s;
   }
   __syncthreads();
-  v = red[0];
-  i = redi[0];
-  s = reds[0];
-  for (int w = 1; w < NT / 64; ++w) {
-    if (red[w] > v || (red[w] == v && redi[w] < i)) { v = red[w]; i = redi[w]; }
-    s += reds[w];
-  }
+  // every wavefront combines the per-wavefront results in parallel
+  const int l = threadIdx.x & 63;
+  v = l < NT / 64 ? red[l] : -INFINITY;
+  i = l < NT / 64 ? redi[l] : 0x7fffffff;
+  s = l < NT / 64 ? reds[l] : 0.0;
+  wargmax(v, i);
+  s = wsum(s);
 }
 
 // Lanes per column group for one step of a Householder sweep over `cols`
@@ -113,20 +115,50 @@ __device__ inline int step_lanes(int rows, int cols, int nt, int cap) {
   return G;
 }
 
-template <class T>
-__device__ inline double core_entry(const SvdTask& t, int a, int b) {
-  double acc = 0.0;
-  if (t.mode == 0) {
-    const T* Ru = static_cast<const T*>(t.Ru);
-    const T* Rv = static_cast<const T*>(t.Rv);
-    for (int l = (a > b ? a : b); l < t.r; ++l)
-      acc += (double)Ru[a + (int64_t)l * t.ldu] * (double)Rv[b + (int64_t)l * t.ldv];
-  } else {
-    const double* Ru = static_cast<const double*>(t.Ru);
-    const double* Rv = static_cast<const double*>(t.Rv);
-    for (int l = 0; l < t.r; ++l) acc += Ru[a + (int64_t)l * t.ldu] * Rv[b + (int64_t)l * t.ldv];
+// The core C = Ru Rv^T (p x q, column stride lc) on the FP64 matrix cores:
+// the wavefronts take 16 x 16 tiles; lane l feeds Ru[i0 + l%16][k] and
+// Rv[j0 + l%16][k] for k = k0 + l/16 (T widened to FP64, so the products are
+// exact and the sums FP64) and receives C[i0 + l/16 + 4v][j0 + l%16].  Mode 0
+// panels are upper trapezoidal: entries below their diagonal (which hold
+// other data) load as zero, and a tile's sum starts at k = max(i0, j0).
+template <class T, int NT>
+__device__ __forceinline__ void core_product_mfma(const SvdTask& t, double* C, int64_t lc) {
+  const int p = t.p, q = t.q, r = t.r;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ti = (p + 15) / 16, tj = (q + 15) / 16;
+  for (int tile = wave; tile < ti * tj; tile += NT / 64) {
+    const int i0 = (tile % ti) * 16, j0 = (tile / ti) * 16;
+    const int a = i0 + li, b = j0 + li;
+    const int ac = a < p ? a : p - 1, bc = b < q ? b : q - 1;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int kstart = t.mode == 0 ? ((i0 > j0 ? i0 : j0) & ~3) : 0;
+    for (int k0 = kstart; k0 < r; k0 += 16) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + 4 * u + lk;
+        const int kc = k < r ? k : r - 1;
+        double x, y;
+        if (t.mode == 0) {
+          x = (double)static_cast<const T*>(t.Ru)[ac + (int64_t)kc * t.ldu];
+          y = (double)static_cast<const T*>(t.Rv)[bc + (int64_t)kc * t.ldv];
+        } else {
+          x = static_cast<const double*>(t.Ru)[ac + (int64_t)kc * t.ldu];
+          y = static_cast<const double*>(t.Rv)[bc + (int64_t)kc * t.ldv];
+        }
+        av[u] = (a < p && k < r && (t.mode != 0 || a <= k)) ? x : 0.0;
+        bv[u] = (b < q && k < r && (t.mode != 0 || b <= k)) ? y : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = i0 + lk + 4 * v, col = j0 + li;
+      if (row < p && col < q) C[row + (int64_t)col * lc] = acc[v];
+    }
   }
-  return acc;
 }
 
 // Reflector j of the pivoted QR, v = (1, x_{j+1..} * scale) with factor tj,
@@ -307,12 +339,9 @@ __global__ __launch_bounds__(NT) void k_qrcp(const SvdTask* __restrict__ tasks, 
   int* perm = LDS ? reinterpret_cast<int*>(nrm + q) : t.perm;
   __shared__ double red[NT / 64];
   __shared__ int redi[NT / 64];
-  for (int64_t e = threadIdx.x; e < (int64_t)p * q; e += NT) {
-    const int a = (int)(e % p), c = (int)(e / p);
-    C[a + (int64_t)c * lc] = core_entry<T>(t, a, c);
-  }
+  core_product_mfma<T, NT>(t, C, lc);
   __syncthreads();
-  const int tcount = qrcp_body<NT, LDS ? 16 : 8>(C, lc, p, q, nrm, perm, delta, red, redi);
+  const int tcount = qrcp_body<NT, LDS ? 12 : 8>(C, lc, p, q, nrm, perm, delta, red, redi);
   double* Wt = t.Y;
   for (int64_t e = threadIdx.x; e < (int64_t)q * tcount; e += NT) {
     const int c = (int)(e % q), a = (int)(e / q);
@@ -486,8 +515,6 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-
-using dbl4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
 
 // One block pair: columns cb[0..7] = bi*kJB.., cb[8..15] = bj*kJB.. (those >= n
 // are zero).  Returns whether Y changed; cmax2 takes the largest squared |cos|
@@ -866,10 +893,7 @@ __global__ __launch_bounds__(NT) void k_svd_block(const SvdTask* __restrict__ ta
   int* ord = perm + q;
   __shared__ double red[NT / 64];
   __shared__ int redi[NT / 64];
-  for (int e = threadIdx.x; e < p * q; e += NT) {
-    const int a = e % p, c = e / p;
-    C[a + c * lc] = core_entry<T>(t, a, c);
-  }
+  core_product_mfma<T, NT>(t, C, lc);
   __syncthreads();
   const int n = qrcp_body<NT, 12>(C, lc, p, q, nrm, perm, delta, red, redi);
   // W^T = P R^T (q x n) through the global workspace back into the C region:
