@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "kern.h"
+#include "wave.h"
 
 namespace acr {
 
@@ -139,6 +140,117 @@ __global__ __launch_bounds__(NT) void k_pchol(const PcholTask* __restrict__ task
 }
 
 // R (r1 x r, original column order): R[a, perm[i]] = L[i, a] for i >= a.
+// Pivoted Cholesky with the Gram matrix in LDS: its lower triangle packed by
+// columns, kept in pivot order (the rows and columns of each pivot are swapped
+// into place), and right-looking rank-1 updates of the trailing block.  Same
+// outputs as k_pchol: L (r x rank, pivot order, column-major in global
+// memory), perm, the remaining diagonal d in the original order, the rank.
+// One workgroup barrier per step (two when the pivot moves).  LDS:
+// r (r + 1) / 2 doubles and r ints.
+__device__ inline int packed(int r, int i, int k) { return k * (2 * r - k - 1) / 2 + i; }   // i >= k
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pchol_lds(const PcholTask* __restrict__ tasks, double tol) {
+  extern __shared__ double spk[];
+  const PcholTask t = tasks[blockIdx.x];
+  const int r = t.r;
+  double* S = spk;
+  int* perm = reinterpret_cast<int*>(S + (size_t)r * (r + 1) / 2);
+  double* L = t.L;
+  constexpr int NW = NT / 64;
+  // per-wavefront pivot candidates, double buffered by step parity: the
+  // wavefront that updates a column's diagonal proposes it for the next step
+  __shared__ double cand[2][NW];
+  __shared__ int candi[2][NW];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int k = 0; k < r; ++k)
+    for (int i = k + threadIdx.x; i < r; i += NT) S[packed(r, i, k)] = t.G[i + (int64_t)k * r];
+  for (int i = threadIdx.x; i < r; i += NT) perm[i] = i;
+  __syncthreads();
+  {
+    double v = -INFINITY;
+    int vi = 0x7fffffff;
+    for (int i = threadIdx.x; i < r; i += NT) {
+      const double x = S[packed(r, i, i)];
+      if (x > v) { v = x; vi = i; }
+    }
+    wave_argmax(v, vi);
+    if (lane == 0) { cand[0][wave] = v; candi[0][wave] = vi; }
+  }
+  __syncthreads();
+  double mx;
+  {
+    int dummy;
+    mx = lane < NW ? cand[0][lane] : -INFINITY;
+    dummy = lane < NW ? candi[0][lane] : 0x7fffffff;
+    wave_argmax(mx, dummy);
+  }
+  const double thr = tol * mx;
+  const bool zero = !(mx > 0.0);
+  int rank = 0;
+  for (int j = 0; j < r && !zero; ++j) {
+    double best = lane < NW ? cand[j & 1][lane] : -INFINITY;
+    int p = lane < NW ? candi[j & 1][lane] : 0x7fffffff;
+    wave_argmax(best, p);
+    if (!(best > thr)) break;
+    if (p != j) {
+      // swap positions j and p among the remaining ones (rows and columns of
+      // the packed trailing block), their diagonals, the pivot order, and
+      // rows j and p of the columns of L already computed
+      for (int x = j + 1 + threadIdx.x; x < r; x += NT) {
+        if (x == p) continue;
+        const int aj = packed(r, x, j);
+        const int ap = packed(r, x > p ? x : p, x > p ? p : x);
+        const double tmp = S[aj];
+        S[aj] = S[ap];
+        S[ap] = tmp;
+      }
+      for (int l = threadIdx.x; l < j; l += NT) {
+        const double a = L[j + (int64_t)l * r];
+        L[j + (int64_t)l * r] = L[p + (int64_t)l * r];
+        L[p + (int64_t)l * r] = a;
+      }
+      if (threadIdx.x == 0) {
+        const double a = S[packed(r, j, j)];
+        S[packed(r, j, j)] = S[packed(r, p, p)];
+        S[packed(r, p, p)] = a;
+        const int b = perm[j];
+        perm[j] = perm[p];
+        perm[p] = b;
+      }
+      __syncthreads();
+    }
+    const double ljj = sqrt(S[packed(r, j, j)]);
+    const double inv = 1.0 / ljj;
+    const double* cj = S + packed(r, 0, j);   // column j (rows j..), not modified in this step
+    if (threadIdx.x == 0) L[j + (int64_t)j * r] = ljj;
+    for (int i = j + 1 + threadIdx.x; i < r; i += NT) L[i + (int64_t)j * r] = cj[i] * inv;
+    // S(i, k) -= l_i l_k for j < k <= i, l_i = S(i, j) / l_jj: a wavefront per
+    // column, lanes down it; lane 0 of each column's first chunk holds its
+    // new diagonal, the wavefront's candidate for the next pivot
+    double v = -INFINITY;
+    int vi = 0x7fffffff;
+    for (int k = j + 1 + wave; k < r; k += NW) {
+      const double lk = cj[k] * inv;
+      double* col = S + packed(r, 0, k);
+      for (int i = k + lane; i < r; i += 64) {
+        const double x = col[i] - (cj[i] * inv) * lk;
+        col[i] = x;
+        if (i == k && x > v) { v = x; vi = k; }
+      }
+    }
+    wave_argmax(v, vi);
+    if (lane == 0) { cand[(j + 1) & 1][wave] = v; candi[(j + 1) & 1][wave] = vi; }
+    __syncthreads();
+    rank = j + 1;
+  }
+  for (int i = threadIdx.x; i < r; i += NT) {
+    t.perm[i] = perm[i];
+    t.d[perm[i]] = S[packed(r, i, i)];
+  }
+  if (threadIdx.x == 0) *t.rank_out = rank;
+}
+
 __global__ __launch_bounds__(256) void k_materialize_r(const PcholTask* __restrict__ tasks) {
   const PcholTask t = tasks[blockIdx.x];
   const int r = t.r, r1 = t.r1;
@@ -206,8 +318,20 @@ void launch_gram(const GramTask* d_tasks, int ntasks, const int* d_tile_task, co
   hipLaunchKernelGGL(k_gram_reduce, dim3(ntasks, 16), dim3(256), 0, s, d_tasks);
 }
 
-void launch_pchol(const PcholTask* d_tasks, int ntasks, int max_r, double tol, hipStream_t s) {
+void launch_pchol(const PcholTask* d_tasks, int ntasks, int max_r, double tol, size_t lds_packed, hipStream_t s) {
   if (ntasks <= 0) return;
+  if (lds_packed > 0) {
+    // small Gram matrices in 256-thread workgroups (several per compute unit)
+    if (lds_packed <= kSmallLds) {
+      hipLaunchKernelGGL(k_pchol_lds<256>, dim3(ntasks), dim3(256), lds_packed, s, d_tasks, tol);
+      return;
+    }
+    if (lds_packed > 64 * 1024)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol_lds<1024>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_packed);
+    hipLaunchKernelGGL(k_pchol_lds<1024>, dim3(ntasks), dim3(1024), lds_packed, s, d_tasks, tol);
+    return;
+  }
   const size_t lds = (size_t)max_r * (sizeof(double) + sizeof(int));
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol<1024>),

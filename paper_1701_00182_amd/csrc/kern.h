@@ -208,7 +208,10 @@ template <class T> void launch_gram(const GramTask* d_tasks, int ntasks, const i
 // pairs of 64-column blocks)
 template <class T> void launch_gram_mfma(const GramTask* d_tasks, const int* d_tile_task, const int* d_first_tile,
                                         int ntiles, hipStream_t s);
-void launch_pchol(const PcholTask* d_tasks, int ntasks, int max_r, double tol, hipStream_t s);
+// lds_packed > 0: the Gram matrices in LDS (packed, right-looking; lds_packed
+// = max over the tasks of lds_bytes_pchol_packed); 0: left-looking with L in
+// global memory (max_r bounds the tasks' orders)
+void launch_pchol(const PcholTask* d_tasks, int ntasks, int max_r, double tol, size_t lds_packed, hipStream_t s);
 void launch_materialize_r(const PcholTask* d_tasks, int ntasks, hipStream_t s);
 template <class T> void launch_wtilde(const WtTask* d_tasks, int ntasks, int kc, int nchunks, size_t lds,
                                       hipStream_t s);
@@ -221,6 +224,7 @@ constexpr size_t kLdsBudget = 156 * 1024;
 constexpr size_t kSmallLds = 32 * 1024;   // LDS-resident tasks up to this size use 256-thread workgroups
 inline size_t lds_bytes_qr(const QrTask& t, size_t w) { return (size_t)t.m * t.r * w; }
 inline size_t lds_bytes_jacobi(const SvdTask& t) { return (size_t)t.q * t.tc * 8; }
+inline size_t lds_bytes_pchol_packed(int r) { return (size_t)r * (r + 1) / 2 * 8 + (size_t)r * 4; }
 constexpr int kSvdWave = 64;
 inline bool svd_wave_ok(const SvdTask& t) {
   return t.mode == 0 && t.p <= kSvdWave && t.q <= kSvdWave && t.r <= kSvdWave;

@@ -851,19 +851,37 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
     check_range(x.rank_out, sizeof(int), "pchol rank");
     flops_qr += (double)x.r * x.r * x.r / 3.0;
   }
-  Work w;
-  w.cls = "pchol";
-  for (auto& x : t) {
-    w.flops += (double)x.r * x.r * x.r / 3.0;
-    w.bytes += 16.0 * x.r * x.r;
-  }
+  // Gram matrices whose packed lower triangle fits in LDS take the right-
+  // looking kernel (one launch: splitting a batch into LDS-size buckets
+  // serialises it and measured slower), wider ones the left-looking one with
+  // L in global memory
+  std::vector<PcholTask> packed, wide;
+  size_t lds_packed = 0;
   int max_r = 1;
-  for (auto& x : t) max_r = std::max(max_r, x.r);
+  for (auto& x : t) {
+    if (lds_bytes_pchol_packed(x.r) <= kLdsBudget) {
+      packed.push_back(x);
+      lds_packed = std::max(lds_packed, lds_bytes_pchol_packed(x.r));
+    } else {
+      wide.push_back(x);
+      max_r = std::max(max_r, x.r);
+    }
+  }
   if ((size_t)max_r * (sizeof(double) + sizeof(int)) > kLdsBudget)
     throw Failure(ST_NOT_SUPPORTED, "stack too wide for the pivoted Cholesky kernel");
-  const PcholTask* dt = upload(t);
-  const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_pchol(dt, n, max_r, tol, s); }, w);
+  auto launch = [&](const std::vector<PcholTask>& b, size_t lds) {
+    Work w;
+    w.cls = "pchol";
+    for (auto& x : b) {
+      w.flops += (double)x.r * x.r * x.r / 3.0;
+      w.bytes += 16.0 * x.r * x.r;
+    }
+    const PcholTask* dt = upload(b);
+    const int n = (int)b.size();
+    submit([=](hipStream_t s) { launch_pchol(dt, n, max_r, tol, lds, s); }, w);
+  };
+  if (!packed.empty()) launch(packed, lds_packed);
+  if (!wide.empty()) launch(wide, 0);
 }
 
 void Exec::materialize_r(const std::vector<PcholTask>& t) {

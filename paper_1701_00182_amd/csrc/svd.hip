@@ -1039,7 +1039,7 @@ __global__ __launch_bounds__(64) void k_svd_wave(const SvdTask* __restrict__ tas
 
 // Left factor of the core, Zu = C Zv = Ru (Rv^T Zv), for the k kept columns:
 // one workgroup per (core, chunk of kc columns); the chunk of Zv and of the
-// intermediate Rv^T Zv sit in LDS.
+// intermediate Rv^T Zv sit in LDS, both products run on the FP64 matrix cores.
 template <class T>
 __global__ __launch_bounds__(256) void k_core_left(const SvdTask* __restrict__ tasks, int kc,
                                                    unsigned long long* ctr) {
@@ -1056,33 +1056,64 @@ __global__ __launch_bounds__(256) void k_core_left(const SvdTask* __restrict__ t
   double* t1 = sl + q * kc;      // r x nc
   for (int e = threadIdx.x; e < q * nc; e += 256) zs[e] = Zv[e];
   __syncthreads();
-  for (int e = threadIdx.x; e < r * nc; e += 256) {
-    const int l = e % r, c = e / r;
-    const double* z = zs + c * q;
-    double s = 0.0;
-    if (t.mode == 0) {
-      const T* col = static_cast<const T*>(t.Rv) + (int64_t)l * t.ldv;
-      const int bmax = l < q - 1 ? l : q - 1;
-      for (int b = 0; b <= bmax; ++b) s += (double)col[b] * z[b];
-    } else {
-      const double* col = static_cast<const double*>(t.Rv) + (int64_t)l * t.ldv;
-      for (int b = 0; b < q; ++b) s += col[b] * z[b];
+  // both products on the FP64 matrix cores, 16 x 16 tiles over the four
+  // wavefronts: lane l feeds A[i0 + l%16][k0 + l/16] and B[k0 + l/16][j0 + l%16]
+  // and receives D[i0 + l/16 + 4v][j0 + l%16]; mode 0 panels are upper
+  // trapezoidal (entries below their diagonal load as zero)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tc = (nc + 15) / 16;
+  // t1 = Rv^T Zv (r x nc): A[l][b] = Rv(b, l), B[b][c] = Zv(b, c)
+  {
+    const int tr = (r + 15) / 16;
+    for (int tile = wave; tile < tr * tc; tile += 4) {
+      const int i0 = (tile % tr) * 16, j0 = (tile / tr) * 16;
+      const int l = i0 + li, c = j0 + li;
+      const int lcl = l < r ? l : r - 1;
+      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+      const int kend = t.mode == 0 ? (i0 + 16 < q ? i0 + 16 : q) : q;
+      for (int k0 = 0; k0 < kend; k0 += 4) {
+        const int b = k0 + lk;
+        const int bcl = b < q ? b : q - 1;
+        double av;
+        if (t.mode == 0) av = (double)static_cast<const T*>(t.Rv)[bcl + (int64_t)lcl * t.ldv];
+        else av = static_cast<const double*>(t.Rv)[bcl + (int64_t)lcl * t.ldv];
+        av = (l < r && b < q && (t.mode != 0 || b <= l)) ? av : 0.0;
+        const double bv = (b < q && c < nc) ? zs[bcl + (c < nc ? c : 0) * q] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = i0 + lk + 4 * v, col = j0 + li;
+        if (row < r && col < nc) t1[row + col * r] = acc[v];
+      }
     }
-    t1[e] = s;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < p * nc; e += 256) {
-    const int a = e % p, c = e / p;
-    const double* z = t1 + c * r;
-    double s = 0.0;
-    if (t.mode == 0) {
-      const T* Ru = static_cast<const T*>(t.Ru);
-      for (int l = a; l < r; ++l) s += (double)Ru[a + (int64_t)l * t.ldu] * z[l];
-    } else {
-      const double* Ru = static_cast<const double*>(t.Ru);
-      for (int l = 0; l < r; ++l) s += Ru[a + (int64_t)l * t.ldu] * z[l];
+  // Zu = Ru t1 (p x nc): A[a][l] = Ru(a, l), B[l][c] = t1(l, c)
+  {
+    const int tp = (p + 15) / 16;
+    for (int tile = wave; tile < tp * tc; tile += 4) {
+      const int i0 = (tile % tp) * 16, j0 = (tile / tp) * 16;
+      const int a = i0 + li, c = j0 + li;
+      const int acl = a < p ? a : p - 1;
+      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = t.mode == 0 ? (i0 & ~3) : 0; k0 < r; k0 += 4) {
+        const int l = k0 + lk;
+        const int lcl = l < r ? l : r - 1;
+        double av;
+        if (t.mode == 0) av = (double)static_cast<const T*>(t.Ru)[acl + (int64_t)lcl * t.ldu];
+        else av = static_cast<const double*>(t.Ru)[acl + (int64_t)lcl * t.ldu];
+        av = (a < p && l < r && (t.mode != 0 || a <= l)) ? av : 0.0;
+        const double bv = (l < r && c < nc) ? t1[lcl + (c < nc ? c : 0) * r] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = i0 + lk + 4 * v, col = j0 + li;
+        if (row < p && col < nc) Zu[row + (int64_t)col * p] = acc[v];
+      }
     }
-    Zu[a + (int64_t)c * p] = s;
   }
   if ((ctr || t.flop_ctr) && threadIdx.x == 0) {
     // multiply-adds of this chunk
