@@ -486,7 +486,7 @@ PMC_CLASSES = [
     ("k_gemm_f32", "gemm", ["paper_1701_00182_amd/csrc/gemm_mfma.hip"]),
     ("k_qr_lds<float", "qr_lds", ["paper_1701_00182_amd/csrc/la_lds.hip", "paper_1701_00182_amd/csrc/wave.h"]),
     ("k_applyq_lds<float", "applyq_lds", ["paper_1701_00182_amd/csrc/la_lds.hip", "paper_1701_00182_amd/csrc/wave.h"]),
-    ("k_pchol<", "pchol", ["paper_1701_00182_amd/csrc/gram.hip"]),
+    ("k_pchol", "pchol", ["paper_1701_00182_amd/csrc/gram.hip", "paper_1701_00182_amd/csrc/wave.h"]),
     ("k_apply_leaf_vec<float>", "solve_leaf", ["paper_1701_00182_amd/csrc/solve_kernels.hip"]),
     ("k_inner_vec<float>", "solve_inner", ["paper_1701_00182_amd/csrc/solve_kernels.hip"]),
 ]
@@ -517,8 +517,10 @@ def summarize_pmc(d, workload):
     scale_f, scale_w = copy_bytes / (fetch_kib * 1024), copy_bytes / (write_kib * 1024)
     bf, bw = per_kernel("fetch"), per_kernel("write")
     classes = {}
-    for prefix, cls, srcs in PMC_CLASSES:
-        names = sorted(k for k in bf if k.startswith(prefix))
+    for cls in dict.fromkeys(c for _, c, _ in PMC_CLASSES):
+        prefixes = [pre for pre, c, _ in PMC_CLASSES if c == cls]
+        srcs = next(sr for _, c, sr in PMC_CLASSES if c == cls)
+        names = sorted(k for k in bf if any(k.startswith(pre) for pre in prefixes))
         if not names:
             continue
         nd = sum(bf[k][0] for k in names)
@@ -528,13 +530,9 @@ def summarize_pmc(d, workload):
         for src in srcs:
             with open(os.path.join(ROOT, src), "rb") as fh:
                 h.update(fh.read())
-        rec = classes.setdefault(cls, {"kernels": [], "sources": srcs, "sha256": h.hexdigest(), "dispatches": 0,
-                                       "fetch_kib_per_dispatch": 0.0, "write_kib_per_dispatch": 0.0})
-        rec["kernels"] += names
-        rec["dispatches"] = nd
-        rec["fetch_kib_per_dispatch"] = round(fk, 1)
-        rec["write_kib_per_dispatch"] = round(wk, 1)
-        rec["bytes_per_launch"] = (fk * scale_f + wk * scale_w) * 1024
+        classes[cls] = {"kernels": names, "sources": srcs, "sha256": h.hexdigest(), "dispatches": nd,
+                        "fetch_kib_per_dispatch": round(fk, 1), "write_kib_per_dispatch": round(wk, 1),
+                        "bytes_per_launch": (fk * scale_f + wk * scale_w) * 1024}
     out = {"workload": workload,
            "calibration": {"kernel": f"{copy} (torch copy of 1 GiB, bench.py --workload copy_calibration)",
                            "copy_bytes": int(copy_bytes), "fetch_kib": round(fetch_kib, 2),
