@@ -17,10 +17,21 @@ namespace acr {
 
 namespace {
 
+// 16-byte vector of T
+template <class T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+
+template <class T>
+__device__ inline bool aligned16(const T* p) {
+  return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_copy(const CopyTask* __restrict__ tasks) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;
   const CopyTask t = tasks[blockIdx.x];
-  const int64_t total = (int64_t)t.m * t.n;
   const T* src = static_cast<const T*>(t.src);
   T* dst = static_cast<T*>(t.dst);
   const T* rs = static_cast<const T*>(t.rs);
@@ -29,14 +40,41 @@ __global__ __launch_bounds__(256) void k_copy(const CopyTask* __restrict__ tasks
   // units of (column, 2048-row chunk): one division per unit, none per element
   const int ich = (t.m + 2047) / 2048;
   const int64_t units = (int64_t)t.n * ich;
-  (void)total;
   for (int64_t u = blockIdx.y; u < units; u += gridDim.y) {
     const int j = (int)(u / ich), i0 = (int)(u % ich) * 2048;
     const int i1 = t.m < i0 + 2048 ? t.m : i0 + 2048;
     const T csj = cs ? cs[j] : T(1);
     const T* sc = src ? src + (int64_t)j * t.lds : nullptr;
     T* dc = dst + (int64_t)j * t.ldd;
-    for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+    int i = i0 + threadIdx.x;
+    // 16-byte vectors when every column pointer is aligned at the chunk start
+    if (sc && aligned16(sc + i0) && aligned16(dc + i0) && (!rs || aligned16(rs + i0))) {
+      const int nv = (i1 - i0) / VN;
+      for (int e = threadIdx.x; e < nv; e += 256) {
+        const int ib = i0 + e * VN;
+        V x = *reinterpret_cast<const V*>(sc + ib);
+        T* xv = reinterpret_cast<T*>(&x);
+        V rv;
+        if (rs) rv = *reinterpret_cast<const V*>(rs + ib);
+        const T* rsv = reinterpret_cast<const T*>(&rv);
+        V y;
+        if (t.accumulate) y = *reinterpret_cast<const V*>(dc + ib);
+        T* yv = reinterpret_cast<T*>(&y);
+        V o;
+        T* ov = reinterpret_cast<T*>(&o);
+#pragma unroll
+        for (int c = 0; c < VN; ++c) {
+          T v = alpha * xv[c];
+          if (rs) v *= rsv[c];
+          v *= csj;
+          if (t.accumulate) v += yv[c];
+          ov[c] = v;
+        }
+        *reinterpret_cast<V*>(dc + ib) = o;
+      }
+      i = i0 + nv * VN + threadIdx.x;
+    }
+    for (; i < i1; i += 256) {
       T v = sc ? alpha * sc[i] : (i == j ? alpha : T(0));
       if (rs) v *= rs[i];
       v *= csj;
