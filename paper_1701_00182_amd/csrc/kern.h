@@ -230,8 +230,9 @@ inline bool svd_wave_ok(const SvdTask& t) {
   return t.mode == 0 && t.p <= kSvdWave && t.q <= kSvdWave && t.r <= kSvdWave;
 }
 inline size_t lds_bytes_svd_wave(const SvdTask& t, size_t w) {
+  (void)w;
   const size_t lc = t.p | 1;
-  return (lc * t.q + t.q) * 8 + (size_t)2 * t.q * 4 + (size_t)t.q * t.r * w;
+  return (lc * t.q + t.q) * 8 + (size_t)2 * t.q * 4;
 }
 // default LDS limit of the one-workgroup path for cores beyond the wavefront
 // size (0: such cores take the two-kernel path, the faster one at the n = 128

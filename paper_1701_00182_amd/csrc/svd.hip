@@ -735,14 +735,15 @@ __device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int
   int G = min_g > 16 ? min_g : 16;
   while (G > min_g && G * npairs > NT) G >>= 1;
   while (G > 1 && G > 2 * len) G >>= 1;
-  const int groups = NT / G;
-  const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   const double tol = fmax(1e-15, 2.3e-16 * (double)len);
   // register-resident slices of up to 12 elements per lane in workgroups of
   // 256 or more threads (at most 128 registers, so that several workgroups
-  // share a compute unit; 8 when the vectors are in global memory), 16 in a
-  // single wavefront
+  // share a compute unit), 16 in a single wavefront; wider groups (a second
+  // pass per round) rather than streamed vectors when a slice would exceed it
   constexpr int kCap = NT >= 256 ? 12 : 16;
+  while (G < 16 && (len + G - 1) / G > kCap) G <<= 1;
+  const int groups = NT / G;
+  const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   const int nu = (len + G - 1) / G;
   if constexpr (BLOCKED) {
     // contiguous vectors (es == 1) and kJBScratch doubles per wavefront
@@ -917,9 +918,9 @@ __global__ __launch_bounds__(NT) void k_svd_block(const SvdTask* __restrict__ ta
 }
 
 // The whole truncated SVD of one small core (p, q, r <= 64, triangular panels)
-// in one wavefront: lane b forms column b of C from the staged Rv panel, the
-// pivoted QR runs with one lane per column and wavefront shuffles.  LDS: C
-// (p x q, ld p|1), Rv staged in T (q x r), q norms, q pivots, q ints.
+// in one wavefront: C from FP64 matrix-core tiles, the pivoted QR with one
+// lane per column and wavefront shuffles, the sweeps on the rows of R.  LDS: C
+// (p x q, ld p|1), q norms, q pivots, q ints.
 template <class T>
 __global__ __launch_bounds__(64) void k_svd_wave(const SvdTask* __restrict__ tasks, double delta, double eps,
                                                  int* flags) {
@@ -935,25 +936,10 @@ __global__ __launch_bounds__(64) void k_svd_wave(const SvdTask* __restrict__ tas
   double* nrm = C + lc * q;
   int* perm = reinterpret_cast<int*>(nrm + q);
   int* ord = perm + q;
-  T* sv = reinterpret_cast<T*>(ord + q);   // q x r, ld q (8-byte aligned: 2q ints precede it)
   __shared__ double red[1];
   __shared__ int redi[1];
-  {
-    const T* Ru = static_cast<const T*>(t.Ru);
-    const T* Rv = static_cast<const T*>(t.Rv);
-    for (int l = 0; l < r; ++l)
-      if (lane < q) sv[lane + l * q] = lane <= l ? Rv[lane + (int64_t)l * t.ldv] : T(0);
-    __syncthreads();
-    // C = Ru Rv^T: lane b forms column b; Ru entries are uniform across lanes
-    if (lane < q)
-      for (int a = 0; a < p; ++a) {
-        const T* ra = Ru + a;
-        double s = 0.0;
-        for (int l = a > lane ? a : lane; l < r; ++l) s += (double)ra[(int64_t)l * t.ldu] * (double)sv[lane + l * q];
-        C[a + lane * lc] = s;
-      }
-    __syncthreads();
-  }
+  core_product_mfma<T, 64>(t, C, lc);
+  __syncthreads();
   // pivoted QR, lane c owns column c
   double nc = 0.0;
   if (lane < q) {
