@@ -852,16 +852,14 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
     flops_qr += (double)x.r * x.r * x.r / 3.0;
   }
   // Gram matrices whose packed lower triangle fits in LDS take the right-
-  // looking kernel (one launch: splitting a batch into LDS-size buckets
-  // serialises it and measured slower), wider ones the left-looking one with
-  // L in global memory
+  // looking kernel (two launches at most: finer LDS-size buckets serialise
+  // the batch and measured slower), wider ones the left-looking one with L in
+  // global memory
   std::vector<PcholTask> packed, wide;
-  size_t lds_packed = 0;
   int max_r = 1;
   for (auto& x : t) {
     if (lds_bytes_pchol_packed(x.r) <= kLdsBudget) {
       packed.push_back(x);
-      lds_packed = std::max(lds_packed, lds_bytes_pchol_packed(x.r));
     } else {
       wide.push_back(x);
       max_r = std::max(max_r, x.r);
@@ -880,7 +878,22 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
     const int n = (int)b.size();
     submit([=](hipStream_t s) { launch_pchol(dt, n, max_r, tol, lds, s); }, w);
   };
-  if (!packed.empty()) launch(packed, lds_packed);
+  // small Gram matrices (packed triangle within kSmallLds) in a launch of
+  // 256-thread workgroups of their own, the others in 1024-thread ones
+  std::vector<PcholTask> small, large;
+  size_t lds_small = 0, lds_large = 0;
+  for (auto& x : packed) {
+    const size_t b = lds_bytes_pchol_packed(x.r);
+    if (b <= kSmallLds) {
+      small.push_back(x);
+      lds_small = std::max(lds_small, b);
+    } else {
+      large.push_back(x);
+      lds_large = std::max(lds_large, b);
+    }
+  }
+  if (!small.empty()) launch(small, lds_small);
+  if (!large.empty()) launch(large, lds_large);
   if (!wide.empty()) launch(wide, 0);
 }
 
