@@ -262,9 +262,10 @@ __global__ __launch_bounds__(256) void k_materialize_r(const PcholTask* __restri
 
 // W = P1 L11^{-T} Z scattered into r x k (precision T): blocked back
 // substitution, one workgroup per (task, chunk of kc right-hand sides) with
-// the chunk of Z in LDS.  Each 32-row diagonal block is solved by the first
-// wavefront (one lane per right-hand side), then subtracted from the rows
-// above it by the whole workgroup.
+// the chunk of Z in LDS.  Each 32-row diagonal block is staged in LDS and
+// solved by the first wavefront (one lane per right-hand side), then
+// subtracted from the rows above it by the whole workgroup.  LDS:
+// r1 * kc + 32 * 32 doubles.
 template <class T>
 __global__ __launch_bounds__(256) void k_wtilde(const WtTask* __restrict__ tasks, int kc) {
   extern __shared__ double zs[];
@@ -279,12 +280,19 @@ __global__ __launch_bounds__(256) void k_wtilde(const WtTask* __restrict__ tasks
     zs[e] = t.Z[a + (int64_t)(c0 + c) * t.ldz];
   }
   __syncthreads();
+  double* Ld = zs + (int64_t)r1 * kc;   // diagonal block: Ld[i + c * 32] = L(lo + i, lo + c)
   for (int hi = r1; hi > 0; hi -= 32) {
     const int lo = hi - 32 > 0 ? hi - 32 : 0;
+    const int h = hi - lo;
+    for (int e = threadIdx.x; e < h * h; e += 256) {
+      const int i = e % h, c = e / h;
+      if (i >= c) Ld[i + c * 32] = L[(lo + i) + (int64_t)(lo + c) * r];
+    }
+    __syncthreads();
     if (threadIdx.x < nc) {
       double* z = zs + threadIdx.x * r1;
       for (int a = hi - 1; a >= lo; --a) {
-        const double* la = L + (int64_t)a * r;
+        const double* la = Ld + (a - lo) * 32 - lo;   // la[b] = L(b, a), b in [a, hi)
         double s = z[a];
         for (int b = a + 1; b < hi; ++b) s -= la[b] * z[b];
         z[a] = s / la[a];

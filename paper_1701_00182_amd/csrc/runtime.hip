@@ -925,9 +925,11 @@ template <class T> void Exec::wtilde(const std::vector<WtTask>& t) {
     r1max = std::max(r1max, x.r1);
     kmax = std::max(kmax, x.k);
   }
+  // chunk of right-hand sides and the 32 x 32 diagonal block of L in LDS, at
+  // most 64 KiB so that two workgroups share a compute unit
   int kc = 64;
-  while (kc > 1 && (size_t)r1max * kc * 8 > 64 * 1024) kc >>= 1;
-  const size_t lds = (size_t)r1max * kc * 8;
+  while (kc > 1 && (size_t)r1max * kc * 8 + 32 * 32 * 8 > 64 * 1024) kc >>= 1;
+  const size_t lds = (size_t)r1max * kc * 8 + 32 * 32 * 8;
   if (lds > kLdsBudget) throw Failure(ST_NOT_SUPPORTED, "rank too large for the back-substitution kernel");
   const int nchunks = (kmax + kc - 1) / kc;
   const WtTask* dt = upload(t);
