@@ -413,80 +413,138 @@ __global__ __launch_bounds__(256) void k_seg_gemm(const SegGemmTask* __restrict_
   }
 }
 
-// FP64 Gram partials on the FP64 matrix cores: for one chunk of rows of a
-// stack S (m x r, precision T) and one upper-triangle pair (bi <= bj) of 64-wide
-// column blocks, part[chunk][i + j r] = sum over the chunk's rows of
-// S[row, i] S[row, j] (FP64 products of the FP32 / FP64 entries).
+// FP64 Gram partials on the FP64 matrix cores.  One wavefront per unit (a
+// chunk of rows of a stack S, m x r in precision T, and an upper-triangle pair
+// bi <= bj of 32-column blocks): part[chunk][i + j r] = sum over the chunk's
+// rows of S[row, i] S[row, j], FP64 products of the FP32 / FP64 entries.
+// Any assignment of rows to the k slots of the 16x16x4 products gives the same
+// sums as long as both operands use it, so lane l takes the RPL consecutive
+// rows starting at RPL (l / 16) of column l % 16 of each 16-column half, read
+// straight into registers with 16-byte loads (no LDS), one row group ahead.
+// A diagonal pair (bi == bj) reads one block and skips the 16 x 16 part
+// below its diagonal, which the reduction never reads.  Narrow stacks (r of a
+// few tens) waste at most a 32-wide tile instead of a 64-wide one.
+template <class T, int RPL> struct RowSlice {
+  T v[2][RPL];
+  __device__ inline void load(const T* const (&p)[2], int k0, bool vec) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const T* q = p[x] + k0;
+      if (vec) {
+        typedef T V __attribute__((ext_vector_type(16 / sizeof(T))));
+        constexpr int W = 16 / sizeof(T);
+#pragma unroll
+        for (int u = 0; u < RPL / W; ++u) {
+          const V y = *reinterpret_cast<const V*>(q + u * W);
+#pragma unroll
+          for (int w = 0; w < W; ++w) v[x][u * W + w] = y[w];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) v[x][u] = q[u];
+      }
+    }
+  }
+  // rows past the chunk's end (kmax rows from the slice start) read as zero
+  __device__ inline void load_tail(const T* const (&p)[2], int k0, int kmax) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) v[x][u] = u < kmax ? p[x][k0 + u] : T(0);
+  }
+};
+
+template <class T, int RPL>
+__device__ inline void gram_step(f64x4 (&acc)[2][2], const RowSlice<T, RPL>& a, const RowSlice<T, RPL>& b,
+                                 bool diag) {
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const double a0 = (double)a.v[0][u], a1 = (double)a.v[1][u];
+    const double b0 = (double)b.v[0][u], b1 = (double)b.v[1][u];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[0][1], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
+    if (!diag) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[1][0], 0, 0, 0);
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_gram_mfma(const GramTask* __restrict__ tasks,
-                                                   const int* __restrict__ tile_task,
-                                                   const int* __restrict__ first_tile) {
-  constexpr int KB = 16;
-  const int ti = tile_task[blockIdx.x];
+                                                   const int* __restrict__ block_task,
+                                                   const int* __restrict__ first_block) {
+  constexpr int RPL = 32 / sizeof(T);   // rows per lane and row group: 32 bytes
+  constexpr int RW = 4 * RPL;           // rows per row group
+  const int ti = block_task[blockIdx.x];
   const GramTask t = tasks[ti];
-  int local = blockIdx.x - first_tile[ti];
-  const int nb = (t.r + 63) / 64, ntri = nb * (nb + 1) / 2;
-  const int chunk = local / ntri;
-  int tri = local - chunk * ntri;
+  const int lane = threadIdx.x & 63;
+  const int nb = (t.r + 31) / 32, ntri = nb * (nb + 1) / 2;
+  const int nch = (t.m + t.rows_per_chunk - 1) / t.rows_per_chunk;
+  const int unit = (blockIdx.x - first_block[ti]) * 4 + (threadIdx.x >> 6);
+  if (unit >= nch * ntri) return;   // no workgroup barrier below
+  const int chunk = unit / ntri;
+  int tri = unit - chunk * ntri;
   int bi = 0;
   while (tri >= nb - bi) { tri -= nb - bi; ++bi; }
   const int bj = bi + tri;
+  const bool diag = bi == bj;
   const int r0 = chunk * t.rows_per_chunk;
-  const int r1 = min(t.m, r0 + t.rows_per_chunk);
+  const int K = min(t.m, r0 + t.rows_per_chunk) - r0;
   const T* S = static_cast<const T*>(t.A);
-  __shared__ double As[KB][64 + 2];
-  __shared__ double Bs[KB][64 + 2];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+  const bool vec = ((reinterpret_cast<uintptr_t>(S) | (uintptr_t)(t.lda * (int64_t)sizeof(T)) |
+                     (uintptr_t)(t.rows_per_chunk * (int64_t)sizeof(T))) & 15) == 0;
+  // columns past r repeat column r - 1; their sums are never written
+  const int c = lane & 15, g = lane >> 4;
+  const T* pa[2];
+  const T* pb[2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    pa[x] = S + (int64_t)min(bi * 32 + 16 * x + c, t.r - 1) * t.lda + r0 + g * RPL;
+    pb[x] = S + (int64_t)min(bj * 32 + 16 * x + c, t.r - 1) * t.lda + r0 + g * RPL;
+  }
   f64x4 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.0;
-  // operand p = column of S inside the block, k = row of S (contiguous)
-  const T* Sa = S + (int64_t)(bi * 64) * t.lda + r0;
-  const T* Sb = S + (int64_t)(bj * 64) * t.lda + r0;
-  const int P_a = min(64, t.r - bi * 64), P_b = min(64, t.r - bj * 64), K = r1 - r0;
-  Stage<T, KB> sa, sb;
-  if (K > 0) {
-    sa.load(Sa, t.lda, 1, P_a, K, 0, 0);
-    sb.load(Sb, t.lda, 1, P_b, K, 0, 0);
-  }
-  for (int k0 = 0; k0 < K; k0 += KB) {
-    sa.store(As, t.lda == 1);
-    sb.store(Bs, t.lda == 1);
-    __syncthreads();
-    if (k0 + KB < K) {
-      sa.load(Sa, t.lda, 1, P_a, K, 0, k0 + KB);
-      sb.load(Sb, t.lda, 1, P_b, K, 0, k0 + KB);
-    }
-#pragma unroll
-    for (int kk = 0; kk < KB; kk += 4) {
-      double a[2], b[2];
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        a[s] = As[kk + (lane >> 4)][wr + 16 * s + (lane & 15)];
-        b[s] = Bs[kk + (lane >> 4)][wc + 16 * s + (lane & 15)];
-      }
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[y], a[x], acc[x][y], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-  double* P = t.part + (int64_t)chunk * t.r * t.r;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
+      for (int v = 0; v < 4; ++v) acc[x][y][v] = 0.0;
+  const int full = K / RW * RW;
+  RowSlice<T, RPL> a, b;
+  if (full > 0) {
+    a.load(pa, 0, vec);
+    if (!diag) b.load(pb, 0, vec);
+  }
+  for (int k0 = 0; k0 < full; k0 += RW) {
+    RowSlice<T, RPL> an, bn;
+    const bool more = k0 + RW < full;
+    if (more) {
+      an.load(pa, k0 + RW, vec);
+      if (!diag) bn.load(pb, k0 + RW, vec);
+    }
+    gram_step(acc, a, diag ? a : b, diag);
+    if (more) {
+      a = an;
+      if (!diag) b = bn;
+    }
+  }
+  if (full < K) {
+    const int kmax = K - full - g * RPL;   // rows of this lane's slice inside the chunk
+    a.load_tail(pa, full, kmax);
+    if (!diag) b.load_tail(pb, full, kmax);
+    gram_step(acc, a, diag ? a : b, diag);
+  }
+  double* P = t.part + (int64_t)chunk * t.r * t.r;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      if (diag && x == 1 && y == 0) continue;
+#pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = bi * 64 + wr + 16 * x + (lane & 15), j = bj * 64 + wc + 16 * y + (lane >> 4) + 4 * v;
+        const int i = bi * 32 + 16 * x + c, j = bj * 32 + 16 * y + g + 4 * v;
         if (i < t.r && j < t.r) P[i + (int64_t)j * t.r] = acc[x][y][v];
       }
+    }
 }
 
 }  // namespace

@@ -2,8 +2,8 @@
 //
 // For a stack S (m x r) too large for one workgroup's local memory, the
 // triangular factor is obtained from the FP64 Gram matrix S^T S (computed on
-// the FP64 matrix cores by many workgroups, each over a chunk of rows and a
-// pair of 64-column blocks -- gemm_mfma.hip -- then reduced in a fixed order)
+// the FP64 matrix cores by many wavefronts, each over a chunk of rows and a
+// pair of 32-column blocks -- gemm_mfma.hip -- then reduced in a fixed order)
 // and a pivoted Cholesky factorisation that stops at the numerical rank:
 //   S P = Q [L11^T L21^T],  Q = S P1 L11^{-T}.
 // The core (L-factors of both stacks) then goes through the same one-sided
@@ -142,11 +142,13 @@ __global__ __launch_bounds__(NT) void k_pchol(const PcholTask* __restrict__ task
 // R (r1 x r, original column order): R[a, perm[i]] = L[i, a] for i >= a.
 // Pivoted Cholesky with the Gram matrix in LDS: its lower triangle packed by
 // columns, kept in pivot order (the rows and columns of each pivot are swapped
-// into place), and right-looking rank-1 updates of the trailing block.  Same
-// outputs as k_pchol: L (r x rank, pivot order, column-major in global
-// memory), perm, the remaining diagonal d in the original order, the rank.
-// One workgroup barrier per step (two when the pivot moves).  LDS:
-// r (r + 1) / 2 doubles and r ints.
+// into place), and right-looking rank-1 updates of the trailing block.  The
+// finished columns stay in LDS, unscaled, and their rows follow every later
+// pivot swap there; L is written to global memory once, at the end, so that no
+// step waits on global memory.  Same outputs as k_pchol: L (r x rank, pivot
+// order, column-major in global memory), perm, the remaining diagonal d in the
+// original order, the rank.  One workgroup barrier per step (two when the
+// pivot moves).  LDS: r (r + 1) / 2 doubles and r ints.
 __device__ inline int packed(int r, int i, int k) { return k * (2 * r - k - 1) / 2 + i; }   // i >= k
 
 template <int NT>
@@ -156,15 +158,21 @@ __global__ __launch_bounds__(NT) void k_pchol_lds(const PcholTask* __restrict__ 
   const int r = t.r;
   double* S = spk;
   int* perm = reinterpret_cast<int*>(S + (size_t)r * (r + 1) / 2);
-  double* L = t.L;
+  auto* L = to_global(t.L);
   constexpr int NW = NT / 64;
   // per-wavefront pivot candidates, double buffered by step parity: the
   // wavefront that updates a column's diagonal proposes it for the next step
   __shared__ double cand[2][NW];
   __shared__ int candi[2][NW];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int k = 0; k < r; ++k)
-    for (int i = k + threadIdx.x; i < r; i += NT) S[packed(r, i, k)] = t.G[i + (int64_t)k * r];
+  // G (column-major) into the packed triangle
+  const auto* Gg = to_global(t.G);
+  staged_copy<NT>(
+      (int64_t)r * r, [&](int64_t e) { return Gg[e]; },
+      [&](int64_t e, double v) {
+        const int k = (int)e / r, i = (int)e - k * r;
+        if (i >= k) S[packed(r, i, k)] = v;
+      });
   for (int i = threadIdx.x; i < r; i += NT) perm[i] = i;
   __syncthreads();
   {
@@ -206,9 +214,10 @@ __global__ __launch_bounds__(NT) void k_pchol_lds(const PcholTask* __restrict__ 
         S[ap] = tmp;
       }
       for (int l = threadIdx.x; l < j; l += NT) {
-        const double a = L[j + (int64_t)l * r];
-        L[j + (int64_t)l * r] = L[p + (int64_t)l * r];
-        L[p + (int64_t)l * r] = a;
+        const int aj = packed(r, j, l), ap = packed(r, p, l);
+        const double a = S[aj];
+        S[aj] = S[ap];
+        S[ap] = a;
       }
       if (threadIdx.x == 0) {
         const double a = S[packed(r, j, j)];
@@ -223,11 +232,6 @@ __global__ __launch_bounds__(NT) void k_pchol_lds(const PcholTask* __restrict__ 
     const double ljj = sqrt(S[packed(r, j, j)]);
     const double inv = 1.0 / ljj;
     const double* cj = S + packed(r, 0, j);   // column j (rows j..), not modified in this step
-    if (threadIdx.x == 0) L[j + (int64_t)j * r] = ljj;
-    for (int i = j + 1 + threadIdx.x; i < r; i += NT) L[i + (int64_t)j * r] = cj[i] * inv;
-    // S(i, k) -= l_i l_k for j < k <= i, l_i = S(i, j) / l_jj: a wavefront per
-    // column, lanes down it; lane 0 of each column's first chunk holds its
-    // new diagonal, the wavefront's candidate for the next pivot
     double v = -INFINITY;
     int vi = 0x7fffffff;
     for (int k = j + 1 + wave; k < r; k += NW) {
@@ -243,6 +247,14 @@ __global__ __launch_bounds__(NT) void k_pchol_lds(const PcholTask* __restrict__ 
     if (lane == 0) { cand[(j + 1) & 1][wave] = v; candi[(j + 1) & 1][wave] = vi; }
     __syncthreads();
     rank = j + 1;
+  }
+  // column j of L: the packed column j (rows moved with every later pivot)
+  // over the square root of its pivot
+  for (int j = 0; j < rank; ++j) {
+    const double ljj = sqrt(S[packed(r, j, j)]);
+    const double inv = 1.0 / ljj;
+    const double* cj = S + packed(r, 0, j);
+    for (int i = j + threadIdx.x; i < r; i += NT) L[i + (int64_t)j * r] = i == j ? ljj : cj[i] * inv;
   }
   for (int i = threadIdx.x; i < r; i += NT) {
     t.perm[i] = perm[i];

@@ -204,8 +204,8 @@ template <class T> void launch_core_left(const SvdTask* d_tasks, int ntasks, int
 template <class T> void launch_applyq_lds(const ApplyQTask* d_tasks, int ntasks, size_t lds, hipStream_t s);
 template <class T> void launch_gram(const GramTask* d_tasks, int ntasks, const int* d_tile_task,
                                    const int* d_first_tile, int ntiles, hipStream_t s);
-// chunk partials of the Gram on the matrix cores (tile map over chunk x upper
-// pairs of 64-column blocks)
+// chunk partials of the Gram on the matrix cores (workgroup map: four
+// wavefronts per workgroup, one per row chunk x upper pair of 32-column blocks)
 template <class T> void launch_gram_mfma(const GramTask* d_tasks, const int* d_tile_task, const int* d_first_tile,
                                         int ntiles, hipStream_t s);
 // lds_packed > 0: the Gram matrices in LDS (packed, right-looking; lds_packed

@@ -165,7 +165,9 @@ __global__ __launch_bounds__(NT) void k_qr_lds(const QrTask* __restrict__ tasks)
   T* a = LDS ? reinterpret_cast<T*>(smq) : A;
   const int64_t la = LDS ? m : t.lda;
   if (LDS)
-    for (int e = threadIdx.x; e < m * r; e += NT) a[e] = A[(e % m) + (int64_t)(e / m) * t.lda];
+    staged_copy<NT>(
+        (int64_t)m * r, [&](int64_t e) { return A[(int)e % m + (int64_t)((int)e / m) * t.lda]; },
+        [&](int64_t e, T v) { a[e] = v; });
   __shared__ double red[NT / 64];
   __shared__ double sh_sig[2];
   const int nref = m < r ? m : r;
@@ -231,12 +233,16 @@ __global__ __launch_bounds__(NT) void k_applyq_lds(const ApplyQTask* __restrict_
   T* o = LDS ? reinterpret_cast<T*>(sma) + m * p : out;
   const int64_t lo = LDS ? m : t.ldo;
   if (LDS)
-    for (int e = threadIdx.x; e < m * p; e += NT)
-      reinterpret_cast<T*>(sma)[e] = Aq[(e % m) + (int64_t)(e / m) * t.lda];
-  for (int e = threadIdx.x; e < m * k; e += NT) {
-    const int i = e % m, c = e / m;
-    o[i + c * lo] = i < p ? T(t.Z[i + (int64_t)c * t.ldz]) : T(0);
-  }
+    staged_copy<NT>(
+        (int64_t)m * p, [&](int64_t e) { return Aq[(int)e % m + (int64_t)((int)e / m) * t.lda]; },
+        [&](int64_t e, T x) { reinterpret_cast<T*>(sma)[e] = x; });
+  staged_copy<NT>(
+      (int64_t)m * k,
+      [&](int64_t e) {
+        const int i = (int)e % m, c = (int)e / m;
+        return i < p ? T(t.Z[i + (int64_t)c * t.ldz]) : T(0);
+      },
+      [&](int64_t e, T x) { o[(int)e % m + ((int)e / m) * lo] = x; });
   __syncthreads();
   for (int j = p - 1; j >= 0; --j) {
     const double tj = (double)tau[j];

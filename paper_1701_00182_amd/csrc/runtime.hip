@@ -822,8 +822,9 @@ template <class T> void Exec::gram(const std::vector<GramTask>& t) {
       check_range(x.G, sizeof(double) * (size_t)x.r * x.r, "gram G");
     }
     first[i] = nt;
-    const int nb = (x.r + 63) / 64, nch = (x.m + x.rows_per_chunk - 1) / x.rows_per_chunk;
-    const int tiles = nch * nb * (nb + 1) / 2;
+    // one wavefront per (row chunk, pair of 32-column blocks), four per workgroup
+    const int nb = (x.r + 31) / 32, nch = (x.m + x.rows_per_chunk - 1) / x.rows_per_chunk;
+    const int tiles = (nch * nb * (nb + 1) / 2 + 3) / 4;
     for (int j = 0; j < tiles; ++j) tile_task.push_back((int)i);
     nt += tiles;
     flops_qr += (double)x.m * x.r * x.r;

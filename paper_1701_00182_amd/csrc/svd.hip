@@ -823,7 +823,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks
   __shared__ double red[NT / 64];
   __shared__ int redi[NT / 64];
   if (LDS)
-    for (int64_t e = threadIdx.x; e < (int64_t)rows * n; e += NT) A[e] = t.Y[e];
+    staged_copy<NT>((int64_t)rows * n, [&](int64_t e) { return t.Y[e]; }, [&](int64_t e, double v) { A[e] = v; });
   __syncthreads();
   int sweeps = 0;
   // the pivot order is no longer needed: its workspace holds the sigma ranks.

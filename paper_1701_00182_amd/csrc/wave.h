@@ -81,4 +81,32 @@ __device__ inline void wave_argmax(double& v, int& i) {
   argmax_step(v, i, __shfl_xor(v, 32, 64), __shfl_xor(i, 32, 64));
 }
 
+// A generic pointer taken as one into global memory.  Generic (flat) accesses
+// count against the LDS wait counter too, so an LDS read after a generic store
+// waits for that store to reach memory; global accesses do not.
+template <class T> __device__ inline __attribute__((address_space(1))) T* to_global(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+// Copy of count elements by a workgroup of NT threads, element e read by
+// load(e) and written by store(e, v): each thread issues B reads before its
+// writes.  A loop of single read-then-write steps waits for every read in
+// turn, since a generic-pointer read may alias the LDS written before it.
+template <int NT, int B = 8, class Load, class Store>
+__device__ inline void staged_copy(int64_t count, Load load, Store store) {
+  for (int64_t e0 = 0; e0 < count; e0 += (int64_t)B * NT) {
+    decltype(load(int64_t(0))) v[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int64_t e = e0 + b * NT + threadIdx.x;
+      if (e < count) v[b] = load(e);
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int64_t e = e0 + b * NT + threadIdx.x;
+      if (e < count) store(e, v[b]);
+    }
+  }
+}
+
 }  // namespace acr

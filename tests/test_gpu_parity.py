@@ -117,11 +117,15 @@ def test_gmres_convdiff_fp32_eps1e2_to_1e10():
     fac.free()
 
 
+@pytest.mark.parametrize("n", [32, 22])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_gram_compression_matches_householder(prec, monkeypatch):
-    """Large blocks take the Gram compression path; it must agree with the
-    Householder path (forced with ACR_GRAM=0) to the truncation level."""
-    n, leaf, eps = 32, 32, 1e-3
+def test_gram_compression_matches_householder(prec, n, monkeypatch):
+    """Blocks take the Gram compression path at this eps; it must agree with
+    the Householder path (forced with ACR_GRAM=0) to the truncation level.
+    n = 32 gives block sizes that are multiples of 32 (whole row groups and
+    16-byte aligned columns); n = 22 gives odd block sizes (ragged row tails
+    and columns read one element at a time)."""
+    leaf, eps = 32, 1e-3
     coef = problem("convdiff", n)
     f = rhs_normal(n ** 3)
     A = operator_from_coef(coef)
