@@ -197,9 +197,12 @@ __global__ __launch_bounds__(NT) void k_pchol_lds(const PcholTask* __restrict__ 
   const bool zero = !(mx > 0.0);
   int rank = 0;
   for (int j = 0; j < r && !zero; ++j) {
+    // the pivot: argmax over the NW candidates, read from the first lane
     double best = lane < NW ? cand[j & 1][lane] : -INFINITY;
     int p = lane < NW ? candi[j & 1][lane] : 0x7fffffff;
-    wave_argmax(best, p);
+    group_argmax<NW>(best, p);
+    best = read_first_lane(best);
+    p = __builtin_amdgcn_readfirstlane(p);
     if (!(best > thr)) break;
     if (p != j) {
       // swap positions j and p among the remaining ones (rows and columns of
@@ -232,6 +235,11 @@ __global__ __launch_bounds__(NT) void k_pchol_lds(const PcholTask* __restrict__ 
     const double ljj = sqrt(S[packed(r, j, j)]);
     const double inv = 1.0 / ljj;
     const double* cj = S + packed(r, 0, j);   // column j (rows j..), not modified in this step
+    // S(i, k) -= l_i l_k for j < k <= i, l_i = S(i, j) / l_jj: a wavefront per
+    // column, lanes down it.  Row k of column k is lane 0's first row, so lane
+    // 0 alone holds the wavefront's candidate for the next pivot (the largest
+    // new diagonal, the first column on ties).  Two or four columns per pass
+    // with their reads in flight together measured no faster.
     double v = -INFINITY;
     int vi = 0x7fffffff;
     for (int k = j + 1 + wave; k < r; k += NW) {
@@ -243,7 +251,6 @@ __global__ __launch_bounds__(NT) void k_pchol_lds(const PcholTask* __restrict__ 
         if (i == k && x > v) { v = x; vi = k; }
       }
     }
-    wave_argmax(v, vi);
     if (lane == 0) { cand[(j + 1) & 1][wave] = v; candi[(j + 1) & 1][wave] = vi; }
     __syncthreads();
     rank = j + 1;

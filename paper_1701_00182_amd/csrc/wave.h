@@ -81,6 +81,24 @@ __device__ inline void wave_argmax(double& v, int& i) {
   argmax_step(v, i, __shfl_xor(v, 32, 64), __shfl_xor(i, 32, 64));
 }
 
+// Argmax over aligned groups of G lanes (G a power of two up to 16), with the
+// same tie rule: the DPP steps of wave_argmax that stay inside the group.
+template <int G> __device__ inline void group_argmax(double& v, int& i) {
+  static_assert(G >= 1 && G <= 16 && (G & (G - 1)) == 0, "group of 1 to 16 lanes");
+  if (G >= 2) argmax_step(v, i, dpp_mov<0xB1>(v), dpp_mov_i<0xB1>(i));
+  if (G >= 4) argmax_step(v, i, dpp_mov<0x4E>(v), dpp_mov_i<0x4E>(i));
+  if (G >= 8) argmax_step(v, i, dpp_mov<0x141>(v), dpp_mov_i<0x141>(i));
+  if (G >= 16) argmax_step(v, i, dpp_mov<0x140>(v), dpp_mov_i<0x140>(i));
+}
+
+// The value of the first active lane, on every lane (a wavefront-uniform value).
+__device__ inline double read_first_lane(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(unsigned)b);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // A generic pointer taken as one into global memory.  Generic (flat) accesses
 // count against the LDS wait counter too, so an LDS read after a generic store
 // waits for that store to reach memory; global accesses do not.
