@@ -82,28 +82,6 @@ template <int NT> __device__ inline void block_argmax(double& v, int& i, double*
   wargmax(v, i);
 }
 
-// Workgroup argmax of (v, i) and sum of s in one exchange (ties go to the
-// smaller index; all threads must call it).
-template <int NT>
-__device__ inline void block_argmax_sum(double& v, int& i, double& s, double* red, int* redi, double* reds) {
-  wargmax(v, i);
-  s = wsum(s);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
-    red[threadIdx.x >> 6] = v;
-    redi[threadIdx.x >> 6] = i;
-    reds[threadIdx.x >> 6] = s;
-  }
-  __syncthreads();
-  // every wavefront combines the per-wavefront results in parallel
-  const int l = threadIdx.x & 63;
-  v = l < NT / 64 ? red[l] : -INFINITY;
-  i = l < NT / 64 ? redi[l] : 0x7fffffff;
-  s = l < NT / 64 ? reds[l] : 0.0;
-  wargmax(v, i);
-  s = wsum(s);
-}
-
 // Lanes per column group for one step of a Householder sweep over `cols`
 // trailing columns of `rows` live rows with nt threads: enough groups to take
 // every column at once (short shuffle reductions, no column queue per group),
@@ -256,7 +234,13 @@ __device__ __forceinline__ int qrcp_body(double* C, int64_t lc, int p, int q, do
   // stop when the Frobenius norm of the remaining block (rows and columns j..)
   // is at most delta * (largest column norm): nrm holds its column norms
   const double thr2 = delta * delta * mx;
-  __shared__ double reds[NT / 64];
+  // per-wavefront pivot candidates and partial sums, double buffered by step
+  // parity: a buffer is written again two steps later, after barriers that
+  // every reader of it has passed, so no barrier is needed before the writes
+  constexpr int NW = NT / 64;
+  __shared__ double cv[2][NW], cs[2][NW];
+  __shared__ int ci[2][NW];
+  const int lane = threadIdx.x & 63;
   int tcount = 0;
   for (int j = 0; j < mn; ++j) {
     double best = -1.0, rest = 0.0;
@@ -265,7 +249,19 @@ __device__ __forceinline__ int qrcp_body(double* C, int64_t lc, int p, int q, do
       rest += nrm[c];
       if (nrm[c] > best) { best = nrm[c]; bc = c; }
     }
-    block_argmax_sum<NT>(best, bc, rest, red, redi, reds);
+    wargmax(best, bc);
+    rest = wsum(rest);
+    if (lane == 0) { cv[j & 1][threadIdx.x >> 6] = best; ci[j & 1][threadIdx.x >> 6] = bc; cs[j & 1][threadIdx.x >> 6] = rest; }
+    __syncthreads();
+    // the NW candidates combined in log2(NW) steps, read from the first lane
+    best = lane < NW ? cv[j & 1][lane] : -INFINITY;
+    bc = lane < NW ? ci[j & 1][lane] : 0x7fffffff;
+    rest = lane < NW ? cs[j & 1][lane] : 0.0;
+    group_argmax<NW>(best, bc);
+    rest = gsum_dpp(rest, NW);
+    best = read_first_lane(best);
+    bc = __builtin_amdgcn_readfirstlane(bc);
+    rest = read_first_lane(rest);
     if (!(rest > thr2) || !(best > 0.0)) break;
     const int pc = bc;
     if (pc != j) {
