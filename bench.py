@@ -487,6 +487,10 @@ PMC_CLASSES = [
     ("k_qr_lds<float", "qr_lds", ["paper_1701_00182_amd/csrc/la_lds.hip", "paper_1701_00182_amd/csrc/wave.h"]),
     ("k_applyq_lds<float", "applyq_lds", ["paper_1701_00182_amd/csrc/la_lds.hip", "paper_1701_00182_amd/csrc/wave.h"]),
     ("k_pchol", "pchol", ["paper_1701_00182_amd/csrc/gram.hip", "paper_1701_00182_amd/csrc/wave.h"]),
+    ("k_gram", "gram", ["paper_1701_00182_amd/csrc/gemm_mfma.hip", "paper_1701_00182_amd/csrc/gram.hip"]),
+    ("k_wtilde<float>", "wtilde", ["paper_1701_00182_amd/csrc/gram.hip"]),
+    ("k_inverse<float", "inverse", ["paper_1701_00182_amd/csrc/la_kernels.hip"]),
+    ("k_copy<float>", "copy", ["paper_1701_00182_amd/csrc/la_kernels.hip"]),
     ("k_apply_leaf_vec<float>", "solve_leaf", ["paper_1701_00182_amd/csrc/solve_kernels.hip"]),
     ("k_inner_vec<float>", "solve_inner", ["paper_1701_00182_amd/csrc/solve_kernels.hip"]),
 ]
