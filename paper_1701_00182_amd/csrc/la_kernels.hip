@@ -9,6 +9,7 @@
 // Gram path) live in la_lds.hip, svd.hip and gram.hip; the matrix-core GEMM
 // in gemm_mfma.hip.
 #include "kern.h"
+#include "wave.h"
 
 #include <cfloat>
 #include <cmath>
@@ -104,7 +105,9 @@ __global__ __launch_bounds__(NT) void k_inverse(const InvTask* __restrict__ task
     a = reinterpret_cast<T*>(smem_d);
     la = s;
     piv = reinterpret_cast<int*>(a + (int64_t)s * s);
-    for (int e = threadIdx.x; e < s * s; e += NT) a[e] = g[(e % s) + (int64_t)(e / s) * t.lda];
+    staged_copy<NT>(
+        (int64_t)s * s, [&](int64_t e) { return g[(int)e % s + (int64_t)((int)e / s) * t.lda]; },
+        [&](int64_t e, T v) { a[e] = v; });
   } else {
     a = g;
     la = t.lda;
@@ -144,9 +147,30 @@ __global__ __launch_bounds__(NT) void k_inverse(const InvTask* __restrict__ task
     const T pv = a[j + j * la];
     if (!(pv != T(0)) || !isfinite((double)pv)) bad = true;
     const T inv = T(1) / pv;
-    for (int64_t e = threadIdx.x; e < (int64_t)s * s; e += NT) {
-      const int i = (int)(e % s), c = (int)(e / s);
-      if (i != j && c != j) a[i + c * la] -= a[i + j * la] * (a[j + c * la] * inv);
+    // a[i, c] -= a[i, j] (a[j, c] / pivot) for i, c != j: a wavefront per
+    // column, lanes down the rows; column j's entries for a lane's rows are
+    // read once per step (kInvRows per lane in registers, larger s in a loop)
+    {
+      constexpr int NW = NT / 64, kInvRows = 4;
+      const int lane = threadIdx.x & 63;
+      T aj[kInvRows];
+#pragma unroll
+      for (int u = 0; u < kInvRows; ++u) {
+        const int i = lane + 64 * u;
+        aj[u] = i < s ? a[i + j * la] : T(0);
+      }
+      for (int c = threadIdx.x >> 6; c < s; c += NW) {
+        if (c == j) continue;
+        T* col = a + c * la;
+        const T rj = col[j] * inv;
+#pragma unroll
+        for (int u = 0; u < kInvRows; ++u) {
+          const int i = lane + 64 * u;
+          if (i < s && i != j) col[i] -= aj[u] * rj;
+        }
+        for (int i = lane + 64 * kInvRows; i < s; i += 64)
+          if (i != j) col[i] -= a[i + j * la] * rj;
+      }
     }
     __syncthreads();
     for (int c = threadIdx.x; c < s; c += NT)
@@ -169,7 +193,8 @@ __global__ __launch_bounds__(NT) void k_inverse(const InvTask* __restrict__ task
     __syncthreads();
   }
   if (LDS) {
-    for (int e = threadIdx.x; e < s * s; e += NT) g[(e % s) + (int64_t)(e / s) * t.lda] = a[e];
+    for (int c = threadIdx.x >> 6; c < s; c += NT / 64)
+      for (int i = threadIdx.x & 63; i < s; i += 64) g[i + (int64_t)c * t.lda] = a[i + c * s];
   }
   if (bad && threadIdx.x == 0) atomicOr(&flags[FLAG_SINGULAR], 1);
 }

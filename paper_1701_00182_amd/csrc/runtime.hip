@@ -534,9 +534,12 @@ template <class T> void Exec::copy(const std::vector<CopyTask>& t) {
   for (auto& x : t) w.bytes += sizeof(T) * (double)x.m * x.n * ((x.src ? 1 : 0) + 1 + (x.accumulate ? 1 : 0));
   int64_t units = 1;
   for (auto& x : t) units = std::max<int64_t>(units, (int64_t)x.n * ((x.m + 2047) / 2048));
-  const int gy = (int)std::min<int64_t>(units, 64);
-  const CopyTask* dt = upload(t);
+  // workgroups per task along y: at least 64, and enough that a launch of few
+  // tasks still spreads over the whole chip (about 4096 workgroups; a single
+  // large copy on 64 workgroups ran one column chunk after another)
   const int n = (int)t.size();
+  const int gy = (int)std::min<int64_t>(units, std::max<int64_t>(64, (4096 + n - 1) / n));
+  const CopyTask* dt = upload(t);
   submit([=](hipStream_t s) { launch_copy<T>(dt, n, gy, s); }, w);
 }
 
