@@ -294,10 +294,9 @@ __global__ __launch_bounds__(256) void k_wtilde(const WtTask* __restrict__ tasks
   if (c0 >= k) return;
   const int nc = k - c0 < kc ? k - c0 : kc;
   const double* L = t.L;
-  for (int e = threadIdx.x; e < r1 * nc; e += 256) {
-    const int a = e % r1, c = e / r1;
-    zs[e] = t.Z[a + (int64_t)(c0 + c) * t.ldz];
-  }
+  staged_copy<256>(
+      (int64_t)r1 * nc, [&](int64_t e) { return t.Z[(int)e % r1 + (int64_t)(c0 + (int)e / r1) * t.ldz]; },
+      [&](int64_t e, double v) { zs[e] = v; });
   __syncthreads();
   double* Ld = zs + (int64_t)r1 * kc;   // diagonal block: Ld[i + c * 32] = L(lo + i, lo + c)
   for (int hi = r1; hi > 0; hi -= 32) {
@@ -318,13 +317,28 @@ __global__ __launch_bounds__(256) void k_wtilde(const WtTask* __restrict__ tasks
       }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < lo * nc; e += 256) {
-      const int b = e % lo, c = e / lo;
-      const double* lb = L + (int64_t)b * r;
-      const double* z = zs + c * r1;
-      double s = 0.0;
-      for (int a = lo; a < hi; ++a) s += lb[a] * z[a];
-      zs[b + c * r1] -= s;
+    // z[b, c] -= sum over a in [lo, hi) of L(a, b) z[a, c] for b < lo: a thread
+    // per (b, group of kWtCols columns) reads L(lo..hi, b) once into registers
+    // for the whole group (one read per column before)
+    {
+      constexpr int kWtCols = 4;
+      const int ng = (nc + kWtCols - 1) / kWtCols;
+      for (int e = threadIdx.x; e < lo * ng; e += 256) {
+        const int b = e % lo, g = e / lo;
+        const double* lb = L + (int64_t)b * r + lo;   // lb[u] = L(lo + u, b)
+        double lv[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) lv[u] = u < h ? lb[u] : 0.0;
+        const int cend = nc < (g + 1) * kWtCols ? nc : (g + 1) * kWtCols;
+        for (int c = g * kWtCols; c < cend; ++c) {
+          const double* z = zs + c * r1 + lo;
+          double s = 0.0;
+#pragma unroll
+          for (int u = 0; u < 32; ++u)
+            if (u < h) s += lv[u] * z[u];
+          zs[b + c * r1] -= s;
+        }
+      }
     }
     __syncthreads();
   }
