@@ -21,12 +21,14 @@ namespace {
 __global__ __launch_bounds__(256) void k_gram_reduce(const GramTask* __restrict__ tasks) {
   const GramTask t = tasks[blockIdx.x];
   const int nchunk = (t.m + t.rows_per_chunk - 1) / t.rows_per_chunk;
-  const int64_t rr = (int64_t)t.r * t.r;
-  for (int64_t e = threadIdx.x + (int64_t)blockIdx.y * 256; e < rr; e += (int64_t)gridDim.y * 256) {
-    const int i = (int)(e % t.r), j = (int)(e / t.r);
+  // r^2 fits 32 bits (the host rejects wider stacks): 32-bit division for the
+  // element index, not the much longer 64-bit one
+  const int rr = t.r * t.r;
+  for (int e = threadIdx.x + blockIdx.y * 256; e < rr; e += gridDim.y * 256) {
+    const int i = e % t.r, j = e / t.r;
     if (i > j) continue;
     double s = 0.0;
-    for (int c = 0; c < nchunk; ++c) s += t.part[c * rr + e];
+    for (int c = 0; c < nchunk; ++c) s += t.part[(int64_t)c * rr + e];
     t.G[i + (int64_t)j * t.r] = s;
     t.G[j + (int64_t)i * t.r] = s;
   }
@@ -273,8 +275,8 @@ __global__ __launch_bounds__(NT) void k_pchol_lds(const PcholTask* __restrict__ 
 __global__ __launch_bounds__(256) void k_materialize_r(const PcholTask* __restrict__ tasks) {
   const PcholTask t = tasks[blockIdx.x];
   const int r = t.r, r1 = t.r1;
-  for (int64_t e = threadIdx.x + (int64_t)blockIdx.y * 256; e < (int64_t)r1 * r; e += (int64_t)gridDim.y * 256) {
-    const int a = (int)(e % r1), i = (int)(e / r1);
+  for (int e = threadIdx.x + blockIdx.y * 256; e < r1 * r; e += gridDim.y * 256) {
+    const int a = e % r1, i = e / r1;
     t.R[a + (int64_t)t.perm[i] * r1] = i >= a ? t.L[i + (int64_t)a * r] : 0.0;
   }
 }

@@ -818,6 +818,8 @@ template <class T> void Exec::gram(const std::vector<GramTask>& t) {
   int nt = 0;
   for (size_t i = 0; i < t.size(); ++i) {
     const GramTask& x = t[i];
+    // the reduction indexes the r x r partials with 32-bit integers
+    if ((int64_t)x.r * x.r > 0x7fffffff) throw Failure(ST_NOT_SUPPORTED, "stack too wide for the Gram kernels");
     if (checking) {
       check_range(x.A, sizeof(T) * ext(x.m, x.r, x.lda), "gram A");
       const int nch = (x.m + x.rows_per_chunk - 1) / x.rows_per_chunk;
