@@ -18,6 +18,10 @@
  *  - One handle may be used by one host thread at a time.  Calls are ordered
  *    on the stream passed in; acr_factor synchronises that stream before it
  *    returns, the solve calls do not (outputs are ready when the stream is).
+ *    A call on a handle issued on another stream than the handle's previous
+ *    call first makes its stream wait for the previous one (the handle's
+ *    solve buffers are shared by its calls); acr_free synchronises every
+ *    stream the handle was used on before it releases memory.
  */
 #ifndef ACR_H
 #define ACR_H
@@ -107,7 +111,7 @@ acr_status_t acr_solve(acr_handle_t h, int32_t nrhs, const double* b, int64_t ld
 acr_status_t acr_solve_transpose(acr_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x,
                                  int64_t ldx, hipStream_t stream);
 
-/* Releases the handle and all its memory after synchronising its last stream. NULL-safe. */
+/* Releases the handle and all its memory after synchronising every stream it was used on. NULL-safe. */
 void acr_free(acr_handle_t h);
 
 typedef struct {
@@ -178,6 +182,54 @@ acr_status_t acr_kappa_gradient(int32_t nx, int32_t ny, int32_t nz, const double
                                 const double* lam, double* grad, hipStream_t stream);
 
 const char* acr_status_string(acr_status_t s);
+
+/*
+ * Structure of a factorisation (integer set-up of the path): the planar
+ * bisection cluster tree of a plane (Section 2.1.1: a box is split across its
+ * longer side, x on ties, the first part keeping ceil(side/2) grid lines; every
+ * box of a depth is split while any box of that depth holds more than leaf
+ * points; points are numbered leaf by leaf, first part first, x fastest inside
+ * a leaf), the permutation from cluster order to the natural in-plane index,
+ * and the red/black level schedule of Section 2.2.2 (Eq. permuted_system,
+ * Eq. next_step: the planes at even positions of a level are eliminated, the
+ * others renumbered for the next level, until one plane is left).
+ *
+ * Sizes go to *info; every array argument may be NULL (then it is skipped),
+ * otherwise it must hold the number of entries named here:
+ *   perm[M]                 cluster position p -> natural index j*nx + i
+ *   node_offset[nodes], node_size[nodes]
+ *                           node (depth d, segment s) at index 2^d - 1 + s:
+ *                           first cluster position and number of points
+ *   level_size[levels]      planes alive at level i
+ *   sched_plane[schedule_len], sched_elim[schedule_len]
+ *                           the alive planes of every level in order, level
+ *                           after level (original plane numbers), and 1 for
+ *                           a plane eliminated at that level, 0 for a kept one
+ * The usual pattern is one call with NULL arrays for the sizes, then a second.
+ */
+typedef struct {
+  int32_t M;             /* points per plane, nx * ny                          */
+  int32_t depth;         /* HODLR depth L: the leaves are the nodes of depth L */
+  int32_t nodes;         /* 2^(L+1) - 1                                        */
+  int32_t levels;        /* cyclic-reduction levels q                          */
+  int32_t schedule_len;  /* sum over the levels of the planes alive            */
+  int32_t last_plane;    /* the plane left after the last level                */
+} acr_structure_t;
+
+/* Host only, no device work: the structure acr_factor would build for these
+ * sizes.  ACR_ERROR_INVALID_VALUE for non-positive sizes, a null info, or a
+ * leaf size that would split a single point. */
+acr_status_t acr_plan_structure(int32_t nx, int32_t ny, int32_t nplanes, int32_t leaf, acr_structure_t* info,
+                                int32_t* perm, int32_t* node_offset, int32_t* node_size, int32_t* level_size,
+                                int32_t* sched_plane, int32_t* sched_elim);
+
+/* The structure a handle was factorised with: perm is read back from the
+ * device copy the solves use (synchronous copy), the schedule from the levels
+ * the factorisation stored (a plane counts as eliminated when its inverse was
+ * stored at that level).  Arrays and errors as for acr_plan_structure. */
+acr_status_t acr_get_structure(acr_handle_t h, acr_structure_t* info, int32_t* perm, int32_t* node_offset,
+                               int32_t* node_size, int32_t* level_size, int32_t* sched_plane,
+                               int32_t* sched_elim);
 
 /*
  * Autotuner for the leaf size and the core-SVD dispatch (the tile-size knobs of

@@ -53,6 +53,11 @@ class Stats(ctypes.Structure):
                 ("level_avg_rank", ctypes.c_double * 32)]
 
 
+class Structure(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("depth", ctypes.c_int32), ("nodes", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("schedule_len", ctypes.c_int32), ("last_plane", ctypes.c_int32)]
+
+
 class RefineOptions(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("transpose", ctypes.c_int32)]
@@ -65,7 +70,7 @@ class RefineResult(ctypes.Structure):
 
 EXPORTS = ("acr_options_default", "acr_factor", "acr_solve", "acr_solve_transpose", "acr_free",
            "acr_get_stats", "acr_solve_refined", "acr_residual", "acr_assemble_diffusion",
-           "acr_kappa_gradient", "acr_status_string")
+           "acr_kappa_gradient", "acr_status_string", "acr_plan_structure", "acr_get_structure")
 
 
 def lib():
@@ -101,10 +106,43 @@ def lib():
         L.acr_autotune.argtypes = [ctypes.POINTER(Options), vp, i32, ctypes.c_char_p, vp,
                                     ctypes.POINTER(TuneResult)]
         L.acr_autotune.restype = ctypes.c_int
+        p32 = ctypes.POINTER(ctypes.c_int32)
+        L.acr_plan_structure.argtypes = [i32, i32, i32, i32, ctypes.POINTER(Structure)] + [p32] * 6
+        L.acr_plan_structure.restype = ctypes.c_int
+        L.acr_get_structure.argtypes = [vp, ctypes.POINTER(Structure)] + [p32] * 6
+        L.acr_get_structure.restype = ctypes.c_int
         L.acr_last_error_message.argtypes = []
         L.acr_last_error_message.restype = ctypes.c_char_p
         _LIB = L
     return _LIB
+
+
+def _structure(call, where):
+    """Two-call pattern of the structure queries: sizes, then the arrays."""
+    import numpy as np
+    info = Structure()
+    _check(call(ctypes.byref(info), *([None] * 6)), where)
+    arrs = [np.zeros(max(n, 1), dtype=np.int32) for n in
+            (info.M, info.nodes, info.nodes, info.levels, info.schedule_len, info.schedule_len)]
+    ptrs = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for a in arrs]
+    _check(call(ctypes.byref(info), *ptrs), where)
+    perm, noff, nsz, lsz, splane, selim = arrs
+    sched, pos = [], 0
+    for i in range(info.levels):
+        m = int(lsz[i])
+        sched.append({"alive": splane[pos:pos + m].tolist(), "elim": selim[pos:pos + m].tolist()})
+        pos += m
+    return {"M": info.M, "depth": info.depth, "perm": perm[:info.M], "node_offset": noff[:info.nodes],
+            "node_size": nsz[:info.nodes], "schedule": sched, "last_plane": info.last_plane}
+
+
+def plan_structure(nx, ny, nplanes, leaf):
+    """Cluster tree, permutation and level schedule for these sizes (host only,
+    acr_plan_structure): dict with M, depth, perm, node_offset / node_size (node
+    (d, s) at index 2^d - 1 + s), schedule (per level the alive planes and a 0/1
+    eliminated flag per plane) and last_plane."""
+    L = lib()
+    return _structure(lambda info, *a: L.acr_plan_structure(nx, ny, nplanes, leaf, info, *a), "acr_plan_structure")
 
 
 def _stream():
@@ -196,6 +234,12 @@ class Factor:
         _check(lib().acr_residual(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(b.data_ptr()),
                                   ctypes.c_void_p(r.data_ptr()), 1 if transpose else 0, _stream()), "acr_residual")
         return r
+
+    def structure(self):
+        """The structure this handle was factorised with (acr_get_structure; the
+        permutation read back from the device); same dict as plan_structure."""
+        L = lib()
+        return _structure(lambda info, *a: L.acr_get_structure(self._h, info, *a), "acr_get_structure")
 
     def stats(self):
         st = Stats()

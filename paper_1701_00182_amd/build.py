@@ -1,8 +1,9 @@
 """Build the ACR shared library (libacr.so) for gfx950 with hipcc, in-tree.
 
 Usage: python -m paper_1701_00182_amd.build [--debug]
-Every source under csrc/ is compiled to an object in _build/ (in parallel) and
-linked into paper_1701_00182_amd/libacr.so next to this file.
+Every HIP source under csrc/ is compiled by hipcc, every host-only C++ source
+(csrc/*.cpp: no device code) by g++, to objects in _build/ (in parallel), and
+all are linked into paper_1701_00182_amd/libacr.so next to this file.
 """
 import concurrent.futures as cf
 import glob
@@ -16,6 +17,9 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libacr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CXX = os.environ.get("CXX", "g++")
+ROCM_INCLUDE = "/opt/rocm/include"
+HOST = ["-std=c++17", "-fPIC", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__", "-I", ROCM_INCLUDE]
 
 COMMON = [
     "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
@@ -25,19 +29,27 @@ COMMON = [
 ]
 
 
+def host_flags():
+    """g++ flags of the host-only sources (also used by the sanitizer test)."""
+    return HOST + ["-I", os.path.join(ROOT, "include")]
+
+
 def _compile(src, opt):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + opt + ["-c", src, "-o", obj]
+    if src.endswith(".cpp"):
+        cmd = [CXX] + host_flags() + opt + ["-c", src, "-o", obj]
+    else:
+        cmd = [HIPCC] + COMMON + opt + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")
+        raise RuntimeError(f"compile failed for {src}:\n{r.stderr[-6000:]}")
     return obj
 
 
 def build(debug=False, verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     opt = ["-O0", "-g"] if debug else ["-O3"]
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
     with cf.ThreadPoolExecutor(max_workers=jobs) as pool:
         objs = list(pool.map(lambda s: _compile(s, opt), srcs))

@@ -45,13 +45,33 @@ struct FactorBase {
   virtual void solve(int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, bool trans,
                      hipStream_t s) = 0;
   virtual void stats(acr_stats_t* st) = 0;
+  virtual void structure(acr_structure_t* info, int32_t* perm, int32_t* node_offset, int32_t* node_size,
+                         int32_t* level_size, int32_t* sched_plane, int32_t* sched_elim) = 0;
   Grid grid{};
   Exec ex;
   double* coef = nullptr;   // FP64 stencil copy
   Arena persist;            // factors, stencil copy, plans' small data
   Arena refine_mem;         // Krylov workspace of acr_solve_refined
   int refine_cap = -1;
+  // Streams the handle's work was issued on.  Work on a new stream waits for
+  // the last one (the solve plans, the refinement workspace and the stored
+  // right-hand-side buffers are shared by every call), and acr_free
+  // synchronises all of them before memory is released.
   hipStream_t last_stream = nullptr;
+  std::vector<hipStream_t> streams;
+  hipEvent_t order_ev = nullptr;
+  void use_stream(hipStream_t s) {
+    if (!streams.empty() && s != last_stream) {
+      if (!order_ev) hip_check(hipEventCreateWithFlags(&order_ev, hipEventDisableTiming), "hipEventCreate");
+      hip_check(hipEventRecord(order_ev, last_stream), "hipEventRecord(order)");
+      hip_check(hipStreamWaitEvent(s, order_ev, 0), "hipStreamWaitEvent(order)");
+    }
+    if (std::find(streams.begin(), streams.end(), s) == streams.end()) streams.push_back(s);
+    last_stream = s;
+  }
+  void sync_all_streams() {
+    for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
+  }
 };
 
 template <class T> struct Level {
@@ -603,6 +623,7 @@ template <class T> struct FactorT : FactorBase {
   }
 
   void solve(int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, bool trans, hipStream_t s) override {
+    use_stream(s);
     ex.stream = s;
     Plan* pl = plan_for(nrhs, trans);
     launch_perm_in<T>(grid, nrhs, b, ldb, d_perm, static_cast<T*>(pl->W), s);
@@ -610,7 +631,27 @@ template <class T> struct FactorT : FactorBase {
     run_plan(pl, s);
     launch_perm_out<T>(grid, nrhs, static_cast<const T*>(pl->Ub), d_perm, x, ldx, s);
     hip_check(hipGetLastError(), "perm_out");
-    last_stream = s;
+  }
+
+  // ---------------------------------------------------------- structure
+  void structure(acr_structure_t* info, int32_t* perm, int32_t* node_offset, int32_t* node_size,
+                 int32_t* level_size, int32_t* sched_plane, int32_t* sched_elim) override {
+    std::vector<std::vector<int>> sched;
+    std::vector<std::vector<char>> elim;
+    for (auto& L : lev) {
+      sched.push_back(L.alive);
+      std::vector<char> e(L.alive.size(), 0);
+      for (size_t q = 0; q < L.alive.size(); ++q) e[q] = L.G[q].absent() ? 0 : 1;
+      elim.push_back(std::move(e));
+    }
+    std::vector<int32_t> dp;
+    if (perm) {
+      // the permutation the solve kernels use, read back from the device
+      dp.resize(tr.M);
+      hip_check(hipMemcpy(dp.data(), d_perm, tr.M * sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy(perm)");
+    }
+    fill_structure(tr, sched, elim, last, perm ? dp.data() : nullptr, info, perm, node_offset, node_size,
+                   level_size, sched_plane, sched_elim);
   }
 
   // ---------------------------------------------------------- statistics
@@ -706,7 +747,7 @@ FactorBase* make_factor(const acr_options_t* o, const double* coef_in, hipStream
   if (fl[FLAG_INVALID]) throw Failure(ST_INVALID, "stencil entry reaching outside the grid is non-zero");
   if (fl[FLAG_NONFINITE]) throw Failure(ST_SINGULAR, "non-finite stencil value");
   f->factor();
-  f->last_stream = s;
+  f->use_stream(s);
   return f.release();
 }
 
@@ -737,6 +778,7 @@ struct Krylov {
 
 int refine(FactorBase& f, const acr_refine_options_t& ro, const double* b, double* x, hipStream_t s,
            acr_refine_result_t* res, double* hist, int hlen) {
+  f.use_stream(s);
   const int64_t N = f.grid.N();
   // Krylov basis vectors: GMRES(m) keeps m + 1, CG uses four (p, A p, z, r_old)
   const int m = ro.method == 1 ? std::max(1, ro.restart > 0 ? ro.restart : 30) : (ro.method == 2 ? 3 : 1);
@@ -917,18 +959,6 @@ template <class F> acr_status_t guarded(F&& fn) {
   }
 }
 
-bool valid_opts(const acr_options_t* o) {
-  if (!o) return false;
-  if (o->nx < 1 || o->ny < 1 || o->nplanes < 1 || o->leaf < 1) return false;
-  if (!(o->eps >= 0.0) || !std::isfinite(o->eps)) return false;
-  if (o->max_rank < 0) return false;
-  if (o->precision < ACR_PREC_FP64 || o->precision > ACR_PREC_FP32_FP16LEAF) return false;
-  if ((o->alloc == nullptr) != (o->release == nullptr)) return false;
-  if (!(o->inner_eps_ratio >= 0.0)) return false;
-  if ((int64_t)o->nx * o->ny > (int64_t)1 << 28) return false;
-  return true;
-}
-
 std::string tune_key(const acr_options_t* o, int sp) {
   char k[256];
   std::snprintf(k, sizeof(k), "nx=%d ny=%d planes=%d eps=%.17g precision=%d max_rank=%d inner=%.17g", o->nx, o->ny,
@@ -1060,7 +1090,7 @@ void acr_options_default(acr_options_t* o) {
 
 acr_status_t acr_factor(const acr_options_t* opt, const double* coef, hipStream_t stream, acr_handle_t* out) {
   if (out) *out = nullptr;
-  if (!out || !coef || !valid_opts(opt)) return ACR_ERROR_INVALID_VALUE;
+  if (!out || !coef || !options_valid(opt)) return ACR_ERROR_INVALID_VALUE;
   return guarded([&]() -> acr_status_t {
     FactorBase* f = opt->precision == ACR_PREC_FP64 ? make_factor<double>(opt, coef, stream)
                                                      : make_factor<float>(opt, coef, stream);
@@ -1096,7 +1126,8 @@ acr_status_t acr_solve_transpose(acr_handle_t h, int32_t nrhs, const double* b, 
 void acr_free(acr_handle_t h) {
   if (!h) return;
   if (h->impl) {
-    if (h->impl->last_stream) (void)hipStreamSynchronize(h->impl->last_stream);
+    h->impl->sync_all_streams();
+    if (h->impl->order_ev) (void)hipEventDestroy(h->impl->order_ev);
     delete h->impl;
   }
   delete h;
@@ -1110,9 +1141,19 @@ acr_status_t acr_get_stats(acr_handle_t h, acr_stats_t* st) {
   });
 }
 
+acr_status_t acr_get_structure(acr_handle_t h, acr_structure_t* info, int32_t* perm, int32_t* node_offset,
+                               int32_t* node_size, int32_t* level_size, int32_t* sched_plane,
+                               int32_t* sched_elim) {
+  if (!h || !h->impl || !info) return ACR_ERROR_INVALID_VALUE;
+  return guarded([&]() -> acr_status_t {
+    h->impl->structure(info, perm, node_offset, node_size, level_size, sched_plane, sched_elim);
+    return ACR_SUCCESS;
+  });
+}
+
 acr_status_t acr_autotune(const acr_options_t* opt, const double* coef, int32_t sample_planes,
                           const char* cache_path, hipStream_t stream, acr_tune_result_t* out) {
-  if (!out || !coef || !valid_opts(opt) || sample_planes < 0) return ACR_ERROR_INVALID_VALUE;
+  if (!out || !coef || !options_valid(opt) || sample_planes < 0) return ACR_ERROR_INVALID_VALUE;
   return guarded([&]() -> acr_status_t { return autotune_impl(opt, coef, sample_planes, cache_path, stream, out); });
 }
 
@@ -1120,6 +1161,7 @@ acr_status_t acr_residual(acr_handle_t h, const double* x, const double* b, doub
                           hipStream_t stream) {
   if (!h || !h->impl || !x || !b || !r) return ACR_ERROR_INVALID_VALUE;
   return guarded([&]() -> acr_status_t {
+    h->impl->use_stream(stream);
     launch_residual(h->impl->grid, h->impl->coef, x, b, r, transpose, stream);
     hip_check(hipGetLastError(), "residual");
     return ACR_SUCCESS;

@@ -11,6 +11,7 @@
 
 #include "acr.h"
 #include "kern.h"
+#include "plan.h"
 
 namespace acr {
 
@@ -26,20 +27,6 @@ enum : int {
 };
 
 void hip_check(hipError_t e, const char* what);
-
-// Planar bisection cluster tree of an nx x ny plane (Sections 2.1.1, 3.1).
-// Split across the longer side (x on ties), first half ceil(side/2); the tree is
-// complete (every box of a depth is split while any box of that depth holds
-// more than `leaf` points); points are numbered leaf by leaf, row-major inside.
-struct Tree {
-  int nx = 0, ny = 0, M = 0, L = 0, leaf = 0, leaf_max = 0;
-  std::vector<std::vector<int>> off, sz;  // [depth][segment]
-  std::vector<int> perm;                   // cluster position -> j * nx + i
-  // Returns false when the rule would have to split a single point.
-  bool build(int nx_, int ny_, int leaf_);
-  int nblk() const { return (1 << (L + 1)) - 2; }
-  static int bid(int d, int s) { return (1 << (d + 1)) - 2 + s; }
-};
 
 struct Allocator {
   void* (*alloc)(size_t bytes, void* ctx, hipStream_t s) = nullptr;
@@ -146,6 +133,7 @@ class Exec {
   bool gram_ok = true;         // ACR_GRAM=0 forces Householder compression everywhere
   size_t fused_lds = 0;        // one-workgroup SVD up to this LDS size (ACR_FUSED_LDS, bytes)
   bool svd_global = false;     // ACR_SVD_GLOBAL=1: every core takes the global-memory two-kernel path
+  bool pchol_global = false;   // ACR_PCHOL_GLOBAL=1: every Gram takes the left-looking global-memory kernel
   int leaf_lowp = 0;           // leaf x leaf products with 16-bit inputs: 1 = BF16, 2 = FP16 (FP32 data)
   const char* trace_tag = "";
   void check_range(const void* p, size_t bytes, const char* what) const;

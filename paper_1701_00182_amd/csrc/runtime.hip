@@ -16,58 +16,6 @@ void hip_check(hipError_t e, const char* what) {
   throw Failure(ST_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// ---------------------------------------------------------------- tree
-namespace {
-struct Box { int x0, x1, y0, y1; };
-inline int box_size(const Box& b) { return (b.x1 - b.x0) * (b.y1 - b.y0); }
-}  // namespace
-
-bool Tree::build(int nx_, int ny_, int leaf_) {
-  nx = nx_; ny = ny_; leaf = leaf_; M = nx * ny;
-  std::vector<std::vector<Box>> levels{{Box{0, nx, 0, ny}}};
-  for (;;) {
-    const auto& cur = levels.back();
-    int mx = 0;
-    for (auto& b : cur) mx = std::max(mx, box_size(b));
-    if (mx <= leaf) break;
-    std::vector<Box> nxt;
-    nxt.reserve(cur.size() * 2);
-    for (auto& b : cur) {
-      if (box_size(b) < 2) return false;
-      const int w = b.x1 - b.x0, h = b.y1 - b.y0;
-      if (w >= h) {
-        const int xm = b.x0 + (w + 1) / 2;
-        nxt.push_back({b.x0, xm, b.y0, b.y1});
-        nxt.push_back({xm, b.x1, b.y0, b.y1});
-      } else {
-        const int ym = b.y0 + (h + 1) / 2;
-        nxt.push_back({b.x0, b.x1, b.y0, ym});
-        nxt.push_back({b.x0, b.x1, ym, b.y1});
-      }
-    }
-    levels.push_back(std::move(nxt));
-  }
-  L = (int)levels.size() - 1;
-  off.assign(L + 1, {});
-  sz.assign(L + 1, {});
-  for (int d = 0; d <= L; ++d) {
-    int o = 0;
-    for (auto& b : levels[d]) {
-      off[d].push_back(o);
-      sz[d].push_back(box_size(b));
-      o += box_size(b);
-    }
-  }
-  perm.clear();
-  leaf_max = 0;
-  for (auto& b : levels[L]) {
-    leaf_max = std::max(leaf_max, box_size(b));
-    for (int j = b.y0; j < b.y1; ++j)
-      for (int i = b.x0; i < b.x1; ++i) perm.push_back(j * nx + i);
-  }
-  return true;
-}
-
 template <class T> size_t HMat<T>::words(const Tree& tr) const {
   if (kind == DIAG) return tr.M;
   if (kind != HODLR) return 0;
@@ -256,6 +204,8 @@ void Exec::init(hipStream_t s, const Allocator& a) {
   fused_lds = kFusedLds;
   const char* sg = std::getenv("ACR_SVD_GLOBAL");
   svd_global = sg && sg[0] == '1';
+  const char* pg = std::getenv("ACR_PCHOL_GLOBAL");
+  pchol_global = pg && pg[0] == '1';
   stream = s;
   al = a;
   ring_bytes_ = size_t(64) << 20;
@@ -286,6 +236,8 @@ void Exec::destroy() {
   event_pool_.clear();
   if (d_counters_) dev_free(d_counters_);
   d_counters_ = nullptr;
+  for (void* p : oversized_) dev_free(p);
+  oversized_.clear();
   if (h_ring_) (void)hipHostFree(h_ring_);
   if (h_flags) (void)hipHostFree(h_flags);
   if (d_ring_) dev_free(d_ring_);
@@ -864,7 +816,7 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
   std::vector<PcholTask> packed, wide;
   int max_r = 1;
   for (auto& x : t) {
-    if (lds_bytes_pchol_packed(x.r) <= kLdsBudget) {
+    if (!pchol_global && lds_bytes_pchol_packed(x.r) <= kLdsBudget) {
       packed.push_back(x);
     } else {
       wide.push_back(x);
