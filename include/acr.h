@@ -104,6 +104,30 @@ acr_status_t acr_solve(acr_handle_t h, int32_t nrhs, const double* b, int64_t ld
                        hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * x = M^{-1} b as acr_solve, with the same arguments, layouts and results, but
+ * every buffer beyond b and x (the permuted and reduced right-hand sides, the
+ * per-block inner products, the task arrays of the launches) lives in one
+ * fixed device array of ACR_NOALLOC_SCRATCH_BYTES per GPU, which the library
+ * holds from its first use on that GPU until the process ends.  The call
+ * allocates no device memory and launches its kernels one by one on `stream`
+ * (no graph).  The first call per (handle, nrhs) records the launch sequence
+ * on the host; the task arrays are copied into the array, ordered on
+ * `stream`, whenever the array was last used by another handle or nrhs.
+ * Every handle on a GPU shares that GPU's array, which keeps the last call's
+ * contents (nothing in it needs to start at zero): calls that overlap on one
+ * GPU -- on different streams or host threads without ordering between them --
+ * race and give wrong results.  b and x are owned by the caller; x may alias b.
+ * Errors: ACR_ERROR_INVALID_VALUE as for acr_solve, and when the workspace of
+ * this grid, precision and nrhs does not fit the array (the message of
+ * acr_last_error_message names the limit); nothing is launched then.
+ */
+#define ACR_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+acr_status_t acr_solve_noalloc(acr_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x,
+                               int64_t ldx, hipStream_t stream);
+
+/*
  * x = M^{-T} b with the same factors: the cyclic reduction of A^T, whose level
  * blocks are (D_j^T, F_{j-1}^T, E_{j+1}^T), applied with transposed blocks.
  * Exactly the transpose of the operator acr_solve applies (up to rounding).

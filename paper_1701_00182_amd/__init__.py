@@ -68,7 +68,7 @@ class RefineResult(ctypes.Structure):
                 ("relres", ctypes.c_double), ("relres0", ctypes.c_double)]
 
 
-EXPORTS = ("acr_options_default", "acr_factor", "acr_solve", "acr_solve_transpose", "acr_free",
+EXPORTS = ("acr_options_default", "acr_factor", "acr_solve", "acr_solve_transpose", "acr_solve_noalloc", "acr_free",
            "acr_get_stats", "acr_solve_refined", "acr_residual", "acr_assemble_diffusion",
            "acr_kappa_gradient", "acr_status_string", "acr_plan_structure", "acr_get_structure")
 
@@ -85,7 +85,7 @@ def lib():
         L.acr_options_default.restype = None
         L.acr_factor.argtypes = [ctypes.POINTER(Options), vp, vp, ctypes.POINTER(vp)]
         L.acr_factor.restype = ctypes.c_int
-        for fn in (L.acr_solve, L.acr_solve_transpose):
+        for fn in (L.acr_solve, L.acr_solve_transpose, L.acr_solve_noalloc):
             fn.argtypes = [vp, i32, vp, i64, vp, i64, vp]
             fn.restype = ctypes.c_int
         L.acr_free.argtypes = [vp]
@@ -209,6 +209,11 @@ class Factor:
 
     def solve_transpose(self, b, out=None):
         return self._solve(lib().acr_solve_transpose, b, out)
+
+    def solve_noalloc(self, b, out):
+        """acr_solve_noalloc: the solve with the library's fixed device scratch
+        (allocates no device memory; `out` must be given)."""
+        return self._solve(lib().acr_solve_noalloc, b, out)
 
     def solve_refined(self, b, tol=1e-8, method="gmres", restart=30, maxit=200, transpose=False,
                       history=64, raise_on_fail=True):

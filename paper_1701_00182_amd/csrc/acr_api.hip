@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <memory>
 
 #include "acr.h"
@@ -38,12 +39,26 @@ struct Plan {
   hipGraphExec_t exec = nullptr;
   int nrhs = 0;
   bool trans = false;
+  // no-allocation plans: the workspace is the fixed device scratch at `base`;
+  // `image` holds the task arrays (from byte img_off of the scratch on), which
+  // are uploaded again whenever another plan used the scratch in between
+  bool noalloc = false;
+  char* base = nullptr;
+  size_t img_off = 0;
+  std::vector<char> image;
+  uint64_t id = 0;
 };
+
+uint64_t next_plan_id() {
+  static std::atomic<uint64_t> n{0};
+  return ++n;
+}
 
 struct FactorBase {
   virtual ~FactorBase() = default;
   virtual void solve(int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, bool trans,
                      hipStream_t s) = 0;
+  virtual void solve_noalloc(int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, hipStream_t s) = 0;
   virtual void stats(acr_stats_t* st) = 0;
   virtual void structure(acr_structure_t* info, int32_t* perm, int32_t* node_offset, int32_t* node_size,
                          int32_t* level_size, int32_t* sched_plane, int32_t* sched_elim) = 0;
@@ -513,11 +528,44 @@ template <class T> struct FactorT : FactorBase {
   // ---------------------------------------------------------- solve plans
   Plan* plan_for(int nrhs, bool trans) {
     for (auto& p : plans)
-      if (p->nrhs == nrhs && p->trans == trans) return p.get();
+      if (!p->noalloc && p->nrhs == nrhs && p->trans == trans) return p.get();
     auto pl = std::make_unique<Plan>();
     pl->nrhs = nrhs;
     pl->trans = trans;
     pl->mem.init(&ex, size_t(64) << 20);
+    record_plan(pl.get());
+    plans.push_back(std::move(pl));
+    return plans.back().get();
+  }
+
+  // Plan of acr_solve_noalloc: recorded into the fixed scratch at `base`
+  // (nothing is allocated; a workspace past its end throws before anything is
+  // launched), task arrays kept as a host image.
+  Plan* noalloc_plan_for(int nrhs, char* base, size_t cap) {
+    for (auto& p : plans)
+      if (p->noalloc && p->nrhs == nrhs && p->base == base) return p.get();
+    auto pl = std::make_unique<Plan>();
+    pl->nrhs = nrhs;
+    pl->noalloc = true;
+    pl->base = base;
+    pl->id = next_plan_id();
+    pl->mem.init_fixed(base, cap);
+    try {
+      record_plan(pl.get());
+    } catch (...) {
+      ex.rec_image = nullptr;
+      ex.rec_image_base = nullptr;
+      throw;
+    }
+    ex.rec_image = nullptr;
+    ex.rec_image_base = nullptr;
+    plans.push_back(std::move(pl));
+    return plans.back().get();
+  }
+
+  void record_plan(Plan* pl) {
+    const bool trans = pl->trans;
+    const int nrhs = pl->nrhs;
     const int M = tr.M, nz = grid.nz, c = nrhs;
     const size_t pane = (size_t)M * c;
     T* W = pl->mem.get_n<T>(pane * nz);
@@ -525,12 +573,18 @@ template <class T> struct FactorT : FactorBase {
     T* Gb = pl->mem.get_n<T>(pane * ((nz + 1) / 2));
     pl->W = W;
     pl->Ub = Ub;
+    if (pl->noalloc) {
+      // everything recorded after the vectors is task data or inner products
+      pl->img_off = pl->mem.used();
+      ex.rec_image = &pl->image;
+      ex.rec_image_base = pl->base + pl->img_off;
+    }
     ex.rec = &pl->launches;
     ex.rec_arena = &pl->mem;
     const bool fused = nrhs <= kFusedMaxRhs && tr.L <= kMaxDepth && fused_ok;
     try {
       if (fused) {
-        record_fused(pl.get(), trans, W, Ub, Gb, nrhs);
+        record_fused(pl, trans, W, Ub, Gb, nrhs);
       } else {
       auto Wp = [&](int plane) { return W + pane * plane; };
       auto Up = [&](int plane) { return Ub + pane * plane; };
@@ -587,8 +641,6 @@ template <class T> struct FactorT : FactorBase {
     }
     ex.rec = nullptr;
     ex.rec_arena = nullptr;
-    plans.push_back(std::move(pl));
-    return plans.back().get();
   }
 
   void run_plan(Plan* pl, hipStream_t s) {
@@ -629,6 +681,27 @@ template <class T> struct FactorT : FactorBase {
     launch_perm_in<T>(grid, nrhs, b, ldb, d_perm, static_cast<T*>(pl->W), s);
     hip_check(hipGetLastError(), "perm_in");
     run_plan(pl, s);
+    launch_perm_out<T>(grid, nrhs, static_cast<const T*>(pl->Ub), d_perm, x, ldx, s);
+    hip_check(hipGetLastError(), "perm_out");
+  }
+
+  void solve_noalloc(int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, hipStream_t s) override {
+    size_t cap = 0;
+    char* base = noalloc_scratch(&cap);
+    use_stream(s);
+    ex.stream = s;
+    Plan* pl = noalloc_plan_for(nrhs, base, cap);
+    if (noalloc_owner() != pl->id) {
+      // the scratch holds another plan's task arrays: restore this plan's
+      if (!pl->image.empty())
+        hip_check(hipMemcpyAsync(base + pl->img_off, pl->image.data(), pl->image.size(), hipMemcpyHostToDevice, s),
+                  "hipMemcpyAsync(no-allocation tasks)");
+      set_noalloc_owner(pl->id);
+    }
+    launch_perm_in<T>(grid, nrhs, b, ldb, d_perm, static_cast<T*>(pl->W), s);
+    hip_check(hipGetLastError(), "perm_in");
+    for (auto& r : pl->launches) r.f(s);
+    hip_check(hipGetLastError(), "solve launch");
     launch_perm_out<T>(grid, nrhs, static_cast<const T*>(pl->Ub), d_perm, x, ldx, s);
     hip_check(hipGetLastError(), "perm_out");
   }
@@ -1107,6 +1180,18 @@ acr_status_t acr_solve(acr_handle_t h, int32_t nrhs, const double* b, int64_t ld
   if (nrhs == 0) return ACR_SUCCESS;
   return guarded([&]() -> acr_status_t {
     h->impl->solve(nrhs, b, ldb, x, ldx, false, stream);
+    return ACR_SUCCESS;
+  });
+}
+
+acr_status_t acr_solve_noalloc(acr_handle_t h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+                               hipStream_t stream) {
+  if (!h || !h->impl || nrhs < 0 || (nrhs > 0 && (!b || !x))) return ACR_ERROR_INVALID_VALUE;
+  const int64_t N = h->impl->grid.N();
+  if (nrhs > 0 && (ldb < N || ldx < N)) return ACR_ERROR_INVALID_VALUE;
+  if (nrhs == 0) return ACR_SUCCESS;
+  return guarded([&]() -> acr_status_t {
+    h->impl->solve_noalloc(nrhs, b, ldb, x, ldx, stream);
     return ACR_SUCCESS;
   });
 }

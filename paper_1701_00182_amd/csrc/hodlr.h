@@ -28,6 +28,14 @@ enum : int {
 
 void hip_check(hipError_t e, const char* what);
 
+// The fixed device scratch of the no-allocation solve on the current device
+// (acquired once per device; *bytes = its size).  Throws on failure.
+char* noalloc_scratch(size_t* bytes);
+// Identifier of the no-allocation plan whose task arrays the current device's
+// scratch holds (0 = none); set after a plan uploads them.
+uint64_t noalloc_owner();
+void set_noalloc_owner(uint64_t id);
+
 struct Allocator {
   void* (*alloc)(size_t bytes, void* ctx, hipStream_t s) = nullptr;
   void (*release)(void* p, void* ctx, hipStream_t s) = nullptr;
@@ -41,6 +49,9 @@ class Arena {
  public:
   Arena() = default;
   void init(Exec* ex, size_t chunk) { ex_ = ex; chunk_ = chunk; }
+  // Bump allocation inside one caller-owned device region of `bytes`: never
+  // allocates; a request past its end throws (status invalid value).
+  void init_fixed(void* base, size_t bytes);
   void* get(size_t bytes);
   template <class T> T* get_n(size_t n) { return static_cast<T*>(get(n * sizeof(T))); }
   struct Mark { size_t ci, off; };
@@ -55,6 +66,7 @@ class Arena {
   size_t chunk_ = 0;
   std::vector<std::pair<char*, size_t>> chunks_;
   size_t ci_ = 0, off_ = 0;
+  bool fixed_ = false;
 };
 
 // Algorithmic work of one launch, for the per-kernel timing table: flops and
@@ -88,6 +100,11 @@ class Exec {
   };
   std::vector<Recorded>* rec = nullptr;
   Arena* rec_arena = nullptr;
+  // With rec_arena set: when rec_image is set too, task arrays are not copied
+  // to the device while recording; their bytes go to *rec_image at their
+  // offset from rec_image_base, for the caller to upload stream-ordered.
+  std::vector<char>* rec_image = nullptr;
+  const char* rec_image_base = nullptr;
 
   void init(hipStream_t s, const Allocator& a);
   void destroy();

@@ -8,6 +8,12 @@
 
 #include "hodlr.h"
 
+// Workspace of acr_solve_noalloc: one copy per GPU, held until the process
+// ends.  Host code never passes this name to a kernel (on the host it is only
+// a stand-in); it uses the device address that noalloc_scratch() obtains with
+// hipGetSymbolAddress.
+static __device__ __align__(256) char scratch[ACR_NOALLOC_SCRATCH_BYTES];
+
 namespace acr {
 
 void hip_check(hipError_t e, const char* what) {
@@ -41,8 +47,15 @@ void* Arena::get(size_t bytes) {
       off_ += bytes;
       return p;
     }
+    if (fixed_) break;
     ++ci_;
     off_ = 0;
+  }
+  if (fixed_) {
+    char msg[160];
+    std::snprintf(msg, sizeof(msg), "workspace exceeds the fixed no-allocation scratch of %zu bytes",
+                  chunks_.empty() ? size_t(0) : chunks_[0].second);
+    throw Failure(ST_INVALID, msg);
   }
   const size_t csz = std::max(chunk_, bytes);
   char* p = static_cast<char*>(ex_->dev_alloc(csz));
@@ -52,7 +65,19 @@ void* Arena::get(size_t bytes) {
   return p;
 }
 
+void Arena::init_fixed(void* base, size_t bytes) {
+  chunks_.assign(1, {static_cast<char*>(base), bytes});
+  chunk_ = 0;
+  ci_ = off_ = 0;
+  fixed_ = true;
+}
+
 void Arena::free_all() {
+  if (fixed_) {
+    chunks_.clear();
+    ci_ = off_ = 0;
+    return;
+  }
   for (auto& c : chunks_) ex_->dev_free(c.first);
   chunks_.clear();
   ci_ = off_ = 0;
@@ -175,6 +200,51 @@ void reg_del(void* p) {
 }
 }  // namespace
 
+namespace {
+struct DeviceScratch {
+  char* ptr = nullptr;
+  uint64_t owner = 0;
+};
+std::mutex g_scratch_mu;
+std::map<int, DeviceScratch>& scratch_table() {
+  static std::map<int, DeviceScratch> t;
+  return t;
+}
+int current_device() {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  return dev;
+}
+}  // namespace
+
+char* noalloc_scratch(size_t* bytes) {
+  const int dev = current_device();
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  DeviceScratch& d = scratch_table()[dev];
+  if (!d.ptr) {
+    // once per device, with that device current: its own copy of the array
+    void* p = nullptr;
+    hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) throw Failure(ST_HIP, "hipGetSymbolAddress(scratch) returned a null address");
+    d.ptr = static_cast<char*>(p);
+    reg_add(p, ACR_NOALLOC_SCRATCH_BYTES);   // known to the host-side bounds check
+  }
+  if (bytes) *bytes = ACR_NOALLOC_SCRATCH_BYTES;
+  return d.ptr;
+}
+
+uint64_t noalloc_owner() {
+  const int dev = current_device();
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return scratch_table()[dev].owner;
+}
+
+void set_noalloc_owner(uint64_t id) {
+  const int dev = current_device();
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  scratch_table()[dev].owner = id;
+}
+
 void Exec::check_range(const void* p, size_t bytes, const char* what) const {
   if (!checking || bytes == 0) return;
   std::lock_guard<std::mutex> lk(g_reg_mu);
@@ -285,6 +355,12 @@ const void* Exec::upload_bytes(const void* src, size_t bytes) {
   if (bytes == 0) return nullptr;
   if (rec_arena) {
     void* d = rec_arena->get(bytes);
+    if (rec_image) {
+      const size_t off = static_cast<const char*>(d) - rec_image_base;
+      if (rec_image->size() < off + bytes) rec_image->resize(off + bytes);
+      std::memcpy(rec_image->data() + off, src, bytes);
+      return d;
+    }
     hip_check(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(plan tasks)");
     return d;
   }
