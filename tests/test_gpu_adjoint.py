@@ -67,10 +67,30 @@ def _setup(n):
     return kappa, f, obs, data
 
 
-def _loss_and_grad_gpu(kappa, f, obs, data, eps=1e-4, precision="fp32"):
+def _setup_cg(n):
+    """As _setup, with u_true from a CPU conjugate-gradient solve to 1e-13
+    (Jacobi preconditioned; the operator is symmetric positive definite) where
+    a sparse LU of the 3D operator would be slow."""
+    import scipy.sparse.linalg as spla
+    from oracle.assemble import operator_from_fields
+    kappa = lognormal_kappa(n)
+    kappa_true = lognormal_kappa(n, seed=SEEDS["kappa_true"])
+    f = rhs_normal(n ** 3)
+    obs = observation_cells(n ** 3, count=512)
+    A = operator_from_fields(kappa_true.shape, kappa=kappa_true).tocsr()
+    dinv = 1.0 / A.diagonal()
+    M = spla.LinearOperator(A.shape, matvec=lambda x: dinv * x)
+    u_true, info = spla.cg(A, f, rtol=1e-13, maxiter=20000, M=M)
+    assert info == 0
+    pu = u_true[obs]
+    data = pu + 0.01 * np.sqrt(np.mean(pu ** 2)) * observation_noise(len(obs))
+    return kappa, f, obs, data
+
+
+def _loss_and_grad_gpu(kappa, f, obs, data, eps=1e-4, precision="fp32", leaf=32):
     k = _t(kappa).requires_grad_(True)
     ft = _t(f)
-    u = acr.ACRSolve.apply(k, ft, eps, 32, precision, 1e-12)
+    u = acr.ACRSolve.apply(k, ft, eps, leaf, precision, 1e-12)
     idx = torch.from_numpy(obs).to(DEV)
     r = u[idx] - _t(data)
     L = 0.5 * (r * r).sum()
@@ -98,6 +118,26 @@ def test_gradient_central_differences():
         Lm, _ = _loss_and_grad_gpu(kappa - h * v, f, obs, data)
         fd = (Lp - Lm) / (2 * h)
         an = float(np.sum(g * v))
+        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-12
+
+
+def test_gradient_central_differences_n64():
+    """The differentiation workload at full size: Poisson n = 64 (N = 262,144
+    nodal kappa values), 512 observation cells, FP32 factors at eps = 1e-4 with
+    forward and adjoint solves refined to 1e-12: the adjoint gradient against
+    central differences (h = 1e-6) along the 8 seeded directions
+    v = kappa * z."""
+    n = 64
+    kappa, f, obs, data = _setup_cg(n)
+    L0, g = _loss_and_grad_gpu(kappa, f, obs, data, leaf=64)
+    assert np.all(np.isfinite(g)) and L0 > 0
+    h = 1e-6
+    for i, v in enumerate(fd_directions(kappa, count=8)):
+        Lp, _ = _loss_and_grad_gpu(kappa + h * v, f, obs, data, leaf=64)
+        Lm, _ = _loss_and_grad_gpu(kappa - h * v, f, obs, data, leaf=64)
+        fd = (Lp - Lm) / (2 * h)
+        an = float(np.sum(g * v))
+        print(f"n=64 direction {i}: fd {fd:.10e} adjoint {an:.10e} rel {abs(fd - an) / abs(an):.2e}", flush=True)
         assert abs(fd - an) <= 1e-5 * abs(an) + 1e-12
 
 

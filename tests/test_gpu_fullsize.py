@@ -24,10 +24,14 @@ def _factor(coef, **kw):
     return acr.Factor(torch.from_numpy(np.ascontiguousarray(coef)).to(DEV), **kw)
 
 
-def test_headline_convdiff_n128_fp32_gmres():
+@pytest.mark.parametrize("tol", [1e-8, 1e-10])
+def test_headline_convdiff_n128_fp32_gmres(tol):
     """n = 128 convection-diffusion (N = 2,097,152), eps = 1e-2, leaf 128,
     FP32 factors, two-kernel core SVD: the unrefined solve is accurate to the
-    truncation level and FP64 GMRES(30) reaches 1e-8 (measured on the CPU)."""
+    truncation level and FP64 GMRES(30) reaches the headline's 1e-8 and the
+    workload's stated 1e-10, both measured again with the CPU operator.  The
+    two residuals differ only by the rounding of one FP64 operator
+    application (|A| |x| u / |b| ~ 1e-15), hence the 1 % margin at 1e-10."""
     n, eps = 128, 1e-2
     coef = problem("convdiff", n)
     f = rhs_normal(n ** 3)
@@ -36,9 +40,12 @@ def test_headline_convdiff_n128_fp32_gmres():
     b = torch.from_numpy(f).to(DEV)
     x0 = fac.solve(b).cpu().numpy()
     assert float(relres(A, x0, f)) <= 5 * eps
-    x, info = fac.solve_refined(b, tol=1e-8, method="gmres")
-    assert info["converged"]
-    assert float(relres(A, x.cpu().numpy(), f)) <= 2e-8
+    x, info = fac.solve_refined(b, tol=tol, method="gmres", maxit=300)
+    rel = float(relres(A, x.cpu().numpy(), f))
+    print(f"n=128 GMRES to {tol:g}: {info['iterations']} applications, relres gpu {info['relres']:.3e} "
+          f"cpu {rel:.3e}", flush=True)
+    assert info["converged"] and info["relres"] <= tol
+    assert rel <= 1.01 * tol
     fac.free()
 
 
