@@ -8,7 +8,10 @@ every block an operation produces, and the solution is recovered by
 Algorithm 2 / Eq. all_backSubs.
 
 Blocks are kept dense (M x M, in cluster order) and a block that is still a
-diagonal (the level-0 E_k and F_k) is kept as its diagonal.  Missing couplings
+diagonal (the level-0 E_k and F_k of a 7-point stencil) is kept as its
+diagonal.  With a 27-point stencil E_k and F_k are 9-point plane operators;
+Eq. elim is written for general blocks, and they are approximated like D_k at
+level 0.  Missing couplings
 (E of the first plane, F of the last plane of a level) are ``None``: the
 terms that would use them are dropped, as Section 2.2.2 prescribes for the
 last plane.
@@ -66,27 +69,31 @@ def _apply_t(a, v):
 class OracleACR:
     """Factorisation by ACR elimination; ``solve`` / ``solve_transpose`` reuse it.
 
-    Parameters: coef (7-point stencil array coef[7, nz, ny, nx]), leaf size of
-    the cluster tree, truncation tolerance eps (relative, per block).
+    Parameters: coef (stencil array coef[7, nz, ny, nx] or coef[27, nz, ny, nx]),
+    leaf size of the cluster tree, truncation tolerance eps (relative, per block).
     """
 
     def __init__(self, coef, leaf, eps):
         coef = np.asarray(coef, dtype=np.float64)
-        _, nz, ny, nx = coef.shape
+        ns, nz, ny, nx = coef.shape
         self.shape = (nz, ny, nx)
         self.M = nx * ny
         self.N = self.M * nz
         self.eps = float(eps)
         self.tree = ClusterTree(nx, ny, leaf)
         self.A = operator_from_coef(coef)
-        D, E, F = plane_blocks(self.A, nx, ny, nz)
+        D, E, F = plane_blocks(self.A, nx, ny, nz, diagonal=ns == 7)
         p = self.tree.perm
         self.ranks = []          # (level, name, plane, ranks-per-depth)
         T = self._T
         # Algorithm 1, first step: block-wise approximation A^(0) of A
         Dc = [T(("dense", d[np.ix_(p, p)]), 0, "D", k) for k, d in enumerate(D)]
-        Ec = [None if e is None else ("diag", e[p]) for e in E]
-        Fc = [None if f is None else ("diag", f[p]) for f in F]
+        if ns == 7:
+            Ec = [None if e is None else ("diag", e[p]) for e in E]
+            Fc = [None if f is None else ("diag", f[p]) for f in F]
+        else:
+            Ec = [None if e is None else T(("dense", e[np.ix_(p, p)]), 0, "E", k) for k, e in enumerate(E)]
+            Fc = [None if f is None else T(("dense", f[np.ix_(p, p)]), 0, "F", k) for k, f in enumerate(F)]
         self.levels = []
         sched, self.last_plane = level_schedule(nz)
         cur = {"D": Dc, "E": Ec, "F": Fc}

@@ -16,7 +16,7 @@ import scipy.fft as sfft
 # Seed assignment for the named workloads (one stream per role).
 SEEDS = {
     "kappa": 0, "rhs": 1, "velocity": 2, "speed": 2,
-    "obs_cells": 3, "obs_noise": 4, "fd_dirs": 5, "kappa_true": 6,
+    "obs_cells": 3, "obs_noise": 4, "fd_dirs": 5, "kappa_true": 6, "perturb27": 7,
 }
 
 

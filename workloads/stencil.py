@@ -1,4 +1,4 @@
-"""7-point stencils of the synthetic workloads, in the solver's input layout.
+"""7- and 27-point stencils of the synthetic workloads, in the solver's input layout.
 
 Layout: ``coef[7, nz, ny, nx]`` float64 with slot order
 ``C, W(i-1), E(i+1), S(j-1), N(j+1), B(k-1), T(k+1)`` so that, for the natural
@@ -88,7 +88,81 @@ def helmholtz_coef(c, omega):
     return coef
 
 
-PROBLEMS = ("poisson", "convdiff", "helmholtz", "laplace")
+# ---------------------------------------------------------------- 27 points
+# Layout coef[27, nz, ny, nx]: slot s = 9 (dz + 1) + 3 (dy + 1) + (dx + 1) holds
+# the coupling to the neighbour at offset (dx, dy, dz), so that
+#     (A u)_r = sum_s coef[s][r] u_{r + dx + dy nx + dz nx ny};
+# slot 13 is the centre.  D_k (dz = 0) and E_k, F_k (dz = -1, +1) are then
+# 9-point plane operators.  Entries reaching outside the grid are zero.
+
+
+def slot27(dx, dy, dz):
+    return 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1)
+
+
+def _outside27(shape):
+    """Boolean [27, nz, ny, nx]: the neighbour of a slot lies outside the grid."""
+    nz, ny, nx = shape
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    out = np.zeros((27,) + tuple(shape), bool)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                out[slot27(dx, dy, dz)] = ((i + dx < 0) | (i + dx >= nx) | (j + dy < 0) | (j + dy >= ny)
+                                           | (k + dz < 0) | (k + dz >= nz))
+    return out
+
+
+def fem_q1_coef(shape, wavenumber=0.0):
+    """27-point stencil of the trilinear (Q1) finite-element discretisation of
+    -lap u - wavenumber^2 u on the unit cube with Dirichlet boundaries
+    (Section 5.3): K - wavenumber^2 M on the interior nodes of a uniform grid.
+
+    Per axis the assembled linear-element stencils are stiffness
+    [-1, 2, -1] / h and mass [1, 4, 1] h / 6; the 3D stencils are their tensor
+    products, K = Kx My Mz + Mx Ky Mz + Mx My Kz and M = Mx My Mz.
+    """
+    nz, ny, nx = shape
+    axes = []
+    for n in (nx, ny, nz):
+        h = fields.grid_h(n)
+        axes.append((np.array([-1.0, 2.0, -1.0]) / h, np.array([1.0, 4.0, 1.0]) * h / 6.0))
+    (kx, mx), (ky, my), (kz, mz) = axes
+    coef = np.zeros((27,) + tuple(shape))
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                a, b, c = dx + 1, dy + 1, dz + 1
+                v = kx[a] * my[b] * mz[c] + mx[a] * ky[b] * mz[c] + mx[a] * my[b] * kz[c]
+                v -= wavenumber ** 2 * mx[a] * my[b] * mz[c]
+                coef[slot27(dx, dy, dz)] = v
+    coef[_outside27(shape)] = 0.0
+    return coef
+
+
+def perturbed_q1_coef(shape, seed=fields.SEEDS["perturb27"], spread=0.3, centre=1.35):
+    """A nonsymmetric 27-point operator with the Q1 pattern: every off-centre
+    entry of the Q1 Laplacian scaled by (1 + spread * xi), xi uniform on
+    [-1, 1] per entry, the centre by ``centre``; strictly diagonally dominant
+    (the Q1 Laplacian's off-centre magnitudes sum to its centre), hence
+    nonsingular."""
+    coef = fem_q1_coef(shape)
+    rng = fields._rng(seed)
+    xi = rng.uniform(-1.0, 1.0, coef.shape)
+    off = np.ones(27, bool)
+    off[13] = False
+    coef[off] *= 1.0 + spread * xi[off]
+    coef[13] *= centre
+    return coef
+
+
+def helmholtz27_wavenumber(n):
+    """Wavenumber of the 27-point Helmholtz workload: n / 2 (16, 32, 64 at
+    n = 32, 64, 128, the paper's choice of about 12 points per wavelength)."""
+    return n / 2.0
+
+
+PROBLEMS = ("poisson", "convdiff", "helmholtz", "laplace", "fem_poisson27", "fem_helmholtz27", "nonsym27")
 
 
 def problem(kind, n, seed=None):
@@ -99,7 +173,16 @@ def problem(kind, n, seed=None):
     cell Peclet <= 1 (velocity seed 2).  ``helmholtz``: -Lap u - (omega/c)^2 u
     with c = 1 + 0.3 * smoothed noise (seed 2), 10 points per wavelength.
     ``laplace``: kappa = 1 (the constant-coefficient special case).
+    27-point (coef[27, ...]): ``fem_poisson27`` the trilinear finite-element
+    Laplacian, ``fem_helmholtz27`` -(lap u + k^2 u) with k = n / 2 (Section
+    5.3), ``nonsym27`` the perturbed nonsymmetric Q1 pattern (seed 7).
     """
+    if kind == "fem_poisson27":
+        return fem_q1_coef((n, n, n))
+    if kind == "fem_helmholtz27":
+        return fem_q1_coef((n, n, n), helmholtz27_wavenumber(n))
+    if kind == "nonsym27":
+        return perturbed_q1_coef((n, n, n), seed=fields.SEEDS["perturb27"] if seed is None else seed)
     if kind == "laplace":
         return diffusion_coef(np.ones((n, n, n)))
     if kind == "helmholtz":
