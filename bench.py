@@ -10,7 +10,10 @@ relative residual 1e-8 with the factorisation as preconditioner.  Inputs are
 synthetic (seeded lognormal kappa, random divergence-free velocity at cell
 Peclet 1, f ~ N(0, 1)) and resident in device memory before the timed region.
 The plain FP64 form and the BF16-leaf variant (same eps and GMRES) are measured
-once beside it, and the oracle is timed on the host on a bounded sample.
+once beside it (the FP64 form with its own kernel table and roofline), the
+factorisation is measured as a CG preconditioner of the paper's Table precond
+problem over its eps sweep, and the oracle is timed on the host on a bounded
+sample.
 
 Other workloads (--workload, one JSON line each, not the headline):
   helmholtz_mrhs  indefinite Helmholtz n = 64, FP32 factors, eps = 1e-3, 256
@@ -46,6 +49,7 @@ HBM_CLASSES = ("solve_leaf", "solve_inner", "copy")
 FP64_CLASSES = ("jacobi", "jacobi_lds", "svd_wave", "svd_block", "core_left", "qrcp", "qrcp_lds", "pchol", "gram",
                 "wtilde")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats.json")
 
 
 def log(msg):
@@ -75,7 +79,7 @@ def class_bound(name, precision):
     """(bound, peak, unit) of a kernel class."""
     if name in HBM_CLASSES:
         return "hbm", PEAK["hbm"], "GB/s"
-    if name == "gemm":
+    if name in ("gemm", "seg_gemm"):
         return "mfma", PEAK["fp64"] if precision == "fp64" else PEAK["fp32"], "TFLOP/s"
     if name == "gemm_bf16":
         return "mfma", PEAK["bf16"], "TFLOP/s"
@@ -85,21 +89,37 @@ def class_bound(name, precision):
     return "alu", PEAK["fp64"] if fp64 else PEAK["fp32"], "TFLOP/s"
 
 
-def measured_traffic(cls):
-    """HBM bytes per launch of a kernel class from the committed rocprofv3 PMC
-    summary, if that summary was taken on the current source of the kernel."""
+def _current_record(path, section, cls):
+    """A class record of a committed rocprofv3 summary, if it was taken on the
+    current source of the kernel (SHA-256 of its files), else None."""
     try:
-        with open(TRAFFIC_FILE) as fh:
-            rec = json.load(fh)["classes"][cls]
+        with open(path) as fh:
+            rec = json.load(fh)[section][cls]
         h = hashlib.sha256()
         for src in rec["sources"]:
             with open(os.path.join(ROOT, src), "rb") as fh:
                 h.update(fh.read())
         if h.hexdigest() != rec["sha256"]:
             return None
-        return rec["bytes_per_launch"]
+        return rec
     except (OSError, KeyError, ValueError):
         return None
+
+
+def measured_traffic(cls, precision="fp32"):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3 PMC
+    summary, if that summary was taken on the current source of the kernel."""
+    if precision != "fp32":
+        return None
+    rec = _current_record(TRAFFIC_FILE, "classes", cls)
+    return rec["bytes_per_launch"] if rec else None
+
+
+def profiled_launch_ms(cls, precision):
+    """Average duration of one launch of a kernel class in the committed
+    rocprofv3 kernel statistics (kernel_stats.json), for the current source."""
+    rec = _current_record(STATS_FILE, precision, cls)
+    return rec["avg_ms"] if rec else None
 
 
 def roofline(table, precision, steps):
@@ -110,22 +130,56 @@ def roofline(table, precision, steps):
     avg_s = dom["ms"] / 1e3 / nl
     bound, peak, unit = class_bound(dom["name"], precision)
     per_launch = (dom["bytes"] if bound == "hbm" else dom["flops"]) / nl
-    achieved = per_launch / avg_s / (1e9 if bound == "hbm" else 1e12)
-    return {"bound": bound, "kernel": dom["name"], "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": measured_traffic(dom["name"]),
-            "avg_launch_ms": avg_s * 1e3, "launches_per_step": dom["launches"] / max(steps, 1),
-            "algorithmic_per_launch": per_launch,
-            "share_of_kernel_time": dom["ms"] / sum(r["ms"] for r in table)}
+    scale = 1e9 if bound == "hbm" else 1e12
+    achieved = per_launch / avg_s / scale
+    out = {"bound": bound, "kernel": dom["name"], "achieved": achieved, "peak": peak, "unit": unit,
+           "frac": achieved / peak, "traffic": measured_traffic(dom["name"], precision),
+           "avg_launch_ms": avg_s * 1e3, "launches_per_step": dom["launches"] / max(steps, 1),
+           "algorithmic_per_launch": per_launch,
+           "algorithmic_bytes_per_launch": dom["bytes"] / nl,
+           "share_of_kernel_time": dom["ms"] / sum(r["ms"] for r in table)}
+    # the same figure from the committed rocprofv3 average of this class
+    pms = profiled_launch_ms(dom["name"], precision)
+    if pms:
+        out["rocprof"] = {"avg_launch_ms": pms, "achieved": per_launch / (pms / 1e3) / scale,
+                          "frac": per_launch / (pms / 1e3) / scale / peak, "source": os.path.relpath(STATS_FILE, ROOT)}
+    return out
 
 
-def brief_table(table, precision, k=10):
+def brief_table(table, precision, k=12):
+    """Per kernel class: time, the bound it is measured against and its rate,
+    plus algorithmic bytes per launch and, where the committed PMC summary is
+    current, the counted HBM bytes per launch and their ratio."""
     out = []
     for r in sorted(table, key=lambda r: -r["ms"])[:k]:
         bound, peak, unit = class_bound(r["name"], precision)
-        rate = (r["bytes"] / 1e9 if bound == "hbm" else r["flops"] / 1e12) / max(r["ms"] / 1e3, 1e-12)
-        out.append({"class": r["name"], "launches": r["launches"], "ms": round(r["ms"], 3), "bound": bound,
-                    "achieved": rate, "unit": unit, "frac": rate / peak})
+        sec = max(r["ms"] / 1e3, 1e-12)
+        rate = (r["bytes"] / 1e9 if bound == "hbm" else r["flops"] / 1e12) / sec
+        nl = max(r["launches"], 1)
+        row = {"class": r["name"], "launches": r["launches"], "ms": round(r["ms"], 3), "bound": bound,
+               "achieved": rate, "unit": unit, "frac": rate / peak,
+               "alg_bytes_per_launch": r["bytes"] / nl, "alg_GBps": r["bytes"] / 1e9 / sec,
+               "flops_per_launch": r["flops"] / nl}
+        tr = measured_traffic(r["name"], precision)
+        if tr is not None and r["bytes"] > 0:
+            row["hbm_bytes_per_launch"] = tr
+            row["hbm_over_alg"] = tr / (r["bytes"] / nl)
+        out.append(row)
     return out
+
+
+def host_cpu():
+    """Model name and logical CPU count of the host (from /proc/cpuinfo)."""
+    model, count = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    count += 1
+                    model = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return model, count
 
 
 # ----------------------------------------------------------------- headline
@@ -192,7 +246,9 @@ def cpu_baseline(n, eps, leaf):
     o = OracleACR(coef, leaf, eps)
     o.solve(f)
     dt = time.perf_counter() - t0
+    model, logical = host_cpu()
     return {"value": n ** 3 / dt, "unit": "DOF/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "host_logical_cpus": logical, "affinity_cpus": len(os.sched_getaffinity(0)),
             "sample": f"oracle factor + one solve of the convection-diffusion operator at n={n} "
                       f"(N={n ** 3}), eps={eps}, leaf {leaf}, FP64 dense plane blocks; {dt:.2f} s"}
 
@@ -253,7 +309,12 @@ def headline(args, torch, acr):
     }
     if not args.no_fp64_form and args.precision != "fp64":
         log("fp64 form")
+        set_timing(L, 1)
         f64, x64 = run_form(acr, coef_d, b, args, "fp64", 1, 0)
+        set_timing(L, 0)
+        t64 = kernel_table(L)
+        f64["kernel_table"] = brief_table(t64, "fp64")
+        f64["roofline"] = roofline(t64, "fp64", 1)
         f64["error_vs_fp64_form"] = 0.0
         out["fp64_form"] = f64
         out["form"]["error_vs_fp64_form"] = float(torch.linalg.norm(x_main - x64) / torch.linalg.norm(x64))
@@ -262,6 +323,9 @@ def headline(args, torch, acr):
             fb, xb = run_form(acr, coef_d, b, args, "fp32_bf16leaf", 1, 0)
             fb["error_vs_fp64_form"] = float(torch.linalg.norm(xb - x64) / torch.linalg.norm(x64))
             out["bf16leaf_form"] = fb
+    if not args.no_precond_sweep:
+        log("preconditioner eps sweep (Table precond problem)")
+        out["precond_sweep"] = precond_sweep(acr, torch, n, args.leaf, args.precision, args.eps_list, warm=False)
     if not args.no_cpu_baseline:
         log(f"cpu baseline (oracle) n={args.cpu_n}")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.eps, args.leaf)
@@ -306,6 +370,36 @@ def helmholtz_mrhs(args, torch, acr):
     fac.free()
     log(f"helmholtz n={n}: factor {t_factor:.3f}s, {nrhs}-RHS solve {t_solve * 1e3:.2f} ms, "
         f"GMRES rhs0 {info['iterations']} its relres {info['relres']:.2e}")
+    # factors GMRES can use: eps = 1e-5 with the operation-internal truncations
+    # at eps / 100 (at eps = 1e-3 the indefinite Schur complements amplify the
+    # truncation errors beyond what GMRES(30) recovers from)
+    ue, ur = 1e-5, 0.01
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fu = acr.Factor(coef_d, eps=ue, leaf=leaf, precision="fp32", inner_eps_ratio=ur)
+    torch.cuda.synchronize()
+    tu = time.perf_counter() - t0
+    Xu = fu.solve(B)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fu.solve(B, out=Xu)
+    torch.cuda.synchronize()
+    tus = time.perf_counter() - t0
+    relu = sorted(float(fu.residual(Xu[j].contiguous(), B[j].contiguous()).norm() / B[j].norm())
+                  for j in range(nrhs))
+    per_rhs = []
+    for j in range(args.refine_rhs):
+        _, inf = fu.solve_refined(B[j].contiguous(), tol=1e-8, method="gmres", maxit=300, raise_on_fail=False)
+        per_rhs.append({"rhs": j, "iterations": inf["iterations"], "converged": inf["converged"],
+                        "relres": inf["relres"]})
+    stu = fu.stats()
+    fu.free()
+    log(f"helmholtz n={n} eps={ue:g} inner ratio {ur:g}: factor {tu:.3f}s, {nrhs}-RHS solve {tus * 1e3:.2f} ms, "
+        f"GMRES its {[r['iterations'] for r in per_rhs]}")
+    usable = {"eps": ue, "inner_eps_ratio": ur, "t_factor_s": tu, "solve_ms": tus * 1e3,
+              "solve_dof_per_s": N * nrhs / tus, "max_rank": stu["max_rank"], "factor_GB": stu["factor_bytes"] / 1e9,
+              "relres_unrefined": {"min": relu[0], "median": relu[len(relu) // 2], "max": relu[-1]},
+              "gmres_per_rhs": per_rhs}
     return {
         "metric": f"multi-RHS solve DOF/s (Helmholtz n={n}, {nrhs} RHS, FP32 factors)",
         "value": N * nrhs / t_solve, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -317,6 +411,7 @@ def helmholtz_mrhs(args, torch, acr):
         "t_factor_s": t_factor, "max_rank": st["max_rank"], "factor_GB": st["factor_bytes"] / 1e9,
         "relres_unrefined": {"min": rel[0], "median": rel[len(rel) // 2], "max": rel[-1]},
         "gmres_rhs0": {"iterations": info["iterations"], "converged": info["converged"], "relres": info["relres"]},
+        "refinable_factors": usable,
         "kernel_table": brief_table(table, "fp32"),
         "roofline": roofline(table, "fp32", 1),
     }
@@ -405,22 +500,21 @@ PAPER_PRECOND = {6e-1: (18.55, 0.050, 43, 20.72), 3e-1: (21.33, 0.053, 34, 23.14
                  1e-2: (51.24, 0.064, 11, 51.94), 1e-3: (89.32, 0.104, 4, 89.73), 1e-4: (149.06, 0.127, 3, 149.44)}
 
 
-def paper_precond(args, torch, acr):
-    """ACR as a CG preconditioner on the paper's own problem: constant-coefficient
-    Poisson with f = 1 at n = 128, eps swept as in its Table precond."""
-    import numpy as np
+def precond_sweep(acr, torch, n, leaf, precision, eps_list, warm=True):
+    """Rows of the preconditioner sweep: constant-coefficient Poisson with f = 1,
+    CG to 1e-6 preconditioned by the factorisation at each eps."""
     from workloads import problem
-    n, leaf = 128, args.leaf
     N = n ** 3
     coef_d = torch.from_numpy(problem("laplace", n)).cuda()
     b = torch.ones(N, dtype=torch.float64, device="cuda")
     rows = []
-    for eps in args.eps_list:
-        fac = acr.Factor(coef_d, eps=eps, leaf=leaf, precision=args.precision)   # warm-up
-        fac.free()
+    for eps in eps_list:
+        if warm:
+            fac = acr.Factor(coef_d, eps=eps, leaf=leaf, precision=precision)   # warm-up
+            fac.free()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        fac = acr.Factor(coef_d, eps=eps, leaf=leaf, precision=args.precision)
+        fac = acr.Factor(coef_d, eps=eps, leaf=leaf, precision=precision)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         x, info = fac.solve_refined(b, tol=1e-6, method="cg", maxit=500, raise_on_fail=False)
@@ -446,6 +540,15 @@ def paper_precond(args, torch, acr):
         rows.append(row)
         log(f"laplace n={n} eps={eps:g}: factor {t1 - t0:.3f}s CG {t2 - t1:.3f}s ({info['iterations']} its, "
             f"relres {info['relres']:.1e}) apply {t_apply * 1e3:.2f}ms max rank {st['max_rank']}")
+    return rows
+
+
+def paper_precond(args, torch, acr):
+    """ACR as a CG preconditioner on the paper's own problem: constant-coefficient
+    Poisson with f = 1 at n = 128, eps swept as in its Table precond."""
+    n, leaf = 128, args.leaf
+    N = n ** 3
+    rows = precond_sweep(acr, torch, n, leaf, args.precision, args.eps_list)
     best = min((r for r in rows if r["converged"]), key=lambda r: r["total_s"])
     paper_best = min(v[3] for v in PAPER_PRECOND.values())
     return {
@@ -494,6 +597,63 @@ PMC_CLASSES = [
     ("k_apply_leaf_vec<float>", "solve_leaf", ["paper_1701_00182_amd/csrc/solve_kernels.hip"]),
     ("k_inner_vec<float>", "solve_inner", ["paper_1701_00182_amd/csrc/solve_kernels.hip"]),
 ]
+# classes grouped for the kernel statistics only (no PMC figures taken)
+STATS_ONLY_CLASSES = [
+    ("k_seg_gemm<float>", "seg_gemm", ["paper_1701_00182_amd/csrc/gemm_mfma.hip"]),
+    ("k_gemm_f64", "gemm", ["paper_1701_00182_amd/csrc/gemm_mfma.hip"]),
+    ("k_gemm_lowp", "gemm_lowp", ["paper_1701_00182_amd/csrc/gemm_mfma.hip"]),
+    ("k_materialize_r", "materialize_r", ["paper_1701_00182_amd/csrc/gram.hip"]),
+    ("k_qr<float", "qr", ["paper_1701_00182_amd/csrc/la_lds.hip", "paper_1701_00182_amd/csrc/wave.h"]),
+]
+
+
+def _class_of(kernel):
+    """Kernel class of a rocprofv3 kernel name (either precision)."""
+    k = kernel.replace("<double", "<float")
+    for pre, cls, srcs in PMC_CLASSES + STATS_ONLY_CLASSES:
+        if k.startswith(pre):
+            return cls, srcs
+    return None, None
+
+
+def summarize_stats(d, precision, workload):
+    """profiles/kernel_stats.json, section `precision`: per kernel class, calls,
+    total and average duration from the rocprofv3 --stats CSV in d, with the
+    SHA-256 of the class's sources (bench.py uses a class's average only while
+    they are unchanged)."""
+    import csv
+    import glob
+    import re
+    acc = {}
+    for path in glob.glob(os.path.join(d, "**", "*_kernel_stats.csv"), recursive=True):
+        for r in csv.DictReader(open(path)):
+            name = re.sub(r"acr::\(anonymous namespace\)::", "", r["Name"])
+            name = re.sub(r"\(.*", "", name).replace("void ", "").strip()
+            cls, srcs = _class_of(name)
+            if not cls:
+                continue
+            a = acc.setdefault(cls, {"kernels": set(), "calls": 0, "total_ns": 0.0, "sources": srcs})
+            a["kernels"].add(name)
+            a["calls"] += int(r["Calls"])
+            a["total_ns"] += float(r["TotalDurationNs"])
+    try:
+        with open(STATS_FILE) as fh:
+            out = json.load(fh)
+    except (OSError, ValueError):
+        out = {}
+    sec = {}
+    for cls, a in sorted(acc.items(), key=lambda kv: -kv[1]["total_ns"]):
+        h = hashlib.sha256()
+        for src in a["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                h.update(fh.read())
+        sec[cls] = {"kernels": sorted(a["kernels"]), "calls": a["calls"], "total_ms": a["total_ns"] / 1e6,
+                    "avg_ms": a["total_ns"] / 1e6 / a["calls"], "sources": a["sources"], "sha256": h.hexdigest()}
+        print(f"{cls:12s} {a['calls']:7d} {a['total_ns'] / 1e6:10.1f} ms {a['total_ns'] / 1e6 / a['calls']:9.4f} ms")
+    out[precision] = sec
+    out.setdefault("workloads", {})[precision] = workload
+    with open(STATS_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
 
 
 def summarize_pmc(d, workload):
@@ -571,12 +731,23 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp32_bf16leaf", "fp32_fp16leaf"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--nrhs", type=int, default=256)
+    ap.add_argument("--refine-rhs", type=int, default=8, help="helmholtz_mrhs: right-hand sides refined by GMRES")
     ap.add_argument("--eps-list", type=float, nargs="+", default=[6e-1, 3e-1, 1e-1, 1e-2, 1e-3])
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--no-lowp-form", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precond-sweep", action="store_true",
+                    help="skip the eps sweep of the preconditioner (Table precond problem) in the default run")
+    ap.add_argument("--summarize-stats", nargs=2, metavar=("DIR", "PRECISION"),
+                    help="write the PRECISION section of profiles/kernel_stats.json from the rocprofv3 "
+                         "--stats CSV files in DIR (CPU only) and exit")
     ap.add_argument("--cpu-n", type=int, default=22)
     args = ap.parse_args()
+    if args.summarize_stats:
+        summarize_stats(args.summarize_stats[0], args.summarize_stats[1],
+                        f"convection-diffusion n={args.n}, {args.summarize_stats[1].upper()} factors, "
+                        f"eps={args.eps:g}, leaf {args.leaf}, svd_fused_lds {args.svd_fused_lds}")
+        return
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc,
                       f"convection-diffusion n={args.n}, FP32 factors, eps={args.eps:g}, leaf {args.leaf}, "

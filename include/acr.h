@@ -64,7 +64,11 @@ typedef struct {
   int32_t leaf;              /* maximum points per leaf cluster of the planar bisection, >= 1 */
   int32_t max_rank;          /* cap on any truncated rank, 0 = none (exceeding it -> error)   */
   int32_t precision;         /* acr_precision_t                                                */
-  double inner_eps_ratio;    /* accumulators inside one operation use eps * ratio; 0 -> 1     */
+  double inner_eps_ratio;    /* intermediate blocks and accumulators inside one operation     */
+                             /* (the SMW inverse, products, sums) are truncated at eps * ratio; */
+                             /* 0 -> 1.  Ratio 1 truncates at every operation; ratios < 1       */
+                             /* approach one truncation per stored block (indefinite operators  */
+                             /* such as Helmholtz need about 0.01)                              */
   /* optional device allocator (e.g. a framework's caching allocator); both NULL -> hipMalloc */
   void* (*alloc)(size_t bytes, void* ctx, hipStream_t stream);
   void (*release)(void* ptr, void* ctx, hipStream_t stream);
@@ -73,6 +77,7 @@ typedef struct {
                              /* needs at most this many bytes of LDS run both in one          */
                              /* workgroup; 0 = default (none), < 0 = never; capped at the     */
                              /* LDS budget.  Tuned by acr_autotune.                            */
+  int32_t stencil_points;    /* layout of coef: 7 (0 -> 7) or 27, see acr_factor              */
 } acr_options_t;
 
 /* Fills defaults: eps 1e-6, leaf 64, FP64, no rank cap, no allocator, default SVD
@@ -86,6 +91,11 @@ void acr_options_default(acr_options_t* opt);
  *   (A u)_r = C u_r + W u_{r-1} + E u_{r+1} + S u_{r-nx} + N u_{r+nx}
  *             + B u_{r-M} + T u_{r+M},   r = (k*ny + j)*nx + i.
  * D_k is the 5-point part of plane k, E_k = diag(B[k]), F_k = diag(T[k]).
+ * With options.stencil_points = 27 (e.g. the trilinear finite elements of
+ * Section 5.3) coef is coef[27][nplanes][ny][nx], slot
+ * s = 9 (dz + 1) + 3 (dy + 1) + (dx + 1) coupling node (i, j, k) to
+ * (i + dx, j + dy, k + dz); D_k, E_k and F_k are then the 9-point plane
+ * operators of dz = 0, -1, +1, and E_k, F_k are approximated like D_k.
  * Entries reaching outside the grid must be 0.  coef is read during the call
  * only; the handle keeps its own FP64 copy for residuals.  On success *out is
  * a new handle owning all factor memory; on failure *out is NULL.

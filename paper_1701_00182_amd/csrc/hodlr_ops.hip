@@ -9,8 +9,11 @@
 // small core and truncation at the relative tolerance (Section 3.1: the
 // accuracy is imposed on every block compression and every arithmetic
 // operation).  Contributions that reach a block from its ancestors (diagonal
-// low-rank terms) are accumulated top-down per segment and truncated at a
-// tighter inner tolerance.
+// low-rank terms) are accumulated top-down per segment and truncated at the
+// inner tolerance eps * inner_eps_ratio: ratio 1 (the default) truncates them
+// like every other operation result; smaller ratios approach one truncation
+// per stored block, which indefinite operators need (their Schur complements
+// amplify the extra truncation errors).
 #include <algorithm>
 #include <cstdio>
 

@@ -729,12 +729,15 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
     w.cls = lds ? "jacobi_lds" : "jacobi";
     unsigned long long* ctr = g_timing ? counter_slot() : nullptr;
     std::vector<SvdTask> bb = b;
-    for (auto& x : bb) x.sweep_ctr = ctr;
-    // one pair visit reads two columns of `rows` values, 3 dot products and a
-    // rotation of both: 12 * rows flops (the counter sums rows per visit)
+    // the kernels add the flops their sweeps did (inner products of every
+    // visit, rotations where applied) to the counter; algorithmic bytes: W^T
+    // (q x t) read once, at most t right vectors of length q written
+    for (auto& x : bb) {
+      x.sweep_ctr = ctr;
+      w.bytes += 2.0 * 8.0 * (double)x.q * (double)x.tc;
+    }
     w.counter = ctr;
-    w.flops_per_count = 12.0;
-    w.bytes_per_count = 32.0;
+    w.flops_per_count = 1.0;
     const SvdTask* dt = upload(bb);
     const int n = (int)bb.size();
     submit([=](hipStream_t s) { launch_jacobi<T>(dt, n, eps, fl, lds, s); }, w);

@@ -460,14 +460,17 @@ __device__ __forceinline__ bool jacobi_pair(double* xa, double* xb, int st, int 
 }
 
 // The sweeps of jacobi_svd for NU elements per lane (0: streamed); returns
-// the number of sweeps run.
+// the number of sweeps run and adds the flops done to `work`: the three inner
+// products of every pair visit (6 len) and the rotation of the pairs that
+// were rotated (6 len).
 template <int NT, int NU>
 __device__ __forceinline__ int jacobi_sweeps(double* V, int64_t vs, int64_t es, int n, int len, int G, double tol, double* red,
-                             int* redi) {
+                             int* redi, double& work) {
   const int ne = n + (n & 1), npairs = ne / 2;
   const int groups = NT / G;
   const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   int sweeps = 0;
+  double nrot = 0.0;
   // Sweeps end when one applies no rotation, or when its largest |cos| was at
   // most sqrt(tol): convergence is quadratic there, so the pairs are left
   // orthogonal to about tol and the confirming sweep is skipped.
@@ -480,7 +483,10 @@ __device__ __forceinline__ int jacobi_sweeps(double* V, int64_t vs, int64_t es, 
         int ia, ib;
         tournament_pair(pi, round, ne, ia, ib);
         if (ib >= n) continue;
-        if (jacobi_pair<NU>(V + ia * vs, V + ib * vs, (int)es, len, G, gl, tol, cmax2)) rot = 1;
+        if (jacobi_pair<NU>(V + ia * vs, V + ib * vs, (int)es, len, G, gl, tol, cmax2)) {
+          rot = 1;
+          nrot += gl == 0 ? 1.0 : 0.0;
+        }
       }
       __syncthreads();
     }
@@ -489,6 +495,8 @@ __device__ __forceinline__ int jacobi_sweeps(double* V, int64_t vs, int64_t es, 
     block_argmax<NT>(cmax2, dummy, red, redi);
     if (cmax2 <= tol) break;
   }
+  const double rots = block_sum<NT>(nrot, red);
+  work += 6.0 * (double)len * ((double)sweeps * 0.5 * (double)n * (double)(n - 1) + rots);
   return sweeps;
 }
 
@@ -681,16 +689,20 @@ __device__ inline bool jacobi_block_pair(double* X, int64_t vs, int n, int len, 
 
 // Sweeps of the blocked one-sided Jacobi over n columns of length len (column
 // stride vs, element stride 1); scratch holds kJBScratch doubles of LDS per
-// wavefront.  Returns the number of sweeps run.
+// wavefront.  Returns the number of sweeps run and adds the flops done to
+// `work`: the 16 x 16 Gram matrix of every block-pair visit (512 len) and the
+// update Y V of the pairs that changed (512 len).
 template <int NT>
 __device__ __forceinline__ int jacobi_block_sweeps(double* X, int64_t vs, int n, int len, double tol,
-                                                   double* scratch, double* red, int* redi) {
+                                                   double* scratch, double* red, int* redi, double& work) {
   const int nblk = (n + kJB - 1) / kJB;
   const int nb = nblk + (nblk & 1);
   const int npairs = nb / 2;
   const int wave = threadIdx.x >> 6;
   double* g = scratch + wave * kJBScratch;
   int sweeps = 0;
+  double visits = 0.0;
+  const double lead = (threadIdx.x & 63) == 0 ? 1.0 : 0.0;
   for (int sweep = 0; sweep < 60; ++sweep) {
     ++sweeps;
     int rot = 0;
@@ -699,7 +711,11 @@ __device__ __forceinline__ int jacobi_block_sweeps(double* X, int64_t vs, int n,
       for (int pi = wave; pi < npairs; pi += NT / 64) {
         int bi, bj;
         tournament_pair(pi, round, nb, bi, bj);
-        if (jacobi_block_pair(X, vs, n, len, bi, bj, tol, g, cmax2)) rot = 1;
+        visits += lead;
+        if (jacobi_block_pair(X, vs, n, len, bi, bj, tol, g, cmax2)) {
+          rot = 1;
+          visits += lead;
+        }
       }
       __threadfence_block();
       __syncthreads();
@@ -709,6 +725,7 @@ __device__ __forceinline__ int jacobi_block_sweeps(double* X, int64_t vs, int n,
     block_argmax<NT>(cmax2, dummy, red, redi);
     if (cmax2 <= tol) break;
   }
+  work += 512.0 * (double)len * block_sum<NT>(visits, red);
   return sweeps;
 }
 
@@ -723,7 +740,8 @@ __device__ __forceinline__ int jacobi_block_sweeps(double* X, int64_t vs, int n,
 template <int NT, int min_g = 1, bool BLOCKED = false>
 __device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int n, int len, const int* perm,
                                           double* sig, int* ord, double eps, const SvdTask& t, int* flags,
-                                          double* red, int* redi, int& sweeps, double* bscratch = nullptr) {
+                                          double* red, int* redi, int& sweeps, double& work,
+                                          double* bscratch = nullptr) {
   const int ne = n + (n & 1), npairs = ne / 2;
   // lanes per pair: up to one row of 16 (sums through DPP), fewer when that
   // takes every pair of a round in one pass; min_g keeps global-memory
@@ -748,15 +766,15 @@ __device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int
   const int nu = (len + G - 1) / G;
   if constexpr (BLOCKED) {
     // contiguous vectors (es == 1) and kJBScratch doubles per wavefront
-    sweeps = jacobi_block_sweeps<NT>(V, vs, n, len, tol, bscratch, red, redi);
+    sweeps = jacobi_block_sweeps<NT>(V, vs, n, len, tol, bscratch, red, redi, work);
   } else switch (nu <= kCap ? nu : 0) {
 #define ACR_JAC_NU(k) \
-  case k: sweeps = jacobi_sweeps<NT, (k <= kCap ? k : 0)>(V, vs, es, n, len, G, tol, red, redi); break;
+  case k: sweeps = jacobi_sweeps<NT, (k <= kCap ? k : 0)>(V, vs, es, n, len, G, tol, red, redi, work); break;
     ACR_JAC_NU(1) ACR_JAC_NU(2) ACR_JAC_NU(3) ACR_JAC_NU(4) ACR_JAC_NU(5) ACR_JAC_NU(6) ACR_JAC_NU(7)
     ACR_JAC_NU(8) ACR_JAC_NU(9) ACR_JAC_NU(10) ACR_JAC_NU(11) ACR_JAC_NU(12) ACR_JAC_NU(13) ACR_JAC_NU(14)
     ACR_JAC_NU(15) ACR_JAC_NU(16)
 #undef ACR_JAC_NU
-    default: sweeps = jacobi_sweeps<NT, 0>(V, vs, es, n, len, G, tol, red, redi); break;
+    default: sweeps = jacobi_sweeps<NT, 0>(V, vs, es, n, len, G, tol, red, redi, work); break;
   }
   for (int i = gi; i < n; i += groups) {
     const double* x = V + i * vs;
@@ -827,27 +845,27 @@ __global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks
     staged_copy<NT>((int64_t)rows * n, [&](int64_t e) { return t.Y[e]; }, [&](int64_t e, double v) { A[e] = v; });
   __syncthreads();
   int sweeps = 0;
+  double work = 0.0;
   // the pivot order is no longer needed: its workspace holds the sigma ranks.
   // Vectors in global memory take the blocked sweeps (LDS holds their
-  // per-wavefront Gram and rotation matrices); the counters record the
-  // equivalent pair visits of the scalar sweeps.
+  // per-wavefront Gram and rotation matrices); the counters record the flops
+  // the sweeps did.
   const int k = jacobi_svd<NT, LDS ? 1 : 16, !LDS>(A, rows, 1, n, rows, nullptr, t.sig, t.perm, eps, t, flags,
-                                                   red, redi, sweeps, LDS ? nullptr : smj);
+                                                   red, redi, sweeps, work, LDS ? nullptr : smj);
   if (threadIdx.x == 0) {
     *t.rank_out = k;
-    const unsigned long long visits =
-        (unsigned long long)sweeps * (unsigned long long)(n * (n - 1) / 2) * (unsigned long long)rows;
-    if (t.sweep_ctr) atomicAdd(t.sweep_ctr, visits);
-    if (t.flop_ctr) atomicAdd(t.flop_ctr, 12ull * visits);
+    const unsigned long long f = (unsigned long long)work;
+    if (t.sweep_ctr) atomicAdd(t.sweep_ctr, f);
+    if (t.flop_ctr) atomicAdd(t.flop_ctr, f);
   }
 }
 
 // flops of one core: its product (macs multiply-adds), the pivoted QR stopped
-// at n, and 12 per element of each pair visit of the sweeps
-__device__ inline void count_core_flops(const SvdTask& t, double macs, int n, int sweeps) {
+// at n, and the flops the sweeps did
+__device__ inline void count_core_flops(const SvdTask& t, double macs, int n, double sweep_work) {
   const double dp = t.p, dq = t.q, dn = n;
   const double fl = 2.0 * macs + 4.0 * dp * dq * dn - 2.0 * dn * dn * (dp + dq) + 4.0 / 3.0 * dn * dn * dn +
-                    12.0 * (double)sweeps * (dn * (dn - 1.0) / 2.0) * dq;
+                    sweep_work;
   const unsigned long long f = (unsigned long long)(fl > 0.0 ? fl : 0.0);
   if (t.sweep_ctr) atomicAdd(t.sweep_ctr, f);
   if (t.flop_ctr) atomicAdd(t.flop_ctr, f);
@@ -910,11 +928,13 @@ __global__ __launch_bounds__(NT) void k_svd_block(const SvdTask* __restrict__ ta
   for (int e = threadIdx.x; e < q * n; e += NT) C[e] = Wt[e];
   __syncthreads();
   int sweeps = 0;
-  const int k = n > 0 ? jacobi_svd<NT>(C, q, 1, n, q, nullptr, nrm, ord, eps, t, flags, red, redi, sweeps) : 0;
+  double work = 0.0;
+  const int k = n > 0 ? jacobi_svd<NT>(C, q, 1, n, q, nullptr, nrm, ord, eps, t, flags, red, redi, sweeps, work)
+                      : 0;
   if (threadIdx.x == 0) {
     *t.t_out = n;
     *t.rank_out = k;
-    count_core_flops(t, core_macs(t), n, sweeps);
+    count_core_flops(t, core_macs(t), n, work);
   }
 }
 
@@ -1011,7 +1031,8 @@ __global__ __launch_bounds__(64) void k_svd_wave(const SvdTask* __restrict__ tas
   clear_below(C, lc, n, 64);
   __syncthreads();
   int sweeps = 0;
-  const int k = n > 0 ? jacobi_svd<64>(C, 1, lc, n, q, perm, nrm, ord, eps, t, flags, red, redi, sweeps) : 0;
+  double work = 0.0;
+  const int k = n > 0 ? jacobi_svd<64>(C, 1, lc, n, q, perm, nrm, ord, eps, t, flags, red, redi, sweeps, work) : 0;
   // multiply-adds of the core product
   double macs = 0.0;
   if (lane < q)
@@ -1020,7 +1041,7 @@ __global__ __launch_bounds__(64) void k_svd_wave(const SvdTask* __restrict__ tas
   if (lane == 0) {
     *t.t_out = n;
     *t.rank_out = k;
-    count_core_flops(t, macs, n, sweeps);
+    count_core_flops(t, macs, n, work);
   }
 }
 
