@@ -9,8 +9,9 @@ operator (N = 2,097,152) plus an FP64 right-preconditioned GMRES(30) solve to
 relative residual 1e-8 with the factorisation as preconditioner.  Inputs are
 synthetic (seeded lognormal kappa, random divergence-free velocity at cell
 Peclet 1, f ~ N(0, 1)) and resident in device memory before the timed region.
-The plain FP64 form and the BF16-leaf variant (same eps and GMRES) are measured
-once beside it (the FP64 form with its own kernel table and roofline), the
+The plain FP64 form and the BF16 variant (every block product of the
+factorisation on BF16 matrix-core inputs with per-block scaling; same eps and
+GMRES) are measured once beside it (the FP64 form with its own kernel table and roofline), the
 factorisation is measured as a CG preconditioner of the paper's Table precond
 problem over its eps sweep, and the oracle is timed on the host on a bounded
 sample.
@@ -25,6 +26,9 @@ Other workloads (--workload, one JSON line each, not the headline):
                   per-cell gradient kernel)
   paper_precond   the paper's Table precond problem (-lap u = 1 at n = 128,
                   CG to 1e-6) over an eps sweep, beside the paper's numbers
+  helmholtz27     the paper's 27-point finite-element Helmholtz problem
+                  (k = n/2) at n = 32 and 64, GMRES to 1e-10, beside its
+                  Table ACRHelConfiguration
   copy_calibration  a plain 1 GiB device copy (reference dispatch for scaling
                   the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)
 
@@ -319,10 +323,14 @@ def headline(args, torch, acr):
         out["fp64_form"] = f64
         out["form"]["error_vs_fp64_form"] = float(torch.linalg.norm(x_main - x64) / torch.linalg.norm(x64))
         if not args.no_lowp_form:
-            log("bf16-leaf form")
-            fb, xb = run_form(acr, coef_d, b, args, "fp32_bf16leaf", 1, 0)
+            log("bf16 form")
+            set_timing(L, 1)
+            fb, xb = run_form(acr, coef_d, b, args, "fp32_bf16", 1, 0)
+            set_timing(L, 0)
+            tb = kernel_table(L)
+            fb["kernel_table"] = brief_table(tb, "fp32", k=6)
             fb["error_vs_fp64_form"] = float(torch.linalg.norm(xb - x64) / torch.linalg.norm(x64))
-            out["bf16leaf_form"] = fb
+            out["bf16_form"] = fb
     if not args.no_precond_sweep:
         log("preconditioner eps sweep (Table precond problem)")
         out["precond_sweep"] = precond_sweep(acr, torch, n, args.leaf, args.precision, args.eps_list, warm=False)
@@ -566,6 +574,59 @@ def paper_precond(args, torch, acr):
     }
 
 
+# the paper's Table ACRHelConfiguration: n -> (H_eps, eta, leaf, relres, average rank, largest rank)
+PAPER_HELM27 = {32: (5e-3, 4, 32, 1.67e-2, 5, 8), 64: (5e-8, 8, 32, 2.63e-2, 30, 56),
+                128: (5e-13, 16, 32, 1.07e-2, 113, 260)}
+
+
+def helmholtz27(args, torch, acr):
+    """The paper's indefinite Helmholtz problem (Section 5.3): -(lap u + k^2 u) = 1
+    on the unit cube, Dirichlet, trilinear finite elements (27-point stencil),
+    k = n / 2 (about 12 points per wavelength); FP32 factors with the
+    operation-internal truncations at eps / 100, FP64 GMRES(30) to 1e-10."""
+    from workloads import problem
+    rows = []
+    for n, eps in zip(args.h27_n, args.h27_eps):
+        N = n ** 3
+        coef_d = torch.from_numpy(problem("fem_helmholtz27", n)).cuda()
+        b = torch.ones(N, dtype=torch.float64, device="cuda")
+        fac = acr.Factor(coef_d, eps=eps, leaf=args.h27_leaf, precision="fp32", inner_eps_ratio=0.01)  # warm-up
+        fac.free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fac = acr.Factor(coef_d, eps=eps, leaf=args.h27_leaf, precision="fp32", inner_eps_ratio=0.01)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, info = fac.solve_refined(b, tol=1e-10, method="gmres", maxit=300, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st = fac.stats()
+        fac.free()
+        row = {"n": n, "N": N, "wavenumber": n / 2, "eps": eps, "leaf": args.h27_leaf, "t_factor_s": t1 - t0,
+               "t_gmres_s": t2 - t1, "gmres_applications": info["iterations"], "converged": info["converged"],
+               "relres": info["relres"], "relres_before_refinement": info["relres0"],
+               "avg_rank": st["avg_rank"], "max_rank": st["max_rank"], "factor_GB": st["factor_bytes"] / 1e9}
+        if n in PAPER_HELM27:
+            pe = PAPER_HELM27[n]
+            row["paper"] = {"H_eps": pe[0], "eta": pe[1], "leaf": pe[2], "relres": pe[3], "avg_rank": pe[4],
+                            "max_rank": pe[5]}
+        rows.append(row)
+        log(f"helmholtz27 n={n} eps={eps:g}: factor {t1 - t0:.3f}s, unrefined relres {info['relres0']:.2e}, "
+            f"GMRES {info['iterations']} its to {info['relres']:.1e} in {t2 - t1:.3f}s, ranks {st['avg_rank']:.1f}/"
+            f"{st['max_rank']}")
+    last = rows[-1]
+    return {
+        "metric": f"factor + GMRES-solve DOF/s (27-point FEM Helmholtz, n={last['n']}, k=n/2, GMRES to 1e-10)",
+        "value": last["N"] / (last["t_factor_s"] + last["t_gmres_s"]), "unit": "DOF/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": (last["t_factor_s"] + last["t_gmres_s"]) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "indefinite Helmholtz -(lap u + k^2 u) = 1, trilinear finite elements (27-point), "
+                               "k = n/2, HODLR FP32 factors (inner truncations at eps/100), FP64 GMRES(30)",
+                   "n": args.h27_n, "eps": args.h27_eps, "leaf": args.h27_leaf},
+        "rows": rows,
+    }
+
+
 def copy_calibration(torch):
     """A plain device copy of exactly 1 GiB, the reference dispatch for scaling
     rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -597,6 +658,9 @@ PMC_CLASSES = [
     ("k_apply_leaf_vec<float>", "solve_leaf", ["paper_1701_00182_amd/csrc/solve_kernels.hip"]),
     ("k_inner_vec<float>", "solve_inner", ["paper_1701_00182_amd/csrc/solve_kernels.hip"]),
 ]
+# kernel classes whose one launch (one timing record) is several dispatches:
+# the Gram partials and their ordered reduction
+DISPATCHES_PER_LAUNCH = {"gram": 2}
 # classes grouped for the kernel statistics only (no PMC figures taken)
 STATS_ONLY_CLASSES = [
     ("k_seg_gemm<float>", "seg_gemm", ["paper_1701_00182_amd/csrc/gemm_mfma.hip"]),
@@ -694,9 +758,11 @@ def summarize_pmc(d, workload):
         for src in srcs:
             with open(os.path.join(ROOT, src), "rb") as fh:
                 h.update(fh.read())
+        per_launch = DISPATCHES_PER_LAUNCH.get(cls, 1)
         classes[cls] = {"kernels": names, "sources": srcs, "sha256": h.hexdigest(), "dispatches": nd,
+                        "dispatches_per_launch": per_launch,
                         "fetch_kib_per_dispatch": round(fk, 1), "write_kib_per_dispatch": round(wk, 1),
-                        "bytes_per_launch": (fk * scale_f + wk * scale_w) * 1024}
+                        "bytes_per_launch": per_launch * (fk * scale_f + wk * scale_w) * 1024}
     out = {"workload": workload,
            "calibration": {"kernel": f"{copy} (torch copy of 1 GiB, bench.py --workload copy_calibration)",
                            "copy_bytes": int(copy_bytes), "fetch_kib": round(fetch_kib, 2),
@@ -706,7 +772,7 @@ def summarize_pmc(d, workload):
         json.dump(out, fh, indent=1)
     for cls, rec in classes.items():
         print(f"{cls:12s} {rec['dispatches']:6d} {rec['fetch_kib_per_dispatch']:14,.0f} "
-              f"{rec['write_kib_per_dispatch']:14,.0f} {rec['bytes_per_launch'] / 1e9:10.3f} GB")
+              f"{rec['write_kib_per_dispatch']:14,.0f} {rec['bytes_per_launch'] / 1e9:10.3f} GB per launch")
     print(f"calibration: fetch x{scale_f:.5f}, write x{scale_w:.5f}")
 
 
@@ -717,7 +783,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="convdiff",
                     choices=["convdiff", "helmholtz_mrhs", "poisson_ir", "gradient", "paper_precond",
-                             "copy_calibration"])
+                             "helmholtz27", "copy_calibration"])
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--leaf", type=int, default=128, help="leaf size (also one of the autotuner's candidates)")
@@ -728,10 +794,14 @@ def main():
                     help="write profiles/pmc_traffic.json from rocprofv3 FETCH_SIZE / WRITE_SIZE runs in "
                          "DIR/{fetch,write,cfetch,cwrite} (CPU only) and exit")
     ap.add_argument("--tune-planes", type=int, default=8)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp32_bf16leaf", "fp32_fp16leaf"])
+    ap.add_argument("--precision", default="fp32",
+                    choices=["fp32", "fp64", "fp32_bf16leaf", "fp32_fp16leaf", "fp32_bf16", "fp32_fp16"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--nrhs", type=int, default=256)
     ap.add_argument("--refine-rhs", type=int, default=8, help="helmholtz_mrhs: right-hand sides refined by GMRES")
+    ap.add_argument("--h27-n", type=int, nargs="+", default=[32, 64], help="helmholtz27: grid sizes")
+    ap.add_argument("--h27-eps", type=float, nargs="+", default=[5e-3, 1e-5], help="helmholtz27: eps per size")
+    ap.add_argument("--h27-leaf", type=int, default=32)
     ap.add_argument("--eps-list", type=float, nargs="+", default=[6e-1, 3e-1, 1e-1, 1e-2, 1e-3])
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--no-lowp-form", action="store_true")
@@ -767,7 +837,7 @@ def main():
         return
     import paper_1701_00182_amd as acr
     fn = {"convdiff": headline, "helmholtz_mrhs": helmholtz_mrhs, "poisson_ir": poisson_ir,
-          "gradient": gradient, "paper_precond": paper_precond}[args.workload]
+          "gradient": gradient, "paper_precond": paper_precond, "helmholtz27": helmholtz27}[args.workload]
     print(json.dumps(fn(args, torch, acr)), flush=True)
 
 

@@ -52,10 +52,18 @@ typedef enum {
   ACR_PREC_FP64 = 0,           /* factors stored and applied in FP64                              */
   ACR_PREC_FP32 = 1,           /* factors in FP32 (QR / products FP32, Jacobi SVD sweeps FP64)   */
   ACR_PREC_FP32_BF16LEAF = 2,  /* as FP32, but the dense leaf x leaf products of the factorisation */
-                               /* run on BF16 matrix-core inputs: each operand panel of a 64 x 64  */
-                               /* output tile is scaled by a power of two (largest magnitude into */
-                               /* [0.5, 1)), rounded to nearest even, accumulated in FP32          */
-  ACR_PREC_FP32_FP16LEAF = 3   /* the same with FP16 inputs                                        */
+                               /* run on BF16 matrix-core inputs: each 32-wide K block of an       */
+                               /* operand panel is scaled by a power of two (largest magnitude    */
+                               /* into [0.5, 1)), rounded to nearest even, accumulated in FP32     */
+  ACR_PREC_FP32_FP16LEAF = 3,  /* the same with FP16 inputs                                        */
+  ACR_PREC_FP32_BF16 = 4,      /* as FP32, but every block product of the factorisation (leaves,  */
+                               /* leaf x factor, factor x factor, the products of the inverse and */
+                               /* of H x H) runs on BF16 matrix-core inputs, each 32-wide K block  */
+                               /* of an operand panel scaled by a power of two (largest magnitude */
+                               /* into [0.5, 1)), accumulated in FP32; the compression (Gram, QR, */
+                               /* SVD, the rebuild of truncated factors) and the solves stay      */
+                               /* FP32 / FP64                                                      */
+  ACR_PREC_FP32_FP16 = 5       /* the same with FP16 inputs                                        */
 } acr_precision_t;
 
 typedef struct {

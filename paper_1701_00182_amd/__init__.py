@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libacr.so")
 _LIB = None
 
-PREC = {"fp64": 0, "fp32": 1, "fp32_bf16leaf": 2, "fp32_fp16leaf": 3}
+PREC = {"fp64": 0, "fp32": 1, "fp32_bf16leaf": 2, "fp32_fp16leaf": 3, "fp32_bf16": 4, "fp32_fp16": 5}
 STATUS = {0: "success", 1: "invalid value", 2: "out of memory", 3: "HIP error",
           4: "singular", 5: "rank capacity", 6: "not converged", 7: "not supported"}
 
@@ -35,7 +35,7 @@ class Options(ctypes.Structure):
                 ("eps", ctypes.c_double), ("leaf", ctypes.c_int32), ("max_rank", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_eps_ratio", ctypes.c_double),
                 ("alloc", ctypes.c_void_p), ("release", ctypes.c_void_p), ("alloc_ctx", ctypes.c_void_p),
-                ("svd_fused_lds", ctypes.c_int32)]
+                ("svd_fused_lds", ctypes.c_int32), ("stencil_points", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):
@@ -172,15 +172,16 @@ def _rhs_view(b, N):
 
 
 class Factor:
-    """ACR factorisation of a 7-point operator given as coef[7, nz, ny, nx] (FP64, CUDA)."""
+    """ACR factorisation of a 7-point operator given as coef[7, nz, ny, nx] or a
+    27-point one given as coef[27, nz, ny, nx] (FP64, CUDA)."""
 
     def __init__(self, coef, eps=1e-6, leaf=64, precision="fp64", max_rank=0, inner_eps_ratio=1.0,
                  svd_fused_lds=0):
         L = lib()
-        if coef.dim() != 4 or coef.shape[0] != 7:
-            raise ValueError("coef must be shaped (7, nz, ny, nx)")
+        if coef.dim() != 4 or coef.shape[0] not in (7, 27):
+            raise ValueError("coef must be shaped (7, nz, ny, nx) or (27, nz, ny, nx)")
         _dev_f64(coef, "coef")
-        _, nz, ny, nx = coef.shape
+        ns, nz, ny, nx = coef.shape
         o = Options()
         L.acr_options_default(ctypes.byref(o))
         o.nx, o.ny, o.nplanes = nx, ny, nz
@@ -188,6 +189,7 @@ class Factor:
         o.precision = PREC[precision]
         o.inner_eps_ratio = float(inner_eps_ratio)
         o.svd_fused_lds = int(svd_fused_lds)
+        o.stencil_points = ns
         h = ctypes.c_void_p()
         _check(L.acr_factor(ctypes.byref(o), ctypes.c_void_p(coef.data_ptr()), _stream(), ctypes.byref(h)),
                "acr_factor")
@@ -293,14 +295,15 @@ def autotune(coef, eps=1e-6, precision="fp64", leaf=64, sample_planes=16, cache=
     """Leaf size and core-SVD dispatch picked by timing a sample of the operator
     (acr_autotune); returns a dict with leaf, svd_fused_lds, seconds, tried,
     from_cache.  Pass leaf / svd_fused_lds on to Factor."""
-    if coef.dim() != 4 or coef.shape[0] != 7:
-        raise ValueError("coef must be shaped (7, nz, ny, nx)")
+    if coef.dim() != 4 or coef.shape[0] not in (7, 27):
+        raise ValueError("coef must be shaped (7, nz, ny, nx) or (27, nz, ny, nx)")
     _dev_f64(coef, "coef")
     L = lib()
-    _, nz, ny, nx = coef.shape
+    ns, nz, ny, nx = coef.shape
     o = Options()
     L.acr_options_default(ctypes.byref(o))
     o.nx, o.ny, o.nplanes = nx, ny, nz
+    o.stencil_points = ns
     o.eps, o.leaf, o.max_rank = float(eps), int(leaf), int(max_rank)
     o.precision = PREC[precision]
     o.inner_eps_ratio = float(inner_eps_ratio)

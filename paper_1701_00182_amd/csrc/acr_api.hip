@@ -110,6 +110,7 @@ template <class T> struct FactorT : FactorBase {
   double t_factor = 0;
   bool use_graph = true;
   bool fused_ok = true;   // ACR_FUSED_SOLVE=0 records the GEMM-based sweeps instead
+  int prod_lowp = 0;      // 16-bit inputs for every factorisation product (not for the solves)
   static constexpr int kFusedMaxRhs = 4;
 
   void destroy_all() {
@@ -254,11 +255,140 @@ template <class T> struct FactorT : FactorBase {
     }
   }
 
+  // ---------------------------------------------------------- level 0, 27 points
+  // D_k, E_k and F_k are 9-point plane operators (the in-plane slots of the
+  // offsets dz = 0, -1, +1).  Each is first written exactly in HODLR form --
+  // dense leaves, and every off-diagonal block as U V^T with U selecting the
+  // rows that couple across the cut (one column per row) and V holding their
+  // couplings -- then truncated at eps block by block (the block-wise
+  // approximation of the first step of Algorithm 1, for every block of A).
+  void convert27(std::vector<HMat<T>>& D, std::vector<HMat<T>>& E, std::vector<HMat<T>>& F) {
+    const int M = tr.M, L = tr.L, nz = grid.nz, nx = tr.nx, ny = tr.ny;
+    const int nleaf = 1 << L, nblk = tr.nblk();
+    std::vector<int> iperm(M);
+    for (int p = 0; p < M; ++p) iperm[tr.perm[p]] = p;
+    std::vector<std::vector<int>> seg_of(L + 1, std::vector<int>(M));
+    for (int d = 0; d <= L; ++d)
+      for (int s = 0; s < (1 << d); ++s)
+        for (int p = tr.off[d][s]; p < tr.off[d][s] + tr.sz[d][s]; ++p) seg_of[d][p] = s;
+    // the pattern (in-plane offset t = 3 (dy + 1) + (dx + 1)) is shared by the
+    // three operators; their slots are 9 (dz + 1) + t
+    std::vector<LeafEnt> le;
+    std::vector<Cut9Ent> ce;
+    std::vector<int> rank(nblk, 0), rows(nblk, 0), cols(nblk, 0);
+    std::vector<std::vector<int>> colof(nblk);   // per block: row point -> column, or -1
+    for (int d = 0; d < L; ++d)
+      for (int s = 0; s < (2 << d); ++s) {
+        const int b = Tree::bid(d, s);
+        rows[b] = tr.sz[d + 1][s];
+        cols[b] = tr.sz[d + 1][s ^ 1];
+        colof[b].assign(rows[b], -1);
+      }
+    for (int a = 0; a < M; ++a) {
+      const int nat = tr.perm[a], i = nat % nx, j = nat / nx;
+      const int la = seg_of[L][a], lo = tr.off[L][la], ln = tr.sz[L][la];
+      for (int t = 0; t < 9; ++t) {
+        const int ii = i + t % 3 - 1, jj = j + t / 3 - 1;
+        if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
+        const int bp = iperm[jj * nx + ii];
+        if (seg_of[L][bp] == la) {
+          le.push_back(LeafEnt{la, a - lo, bp - lo, ln, t, nat});
+          continue;
+        }
+        int d = 0;
+        while (seg_of[d + 1][a] == seg_of[d + 1][bp]) ++d;
+        const int s = seg_of[d + 1][a];
+        const int b = Tree::bid(d, s);
+        const int r = a - tr.off[d + 1][s];
+        if (colof[b][r] < 0) colof[b][r] = rank[b]++;
+        ce.push_back(Cut9Ent{b, colof[b][r], r, bp - tr.off[d + 1][s ^ 1], t, nat});
+      }
+    }
+    const int nle = (int)le.size(), nce = (int)ce.size();
+    const double* cf = coef;
+    Grid g = grid;
+    D.assign(nz, HMat<T>{});
+    E.assign(nz, HMat<T>{});
+    F.assign(nz, HMat<T>{});
+    // exact forms in levtmp (released once the truncated blocks exist)
+    std::vector<HMat<T>> X[3];
+    std::vector<SumJob<T>> jd, jef;
+    for (int o = 0; o < 3; ++o) {
+      const int dz = o == 0 ? 0 : (o == 1 ? -1 : 1);
+      X[o].assign(nz, HMat<T>{});
+      std::vector<T*> lp((size_t)nz * nleaf, nullptr), up((size_t)nz * nblk, nullptr), vp((size_t)nz * nblk, nullptr);
+      std::vector<CopyTask> zero;
+      for (int k = 0; k < nz; ++k) {
+        if (k + dz < 0 || k + dz >= nz) continue;   // no plane to couple to
+        HMat<T>& H = X[o][k];
+        hodlr_alloc_leaves(tr, H, levtmp);
+        for (int l = 0; l < nleaf; ++l) {
+          lp[(size_t)k * nleaf + l] = H.leaf[l];
+          const int n = tr.sz[L][l];
+          CopyTask c{};
+          c.dst = H.leaf[l]; c.ldd = n; c.m = n; c.n = n; c.alpha = 0.0;
+          zero.push_back(c);
+        }
+        for (int b = 0; b < nblk; ++b) {
+          LR<T>& blk = H.blk[b];
+          blk.k = rank[b];
+          if (!rank[b]) continue;
+          blk.U = levtmp.get_n<T>((size_t)rows[b] * rank[b]);
+          blk.V = levtmp.get_n<T>((size_t)cols[b] * rank[b]);
+          up[(size_t)k * nblk + b] = blk.U;
+          vp[(size_t)k * nblk + b] = blk.V;
+          CopyTask c{};
+          c.dst = blk.U; c.ldd = rows[b]; c.m = rows[b]; c.n = rank[b];
+          zero.push_back(c);
+          c.dst = blk.V; c.ldd = cols[b]; c.m = cols[b];
+          zero.push_back(c);
+        }
+        SumJob<T> sj;
+        sj.terms.push_back({&H, 1.0});
+        sj.C = o == 0 ? &D[k] : (o == 1 ? &E[k] : &F[k]);
+        (o == 0 ? jd : jef).push_back(sj);
+      }
+      ex.copy<T>(zero);
+      // the operator's slots: 9 (dz + 1) + t
+      std::vector<LeafEnt> leo = le;
+      for (auto& x : leo) x.slot += 9 * (dz + 1);
+      std::vector<Cut9Ent> ceo = ce;
+      for (auto& x : ceo) x.slot += 9 * (dz + 1);
+      const LeafEnt* d_le = nle ? ex.upload(leo) : nullptr;
+      T* const* d_lp = ex.upload(lp);
+      ex.submit([=](hipStream_t s) { launch_conv_leaves<T>(g, cf, d_le, nle, d_lp, nleaf, s); });
+      if (nce) {
+        const Cut9Ent* d_ce = ex.upload(ceo);
+        T* const* d_up = ex.upload(up);
+        T* const* d_vp = ex.upload(vp);
+        const int* d_rows = ex.upload(rows);
+        const int* d_cols = ex.upload(cols);
+        ex.submit([=](hipStream_t s) {
+          launch_cut9_fill<T>(g, cf, d_ce, nce, nblk, d_up, d_vp, d_rows, d_cols, s);
+        });
+      }
+    }
+    ex.trace_tag = "level-0 D";
+    hodlr_sum<T>(ex, tr, jd, tc, lvl[0], tmp);
+    ex.trace_tag = "level-0 E, F";
+    if (!jef.empty()) hodlr_sum<T>(ex, tr, jef, tc, fac, tmp);
+    ex.sync();
+    levtmp.reset();
+  }
+
   // ---------------------------------------------------------- factor
   void factor() {
     const double t0 = now_s();
+    ex.prod_lowp = prod_lowp;
+    struct Reset {
+      Exec& e;
+      ~Reset() { e.prod_lowp = 0; }
+    } reset{ex};
     std::vector<HMat<T>> D, E, F;
-    convert(D, E, F);
+    if (grid.ns == 27)
+      convert27(D, E, F);
+    else
+      convert(D, E, F);
     std::vector<int> alive(grid.nz);
     for (int k = 0; k < grid.nz; ++k) alive[k] = k;
     int cur = 0;
@@ -784,12 +914,14 @@ FactorBase* make_factor(const acr_options_t* o, const double* coef_in, hipStream
   al.ctx = o->alloc_ctx;
   f->ex.init(s, al);
   f->ex.leaf_lowp = o->precision == ACR_PREC_FP32_BF16LEAF ? 1 : (o->precision == ACR_PREC_FP32_FP16LEAF ? 2 : 0);
+  f->prod_lowp = o->precision == ACR_PREC_FP32_BF16 ? 1 : (o->precision == ACR_PREC_FP32_FP16 ? 2 : 0);
+  if (f->prod_lowp) f->ex.leaf_lowp = f->prod_lowp;
   // core-SVD dispatch: the option, overridden by ACR_FUSED_LDS (bytes) when set
   if (o->svd_fused_lds < 0) f->ex.fused_lds = 0;
   else if (o->svd_fused_lds > 0) f->ex.fused_lds = std::min<size_t>((size_t)o->svd_fused_lds, kLdsBudget);
   if (const char* fu = std::getenv("ACR_FUSED_LDS"))
     f->ex.fused_lds = std::min<size_t>(std::strtoull(fu, nullptr, 10), kLdsBudget);
-  f->grid = Grid{o->nx, o->ny, o->nplanes};
+  f->grid = Grid{o->nx, o->ny, o->nplanes, o->stencil_points == 27 ? 27 : 7};
   f->persist.init(&f->ex, size_t(32) << 20);
   f->refine_mem.init(&f->ex, size_t(64) << 20);
   const size_t big = size_t(512) << 20;
@@ -808,8 +940,9 @@ FactorBase* make_factor(const acr_options_t* o, const double* coef_in, hipStream
   const char* fs = std::getenv("ACR_FUSED_SOLVE");
   f->fused_ok = !(fs && fs[0] == '0');
   const int64_t N = f->grid.N();
-  f->coef = f->persist.template get_n<double>(7 * (size_t)N);
-  hip_check(hipMemcpyAsync(f->coef, coef_in, 7 * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s),
+  const size_t ns = (size_t)f->grid.ns;
+  f->coef = f->persist.template get_n<double>(ns * (size_t)N);
+  hip_check(hipMemcpyAsync(f->coef, coef_in, ns * (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s),
             "hipMemcpyAsync(coef)");
   f->d_perm = f->persist.template get_n<int>(f->tr.M);
   hip_check(hipMemcpyAsync(f->d_perm, f->tr.perm.data(), f->tr.M * sizeof(int), hipMemcpyHostToDevice, s),
@@ -1034,8 +1167,9 @@ template <class F> acr_status_t guarded(F&& fn) {
 
 std::string tune_key(const acr_options_t* o, int sp) {
   char k[256];
-  std::snprintf(k, sizeof(k), "nx=%d ny=%d planes=%d eps=%.17g precision=%d max_rank=%d inner=%.17g", o->nx, o->ny,
-                sp, o->eps, o->precision, o->max_rank, o->inner_eps_ratio > 0 ? o->inner_eps_ratio : 1.0);
+  std::snprintf(k, sizeof(k), "nx=%d ny=%d planes=%d eps=%.17g precision=%d max_rank=%d inner=%.17g stencil=%d",
+                o->nx, o->ny, sp, o->eps, o->precision, o->max_rank,
+                o->inner_eps_ratio > 0 ? o->inner_eps_ratio : 1.0, o->stencil_points == 27 ? 27 : 7);
   return k;
 }
 
@@ -1080,23 +1214,28 @@ acr_status_t autotune_impl(const acr_options_t* opt, const double* coef, int sam
     return ACR_SUCCESS;
   }
   const int64_t M = (int64_t)opt->nx * opt->ny, Ns = M * sp, Nf = M * opt->nplanes;
-  // sample operator: the first sp planes of every stencil slot; the coupling
-  // from the last sample plane to the next (slot T) is dropped
+  // sample operator: the first sp planes of every stencil slot; the couplings
+  // from the last sample plane to the next (slot T, or the nine dz = +1 slots
+  // of a 27-point stencil) are dropped
+  const int ns = opt->stencil_points == 27 ? 27 : 7;
   double* d = nullptr;
-  hip_check(hipMalloc((void**)&d, sizeof(double) * (7 * Ns + 2 * Ns)), "hipMalloc(autotune)");
+  hip_check(hipMalloc((void**)&d, sizeof(double) * (ns * Ns + 2 * Ns)), "hipMalloc(autotune)");
   struct Free {
     double* p;
     ~Free() { (void)hipFree(p); }
   } guard{d};
   double* dcoef = d;
-  double* db = d + 7 * Ns;
+  double* db = d + ns * Ns;
   double* dx = db + Ns;
-  for (int s = 0; s < 7; ++s)
+  for (int s = 0; s < ns; ++s)
     hip_check(hipMemcpyAsync(dcoef + s * Ns, coef + s * Nf, sizeof(double) * Ns, hipMemcpyDeviceToDevice, stream),
               "hipMemcpyAsync(sample)");
-  hip_check(hipMemsetAsync(dcoef + 6 * Ns + (sp - 1) * M, 0, sizeof(double) * M, stream), "hipMemsetAsync(sample)");
+  for (int s = ns == 27 ? 18 : 6; s < ns; ++s)
+    hip_check(hipMemsetAsync(dcoef + s * Ns + (sp - 1) * M, 0, sizeof(double) * M, stream), "hipMemsetAsync(sample)");
   // right-hand side: the sample's diagonal coefficients (any non-zero vector)
-  hip_check(hipMemcpyAsync(db, dcoef, sizeof(double) * Ns, hipMemcpyDeviceToDevice, stream), "hipMemcpyAsync(rhs)");
+  const int centre = ns == 27 ? 13 : 0;
+  hip_check(hipMemcpyAsync(db, dcoef + centre * Ns, sizeof(double) * Ns, hipMemcpyDeviceToDevice, stream),
+            "hipMemcpyAsync(rhs)");
   std::vector<int> leaves;
   for (int l : {32, 64, 128, opt->leaf})
     if (l >= 1 && l <= M && std::find(leaves.begin(), leaves.end(), l) == leaves.end()) leaves.push_back(l);

@@ -12,11 +12,12 @@
 // matrix-core input type on the way in:
 //   FP64 data            v_mfma_f64_16x16x4_f64   (2 x 2 per wavefront)
 //   FP32 data            v_mfma_f32_32x32x2_f32
-//   FP32 data, 16-bit    v_mfma_f32_32x32x16_{bf16,f16}: the A row panel and
-//                        the B column panel of the tile are scaled by powers of
-//                        two that bring their largest magnitude into [0.5, 1),
-//                        rounded to nearest even, accumulated in FP32, and the
-//                        scales are removed exactly when C is written.
+//   FP32 data, 16-bit    v_mfma_f32_32x32x16_{bf16,f16}: each K block of the
+//                        A row panel and of the B column panel of the tile is
+//                        scaled by a power of two that brings its largest
+//                        magnitude into [0.5, 1), rounded to nearest even; the
+//                        block's product is accumulated in FP32 with the
+//                        scales removed exactly.
 // Operand / accumulator lane layouts (64 lanes, lane l):
 //   32x32xK: A[i = l % 32][k = kb * (l / 32) + 0..kb-1], B[k ...][j = l % 32],
 //            D[v] = C[8 (v / 4) + 4 (l / 32) + v % 4][l % 32]  (v = 0..15)
@@ -61,28 +62,29 @@ __device__ inline void store_tile(const GemmTask& t, int row0, int col0, int i, 
   *c = r;
 }
 
-// Register-staged operand tile: 64 positions p (rows of op(A) or columns of
+// Register-staged operand tile: P positions p (rows of op(A) or columns of
 // op(B)) x KB values of k, element (p, k) at base[p * sp + k * sk] with one of
 // sp / sk equal to 1.  Each thread moves NV vectors of VEC consecutive elements
 // along the contiguous dimension (one 16-byte load when aligned and inside the
 // matrix, element loads with zero fill otherwise); the values are held in
 // registers while the previous block is multiplied, then written to LDS.
-template <class T, int KB> struct Stage {
+template <class T, int KB, int P = 64> struct Stage {
   static constexpr int VEC = 16 / sizeof(T);
-  static constexpr int NV = 64 * KB / (VEC * 256);
+  static constexpr int NV = P * KB / (VEC * 256);
+  static_assert(NV >= 1 && NV * VEC * 256 == P * KB, "tile not a multiple of the workgroup's vectors");
   T v[NV][VEC];
 
-  __device__ inline void load(const T* base, int64_t sp, int64_t sk, int P, int K, int p0, int k0) {
+  __device__ inline void load(const T* base, int64_t sp, int64_t sk, int np, int K, int p0, int k0) {
     const bool pc = sp == 1;
 #pragma unroll
     for (int s = 0; s < NV; ++s) {
       const int e = threadIdx.x + s * 256;
       int p, k;
-      if (pc) { p = (e % (64 / VEC)) * VEC; k = e / (64 / VEC); }
+      if (pc) { p = (e % (P / VEC)) * VEC; k = e / (P / VEC); }
       else { k = (e % (KB / VEC)) * VEC; p = e / (KB / VEC); }
       const int gp = p0 + p, gk = k0 + k;
       const T* ptr = base + gp * sp + gk * sk;
-      const bool full = pc ? (gp + VEC <= P && gk < K) : (gp < P && gk + VEC <= K);
+      const bool full = pc ? (gp + VEC <= np && gk < K) : (gp < np && gk + VEC <= K);
       if (full && (((uintptr_t)ptr & 15) == 0)) {
         typedef T V __attribute__((ext_vector_type(VEC)));
         const V x = *reinterpret_cast<const V*>(ptr);
@@ -92,7 +94,7 @@ template <class T, int KB> struct Stage {
 #pragma unroll
         for (int u = 0; u < VEC; ++u) {
           const int qp = pc ? gp + u : gp, qk = pc ? gk : gk + u;
-          v[s][u] = (qp < P && qk < K) ? base[qp * sp + qk * sk] : T(0);
+          v[s][u] = (qp < np && qk < K) ? base[qp * sp + qk * sk] : T(0);
         }
       }
     }
@@ -103,7 +105,7 @@ template <class T, int KB> struct Stage {
     for (int s = 0; s < NV; ++s) {
       const int e = threadIdx.x + s * 256;
       int p, k;
-      if (pc) { p = (e % (64 / VEC)) * VEC; k = e / (64 / VEC); }
+      if (pc) { p = (e % (P / VEC)) * VEC; k = e / (P / VEC); }
       else { k = (e % (KB / VEC)) * VEC; p = e / (KB / VEC); }
 #pragma unroll
       for (int u = 0; u < VEC; ++u) {
@@ -166,6 +168,56 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const GemmTask* __restrict__ t
 #pragma unroll
   for (int v = 0; v < 16; ++v)
     store_tile<float>(t, row0, col0, wr + (lane & 31), wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), acc[v]);
+}
+
+// FP32 data, FP32 matrix cores, for outputs at most 32 columns wide (the
+// low-rank side of most factorisation products): 128 x 32 output tiles, wave
+// w owning rows 32 w .. 32 w + 31, so that no matrix-core work goes to the
+// empty half of a 64 x 64 tile.
+__global__ __launch_bounds__(256) void k_gemm_f32_n32(const GemmTask* __restrict__ tasks,
+                                                      const int* __restrict__ tile_task,
+                                                      const int* __restrict__ first_tile) {
+  constexpr int KB = 32;
+  const int ti = tile_task[blockIdx.x];
+  const GemmTask t = tasks[ti];
+  const int row0 = (blockIdx.x - first_tile[ti]) * 128;
+  __shared__ float As[KB][128 + 4];
+  __shared__ float Bs[KB][32 + 4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w * 32;
+  const float* A = static_cast<const float*>(t.A);
+  const float* B = static_cast<const float*>(t.B);
+  int64_t asp, ask, bsp, bsk;
+  a_geom(t, asp, ask);
+  b_geom(t, bsp, bsk);
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  Stage<float, KB, 128> sa;
+  Stage<float, KB, 32> sb;
+  if (t.k > 0) {
+    sa.load(A, asp, ask, t.m, t.k, row0, 0);
+    sb.load(B, bsp, bsk, t.n, t.k, 0, 0);
+  }
+  for (int k0 = 0; k0 < t.k; k0 += KB) {
+    sa.store(As, asp == 1);
+    sb.store(Bs, bsp == 1);
+    __syncthreads();
+    if (k0 + KB < t.k) {   // next block in flight during the products
+      sa.load(A, asp, ask, t.m, t.k, row0, k0 + KB);
+      sb.load(B, bsp, bsk, t.n, t.k, 0, k0 + KB);
+    }
+#pragma unroll
+    for (int kk = 0; kk < KB; kk += 2) {
+      const float a = As[kk + (lane >> 5)][wr + (lane & 31)];
+      const float b = Bs[kk + (lane >> 5)][lane & 31];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b, a, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v)
+    store_tile<float>(t, row0, 0, wr + (lane & 31), 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), acc[v]);
 }
 
 // FP64 data, FP64 matrix cores.
@@ -239,24 +291,31 @@ template <> struct Mfma16<_Float16> {
   static __device__ inline f32x16 run(V a, V b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0); }
 };
 
-// power of two s with max * s in [0.5, 1) (1 for an all-zero panel)
-__device__ inline float panel_scale(float mx) {
-  if (!(mx > 0.f) || !isfinite(mx)) return 1.f;
+// Exponent e with max * 2^-e in [0.5, 1) (0 for an all-zero or non-finite block).
+__device__ inline int block_exponent(float mx) {
+  if (!(mx > 0.f) || !isfinite(mx)) return 0;
   int e;
   (void)frexpf(mx, &e);
-  return ldexpf(1.f, -e);
+  return e;
 }
 
-// FP32 data through 16-bit matrix-core inputs with per-panel scaling.
+// FP32 data through 16-bit matrix-core inputs.  The operands are staged with
+// the FP32 kernel's 16-byte register loads; each K block of the A row panel
+// and of the B column panel is scaled by a power of two that brings its
+// largest magnitude into [0.5, 1) (a workgroup maximum over the staged
+// values), rounded to nearest even into LDS (k contiguous, so that each lane
+// reads its 8 k values at once), multiplied into a fresh FP32 accumulator, and
+// that block's product is added to the tile with the scales removed (exactly:
+// a power of two).
 template <class H>
 __global__ __launch_bounds__(256) void k_gemm_lowp(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_task,
                                                    const int* __restrict__ first_tile) {
   constexpr int KB = 32;
+  typedef Stage<float, KB> S;
   const int ti = tile_task[blockIdx.x];
   const GemmTask t = tasks[ti];
   int row0, col0;
   tile_of(t, blockIdx.x - first_tile[ti], row0, col0);
-  // operands stored k-contiguous so that each lane reads its 8 k values at once
   __shared__ __attribute__((aligned(16))) H As[64][KB + 8];
   __shared__ __attribute__((aligned(16))) H Bs[64][KB + 8];
   __shared__ float red[2][4];
@@ -264,52 +323,73 @@ __global__ __launch_bounds__(256) void k_gemm_lowp(const GemmTask* __restrict__ 
   const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
   const float* A = static_cast<const float*>(t.A);
   const float* B = static_cast<const float*>(t.B);
-  // panel maxima: rows row0.. of op(A) and columns col0.. of op(B) over all k
-  float ma = 0.f, mb = 0.f;
-  for (int e = tid; e < 64 * t.k; e += 256) {
-    int i, kk;
-    if (!t.ta) { i = e & 63; kk = e >> 6; } else { kk = e % t.k; i = e / t.k; }
-    ma = fmaxf(ma, fabsf(load_a(t, A, row0 + i, kk)));
-    int j, k2;
-    if (!t.tb) { k2 = e % t.k; j = e / t.k; } else { j = e & 63; k2 = e >> 6; }
-    mb = fmaxf(mb, fabsf(load_b(t, B, k2, col0 + j)));
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    ma = fmaxf(ma, __shfl_xor(ma, off, 64));
-    mb = fmaxf(mb, __shfl_xor(mb, off, 64));
-  }
-  if (lane == 0) { red[0][w] = ma; red[1][w] = mb; }
-  __syncthreads();
-  ma = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
-  mb = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
-  const float sa = panel_scale(ma), sb = panel_scale(mb);
+  int64_t asp, ask, bsp, bsk;
+  a_geom(t, asp, ask);
+  b_geom(t, bsp, bsk);
   f32x16 acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.f;
   typedef typename Mfma16<H>::V V;
+  S sa, sb;
+  if (t.k > 0) {
+    sa.load(A, asp, ask, t.m, t.k, row0, 0);
+    sb.load(B, bsp, bsk, t.n, t.k, col0, 0);
+  }
+  // staged element (p, k) of the thread's slot (s, u), as in Stage::store
+  auto pos = [&](bool pc, int s, int u, int& p, int& k) {
+    const int e = tid + s * 256;
+    if (pc) { p = (e % (64 / S::VEC)) * S::VEC + u; k = e / (64 / S::VEC); }
+    else { k = (e % (KB / S::VEC)) * S::VEC + u; p = e / (KB / S::VEC); }
+  };
   for (int k0 = 0; k0 < t.k; k0 += KB) {
-    for (int e = tid; e < 64 * KB; e += 256) {
-      int i, kk;
-      if (!t.ta) { i = e & 63; kk = e >> 6; } else { kk = e % KB; i = e / KB; }
-      As[i][kk] = H(load_a(t, A, row0 + i, k0 + kk) * sa);
-      int j, k2;
-      if (!t.tb) { k2 = e % KB; j = e / KB; } else { j = e & 63; k2 = e >> 6; }
-      Bs[j][k2] = H(load_b(t, B, k0 + k2, col0 + j) * sb);
+    float ma = 0.f, mb = 0.f;
+#pragma unroll
+    for (int s = 0; s < S::NV; ++s)
+#pragma unroll
+      for (int u = 0; u < S::VEC; ++u) {
+        ma = fmaxf(ma, fabsf(sa.v[s][u]));
+        mb = fmaxf(mb, fabsf(sb.v[s][u]));
+      }
+    for (int off = 32; off > 0; off >>= 1) {
+      ma = fmaxf(ma, __shfl_xor(ma, off, 64));
+      mb = fmaxf(mb, __shfl_xor(mb, off, 64));
     }
+    if (lane == 0) { red[0][w] = ma; red[1][w] = mb; }
     __syncthreads();
+    const int ea = block_exponent(fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3])));
+    const int eb = block_exponent(fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3])));
+    const bool apc = asp == 1, bpc = bsp == 1;
+#pragma unroll
+    for (int s = 0; s < S::NV; ++s)
+#pragma unroll
+      for (int u = 0; u < S::VEC; ++u) {
+        int p, k;
+        pos(apc, s, u, p, k);
+        As[p][k] = H(ldexpf(sa.v[s][u], -ea));
+        pos(bpc, s, u, p, k);
+        Bs[p][k] = H(ldexpf(sb.v[s][u], -eb));
+      }
+    __syncthreads();
+    if (k0 + KB < t.k) {   // next block in flight during the products
+      sa.load(A, asp, ask, t.m, t.k, row0, k0 + KB);
+      sb.load(B, bsp, bsk, t.n, t.k, col0, k0 + KB);
+    }
+    f32x16 blk;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) blk[v] = 0.f;
 #pragma unroll
     for (int kk = 0; kk < KB; kk += 16) {
       const V a = *reinterpret_cast<const V*>(&As[wr + (lane & 31)][kk + 8 * (lane >> 5)]);
       const V b = *reinterpret_cast<const V*>(&Bs[wc + (lane & 31)][kk + 8 * (lane >> 5)]);
-      acc = Mfma16<H>::run(b, a, acc);
+      blk = Mfma16<H>::run(b, a, blk);
     }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] += ldexpf(blk[v], ea + eb);
     __syncthreads();
   }
-  const double inv = 1.0 / ((double)sa * (double)sb);   // a power of two: exact
 #pragma unroll
   for (int v = 0; v < 16; ++v)
-    store_tile<float>(t, row0, col0, wr + (lane & 31), wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3),
-                      (float)((double)acc[v] * inv));
+    store_tile<float>(t, row0, col0, wr + (lane & 31), wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), acc[v]);
 }
 
 // Segmented GEMM: the inner dimension runs over the task's (A_s, B_s) pairs,
@@ -559,6 +639,12 @@ void launch_gemm_mfma<float>(const GemmTask* d_tasks, const int* d_tile_task, co
     hipLaunchKernelGGL(k_gemm_lowp<_Float16>, dim3(ntiles), dim3(256), 0, s, d_tasks, d_tile_task, d_first_tile);
   else
     hipLaunchKernelGGL(k_gemm_f32, dim3(ntiles), dim3(256), 0, s, d_tasks, d_tile_task, d_first_tile);
+}
+
+void launch_gemm_narrow(const GemmTask* d_tasks, const int* d_tile_task, const int* d_first_tile, int ntiles,
+                        hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_gemm_f32_n32, dim3(ntiles), dim3(256), 0, s, d_tasks, d_tile_task, d_first_tile);
 }
 
 template <>

@@ -272,6 +272,190 @@ __global__ __launch_bounds__(NT) void k_pchol_lds(const PcholTask* __restrict__ 
   if (threadIdx.x == 0) *t.rank_out = rank;
 }
 
+// Pivoted Cholesky with the Gram matrix held in registers and no row or column
+// swaps.  The lower triangle (with the upper halves of the diagonal blocks,
+// kept symmetric) is cut into TB x TB tiles, one per thread, fixed for the
+// whole factorisation.  Step j: the pivot p is the remaining index with the
+// largest diagonal (ties: the lowest position in the order the swap-based
+// kernels produce, tracked in perm / posof); its column scaled by 1 / l_pp,
+// with zeros at indices already eliminated, goes to LDS from the tiles that
+// hold column p (row p left of the diagonal block); every tile then takes the
+// rank-1 update S(i, k) -= l_i l_k (2 TB LDS reads and TB^2 multiply-adds per
+// thread, the same arithmetic as the right-looking update), and the diagonal
+// tiles propose the next pivot.  The columns of L are written in original row
+// order into the Gram buffer, which is not read after the start, and gathered
+// into pivot order at the end: the outputs are those of the swap-based kernels.
+// The columns collect in LDS and go to global memory every kPcholChunk steps:
+// a workgroup barrier waits for the thread's outstanding global stores, so a
+// store per step would put a memory round trip into every step.
+constexpr int kPcholChunk = 32;
+template <int NT, int TB>
+__global__ __launch_bounds__(NT) void k_pchol_reg(const PcholTask* __restrict__ tasks, double tol) {
+  extern __shared__ double spr[];
+  const PcholTask t = tasks[blockIdx.x];
+  const int r = t.r;
+  double* lv = spr;                                // pivot column / l_pp, 0 at eliminated indices
+  double* dpiv = lv + r;                           // diagonal of each pivot when it was taken
+  double* lbuf = dpiv + r;                         // the last kPcholChunk columns of L
+  int* perm = reinterpret_cast<int*>(lbuf + (int64_t)kPcholChunk * r);   // position -> original index
+  int* posof = perm + r;                           // original index -> position
+  int* alive = posof + r;                          // 1 until the index is eliminated
+  constexpr int NW = NT / 64;
+  __shared__ double cand[2][NW];
+  __shared__ int candi[2][NW];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // this thread's tile: block row R >= block column C, tile index R (R + 1) / 2 + C
+  const int nb = (r + TB - 1) / TB;
+  int R = -1, C = -1;
+  if ((int)threadIdx.x < nb * (nb + 1) / 2) {
+    int rr = 0;
+    while ((rr + 1) * (rr + 2) / 2 <= (int)threadIdx.x) ++rr;
+    R = rr;
+    C = (int)threadIdx.x - rr * (rr + 1) / 2;
+  }
+  const int i0 = R * TB, k0 = C * TB;
+  const auto* Gg = to_global(t.G);
+  double v[TB][TB];
+#pragma unroll
+  for (int a = 0; a < TB; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+      const int i = i0 + a, k = k0 + b;
+      v[a][b] = (R >= 0 && i < r && k < r) ? Gg[i + (int64_t)k * r] : 0.0;
+    }
+  for (int x = threadIdx.x; x < r; x += NT) {
+    perm[x] = x;
+    posof[x] = x;
+    alive[x] = 1;
+  }
+  // candidates: value and key position * 512 + original index (positions win ties)
+  double cv = -INFINITY;
+  int ck = 0x7fffffff;
+  if (R >= 0 && R == C) {
+#pragma unroll
+    for (int a = 0; a < TB; ++a) {
+      const int i = i0 + a;
+      if (i < r && v[a][a] > cv) { cv = v[a][a]; ck = i * 512 + i; }
+    }
+  }
+  wave_argmax(cv, ck);
+  if (lane == 0) { cand[0][wave] = cv; candi[0][wave] = ck; }
+  __syncthreads();
+  double mx;
+  {
+    double m = lane < NW ? cand[0][lane] : -INFINITY;
+    int mi = lane < NW ? candi[0][lane] : 0x7fffffff;
+    group_argmax<NW>(m, mi);
+    mx = read_first_lane(m);
+  }
+  const double thr = tol * mx;
+  const bool zero = !(mx > 0.0);
+  // the Gram buffer receives the columns of L in original row order
+  auto* Lo = to_global(const_cast<double*>(t.G));
+  unsigned dead = 0;   // this thread's diagonal entries already eliminated (bit a)
+  int rank = 0;
+  // columns j0 .. j0 + n - 1 of the LDS buffer to global memory
+  auto flush = [&](int j0, int n) {
+    for (int e = threadIdx.x; e < n * r; e += NT) {
+      const int c = e / r, x = e - c * r;
+      Lo[x + (int64_t)(j0 + c) * r] = lbuf[x + (int64_t)c * r];
+    }
+  };
+  for (int j = 0; j < r && !zero; ++j) {
+    if (j > 0 && j % kPcholChunk == 0) flush(j - kPcholChunk, kPcholChunk);
+    double b = lane < NW ? cand[j & 1][lane] : -INFINITY;
+    int bk = lane < NW ? candi[j & 1][lane] : 0x7fffffff;
+    group_argmax<NW>(b, bk);
+    b = read_first_lane(b);
+    bk = __builtin_amdgcn_readfirstlane(bk);
+    if (!(b > thr)) break;
+    const int p = bk & 511, pb = p / TB;
+    const double inv = 1.0 / sqrt(b);   // as 1 / l_pp in the swap-based kernels
+    if (R >= 0 && C == pb) {
+      // column p in the tiles of block column pb (rows at and below the block)
+#pragma unroll
+      for (int a = 0; a < TB; ++a) {
+        const int i = i0 + a;
+        double x = 0.0;
+#pragma unroll
+        for (int c = 0; c < TB; ++c) x = k0 + c == p ? v[a][c] : x;
+        if (i < r) lv[i] = (i == p || alive[i]) ? x * inv : 0.0;
+      }
+    }
+    if (R >= 0 && R == pb && C < R) {
+      // row p in the tiles left of the diagonal block: columns of the blocks before pb
+#pragma unroll
+      for (int c = 0; c < TB; ++c) {
+        const int k = k0 + c;
+        double x = 0.0;
+#pragma unroll
+        for (int a = 0; a < TB; ++a) x = i0 + a == p ? v[a][c] : x;
+        if (k < r) lv[k] = alive[k] ? x * inv : 0.0;
+      }
+    }
+    if (threadIdx.x == 0) {
+      dpiv[p] = b;
+      const int q = posof[p], pj = perm[j];
+      perm[j] = p;
+      perm[q] = pj;
+      posof[p] = j;
+      posof[pj] = q;
+      alive[p] = 0;
+    }
+    __syncthreads();
+    // (the pivot's own entry is l_pp = sqrt(S(p, p)), not S(p, p) / l_pp)
+    const double lpp = sqrt(b);
+    double* lc = lbuf + (int64_t)(j % kPcholChunk) * r;
+    for (int x = threadIdx.x; x < r; x += NT) lc[x] = x == p ? lpp : lv[x];
+    cv = -INFINITY;
+    ck = 0x7fffffff;
+    if (R >= 0) {
+      double li[TB], lk[TB];
+#pragma unroll
+      for (int a = 0; a < TB; ++a) {
+        li[a] = i0 + a < r ? lv[i0 + a] : 0.0;
+        lk[a] = k0 + a < r ? lv[k0 + a] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < TB; ++a)
+#pragma unroll
+        for (int c = 0; c < TB; ++c) v[a][c] -= li[a] * lk[c];
+      if (R == C) {
+#pragma unroll
+        for (int a = 0; a < TB; ++a) {
+          const int i = i0 + a;
+          if (i == p) dead |= 1u << a;
+          if (i < r && !((dead >> a) & 1u)) {
+            const int key = posof[i] * 512 + i;
+            if (v[a][a] > cv || (v[a][a] == cv && key < ck)) { cv = v[a][a]; ck = key; }
+          }
+        }
+      }
+    }
+    wave_argmax(cv, ck);
+    if (lane == 0) { cand[(j + 1) & 1][wave] = cv; candi[(j + 1) & 1][wave] = ck; }
+    __syncthreads();
+    rank = j + 1;
+  }
+  // the columns of the last, partial chunk
+  if (rank > 0) flush((rank - 1) / kPcholChunk * kPcholChunk, rank - (rank - 1) / kPcholChunk * kPcholChunk);
+  __syncthreads();
+  auto* L = to_global(t.L);
+  if (R >= 0 && R == C) {
+#pragma unroll
+    for (int a = 0; a < TB; ++a) {
+      const int i = i0 + a;
+      if (i < r) t.d[i] = alive[i] ? v[a][a] : dpiv[i];
+    }
+  }
+  for (int x = threadIdx.x; x < r; x += NT) t.perm[x] = perm[x];
+  for (int e = threadIdx.x; e < rank * r; e += NT) {
+    const int a = e / r, q = e - a * r;
+    if (q >= a) L[q + (int64_t)a * r] = Lo[perm[q] + (int64_t)a * r];
+  }
+  if (threadIdx.x == 0) *t.rank_out = rank;
+}
+
 __global__ __launch_bounds__(256) void k_materialize_r(const PcholTask* __restrict__ tasks) {
   const PcholTask t = tasks[blockIdx.x];
   const int r = t.r, r1 = t.r1;
@@ -380,6 +564,23 @@ void launch_pchol(const PcholTask* d_tasks, int ntasks, int max_r, double tol, s
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol<1024>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_pchol<1024>, dim3(ntasks), dim3(1024), lds, s, d_tasks, tol);
+}
+
+void launch_pchol_reg(const PcholTask* d_tasks, int ntasks, int max_r, double tol, bool small, hipStream_t s) {
+  if (ntasks <= 0) return;
+  // LDS: the scaled column, the pivot diagonals and kPcholChunk columns of L
+  // (doubles), perm, posof, alive (ints)
+  const size_t lds = (size_t)max_r * ((2 + kPcholChunk) * sizeof(double) + 3 * sizeof(int));
+  if (lds > 64 * 1024) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol_reg<256, 4>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol_reg<1024, 5>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  if (small)
+    hipLaunchKernelGGL((k_pchol_reg<256, 4>), dim3(ntasks), dim3(256), lds, s, d_tasks, tol);
+  else
+    hipLaunchKernelGGL((k_pchol_reg<1024, 5>), dim3(ntasks), dim3(1024), lds, s, d_tasks, tol);
 }
 
 void launch_materialize_r(const PcholTask* d_tasks, int ntasks, hipStream_t s) {

@@ -151,7 +151,11 @@ class Exec {
   size_t fused_lds = 0;        // one-workgroup SVD up to this LDS size (ACR_FUSED_LDS, bytes)
   bool svd_global = false;     // ACR_SVD_GLOBAL=1: every core takes the global-memory two-kernel path
   bool pchol_global = false;   // ACR_PCHOL_GLOBAL=1: every Gram takes the left-looking global-memory kernel
+  bool inverse_unblocked = false;  // ACR_INVERSE_UNBLOCKED=1: unblocked Gauss-Jordan for every inverse
+  bool pchol_lds = false;      // ACR_PCHOL_LDS=1: the right-looking LDS kernel instead of the register-tiled one
+  bool gemm_narrow = true;     // ACR_GEMM_NARROW=0: FP32 outputs <= 32 columns wide in 64 x 64 tiles too
   int leaf_lowp = 0;           // leaf x leaf products with 16-bit inputs: 1 = BF16, 2 = FP16 (FP32 data)
+  int prod_lowp = 0;           // every factorisation product without its own choice, as leaf_lowp
   const char* trace_tag = "";
   void check_range(const void* p, size_t bytes, const char* what) const;
 

@@ -224,8 +224,11 @@ void compress_gram(Exec& ex, std::vector<CJob<T>*>& live, double eps, int max_ra
       wt.push_back(WtTask{pv.L, pv.perm, Yw[i] + (size_t)q * q, q, Wv[i], r, q, k});
       o.U = out.get_n<T>((size_t)j.m * k);
       o.V = out.get_n<T>((size_t)j.n * k);
+      // the truncated factors are rebuilt in FP32 in every precision variant
       gg.push_back(gt<T>(j.Us, j.m, 0, Wu[i], r, 0, o.U, j.m, j.m, k, r, 1.0, 0.0));
+      gg.back().lowp = -1;
       gg.push_back(gt<T>(j.Vs, j.n, 0, Wv[i], r, 0, o.V, j.n, j.n, k, r, 1.0, 0.0));
+      gg.back().lowp = -1;
     }
     *j.out = o;
   }

@@ -19,7 +19,8 @@ struct GemmTask {
   int m, n, k;
   int ta, tb;
   double alpha, beta;
-  int lowp;   // FP32 data only: 1 = BF16, 2 = FP16 matrix-core inputs with panel scaling
+  int lowp;   // FP32 data only: 1 = BF16, 2 = FP16 matrix-core inputs with block scaling; 0 = the
+              // launch's default (Exec::prod_lowp), -1 = always FP32
 };
 
 // C = alpha * sum_s op_s(A_s) B_s + beta * C: one output block with the inner
@@ -180,12 +181,17 @@ enum : int { FLAG_SINGULAR = 0, FLAG_RANK = 1, FLAG_NONFINITE = 2, FLAG_INVALID 
 // variant for FP32 data (0 = FP32 / FP64 inputs)
 template <class T> void launch_gemm_mfma(const GemmTask* d_tasks, const int* d_tile_task, const int* d_first_tile,
                                          int ntiles, int lowp, hipStream_t s);
+// FP32 GEMM in 128 x 32 output tiles for outputs at most 32 columns wide
+// (tile map: ceil(m / 128) tiles per task)
+void launch_gemm_narrow(const GemmTask* d_tasks, const int* d_tile_task, const int* d_first_tile, int ntiles,
+                        hipStream_t s);
 template <class T> void launch_seg_gemm(const SegGemmTask* d_tasks, const int* d_tile_task, const int* d_first_tile,
                                         int ntiles, hipStream_t s);
 // units: workgroups per task (each takes (column, 2048-row chunk) units in turn)
 template <class T> void launch_copy(const CopyTask* d_tasks, int ntasks, int units, hipStream_t s);
+// unblocked = true forces the unblocked Gauss-Jordan kernel
 template <class T> void launch_inverse(const InvTask* d_tasks, int ntasks, int max_s,
-                                       int* d_flags, hipStream_t s);
+                                       int* d_flags, hipStream_t s, bool unblocked);
 // LDS-resident variants; `lds` is the dynamic shared memory per workgroup
 template <class T> void launch_qr_lds(const QrTask* d_tasks, int ntasks, size_t lds, hipStream_t s);
 template <class T> void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, hipStream_t s);
@@ -212,6 +218,13 @@ template <class T> void launch_gram_mfma(const GramTask* d_tasks, const int* d_t
 // = max over the tasks of lds_bytes_pchol_packed); 0: left-looking with L in
 // global memory (max_r bounds the tasks' orders)
 void launch_pchol(const PcholTask* d_tasks, int ntasks, int max_r, double tol, size_t lds_packed, hipStream_t s);
+// register-tiled pivoted Cholesky (no swaps): orders up to kPcholRegSmall in
+// 256-thread workgroups (4 x 4 tiles), up to kPcholReg in 1024-thread ones
+// (5 x 5 tiles); overwrites the tasks' Gram buffers (the columns of L in
+// original row order)
+constexpr int kPcholRegSmall = 88;
+constexpr int kPcholReg = 220;
+void launch_pchol_reg(const PcholTask* d_tasks, int ntasks, int max_r, double tol, bool small, hipStream_t s);
 void launch_materialize_r(const PcholTask* d_tasks, int ntasks, hipStream_t s);
 template <class T> void launch_wtilde(const WtTask* d_tasks, int ntasks, int kc, int nchunks, size_t lds,
                                       hipStream_t s);

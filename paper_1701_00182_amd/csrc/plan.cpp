@@ -79,9 +79,10 @@ bool options_valid(const acr_options_t* o) {
   if (o->nx < 1 || o->ny < 1 || o->nplanes < 1 || o->leaf < 1) return false;
   if (!(o->eps >= 0.0) || !std::isfinite(o->eps)) return false;
   if (o->max_rank < 0) return false;
-  if (o->precision < ACR_PREC_FP64 || o->precision > ACR_PREC_FP32_FP16LEAF) return false;
+  if (o->precision < ACR_PREC_FP64 || o->precision > ACR_PREC_FP32_FP16) return false;
   if ((o->alloc == nullptr) != (o->release == nullptr)) return false;
   if (!(o->inner_eps_ratio >= 0.0) || !std::isfinite(o->inner_eps_ratio)) return false;
+  if (o->stencil_points != 0 && o->stencil_points != 7 && o->stencil_points != 27) return false;
   if ((int64_t)o->nx * o->ny > (int64_t)1 << 28) return false;
   if ((int64_t)o->nx * o->ny * o->nplanes > (int64_t)1 << 34) return false;
   return true;

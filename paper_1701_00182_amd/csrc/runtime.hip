@@ -276,6 +276,12 @@ void Exec::init(hipStream_t s, const Allocator& a) {
   svd_global = sg && sg[0] == '1';
   const char* pg = std::getenv("ACR_PCHOL_GLOBAL");
   pchol_global = pg && pg[0] == '1';
+  const char* pl = std::getenv("ACR_PCHOL_LDS");
+  pchol_lds = pl && pl[0] == '1';
+  const char* iu = std::getenv("ACR_INVERSE_UNBLOCKED");
+  inverse_unblocked = iu && iu[0] == '1';
+  const char* gn = std::getenv("ACR_GEMM_NARROW");
+  gemm_narrow = !(gn && gn[0] == '0');
   stream = s;
   al = a;
   ring_bytes_ = size_t(64) << 20;
@@ -478,16 +484,18 @@ template <class T> void Exec::gemm(const std::vector<GemmTask>& t) {
       if ((x.tb ? x.ldb < x.n : x.ldb < x.k) && x.n * x.k > 0) throw Failure(ST_HIP, "bounds check: gemm ldb");
       if (x.ldc < x.m && x.m * x.n > 0) throw Failure(ST_HIP, "bounds check: gemm ldc");
     }
-  // one launch per input kind: native-precision matrix cores, or 16-bit inputs
-  for (int mode = 0; mode < 3; ++mode) {
+  // one launch per input kind: native-precision matrix cores, or 16-bit
+  // inputs; FP32 outputs at most 32 columns wide in a launch of 128 x 32 tiles
+  for (int mode = 0; mode < 4; ++mode) {
     std::vector<int> first, tile_task;
     std::vector<GemmTask> sel;
     int nt = 0;
     for (const GemmTask& x : t) {
-      const int m = (sizeof(T) == 4) ? x.lowp : 0;
+      int m = (sizeof(T) != 4 || x.lowp < 0) ? 0 : (x.lowp > 0 ? x.lowp : prod_lowp);
+      if (m == 0 && sizeof(T) == 4 && gemm_narrow && x.n <= 32) m = 3;
       if (m != mode) continue;
       first.push_back(nt);
-      const int tiles = ((x.m + 63) / 64) * ((x.n + 63) / 64);
+      const int tiles = mode == 3 ? (x.m + 127) / 128 : ((x.m + 63) / 64) * ((x.n + 63) / 64);
       for (int j = 0; j < tiles; ++j) tile_task.push_back((int)sel.size());
       nt += tiles;
       sel.push_back(x);
@@ -495,7 +503,7 @@ template <class T> void Exec::gemm(const std::vector<GemmTask>& t) {
     }
     if (nt == 0) continue;
     Work w;
-    w.cls = mode == 0 ? "gemm" : (mode == 1 ? "gemm_bf16" : "gemm_f16");
+    w.cls = (mode == 0 || mode == 3) ? "gemm" : (mode == 1 ? "gemm_bf16" : "gemm_f16");
     for (auto& x : sel) {
       w.flops += 2.0 * x.m * x.n * (double)x.k;
       w.bytes += sizeof(T) * ((double)x.m * x.k + (double)x.k * x.n + (double)x.m * x.n * (x.beta != 0.0 ? 2 : 1));
@@ -503,7 +511,10 @@ template <class T> void Exec::gemm(const std::vector<GemmTask>& t) {
     const GemmTask* dt = upload(sel);
     const int* dtt = upload(tile_task);
     const int* dft = upload(first);
-    submit([=](hipStream_t s) { launch_gemm_mfma<T>(dt, dtt, dft, nt, mode, s); }, w);
+    if (mode == 3)
+      submit([=](hipStream_t s) { launch_gemm_narrow(dt, dtt, dft, nt, s); }, w);
+    else
+      submit([=](hipStream_t s) { launch_gemm_mfma<T>(dt, dtt, dft, nt, mode, s); }, w);
   }
 }
 
@@ -592,7 +603,8 @@ template <class T> void Exec::inverse(const std::vector<InvTask>& t) {
   const InvTask* dt = upload(t);
   const int n = (int)t.size();
   int* fl = d_flags;
-  submit([=](hipStream_t s) { launch_inverse<T>(dt, n, mx, fl, s); }, w);
+  const bool ub = inverse_unblocked;
+  submit([=](hipStream_t s) { launch_inverse<T>(dt, n, mx, fl, s, ub); }, w);
 }
 
 template <class T> void Exec::qr(const std::vector<QrTask>& t) {
@@ -888,19 +900,37 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
     check_range(x.rank_out, sizeof(int), "pchol rank");
     flops_qr += (double)x.r * x.r * x.r / 3.0;
   }
-  // Gram matrices whose packed lower triangle fits in LDS take the right-
-  // looking kernel (two launches at most: finer LDS-size buckets serialise
-  // the batch and measured slower), wider ones the left-looking one with L in
-  // global memory
-  std::vector<PcholTask> packed, wide;
+  // Gram matrices of order up to kPcholReg take the register-tiled kernel
+  // (ACR_PCHOL_LDS=1: those whose packed lower triangle fits in LDS take the
+  // right-looking LDS kernel instead), wider ones the left-looking one with L
+  // in global memory; two launches at most per kind (finer size buckets
+  // serialise the batch)
+  std::vector<PcholTask> packed, wide, reg_small, reg_large;
   int max_r = 1;
   for (auto& x : t) {
-    if (!pchol_global && lds_bytes_pchol_packed(x.r) <= kLdsBudget) {
+    if (!pchol_global && pchol_lds && lds_bytes_pchol_packed(x.r) <= kLdsBudget) {
       packed.push_back(x);
+    } else if (!pchol_global && x.r <= kPcholReg) {
+      (x.r <= kPcholRegSmall ? reg_small : reg_large).push_back(x);
     } else {
       wide.push_back(x);
       max_r = std::max(max_r, x.r);
     }
+  }
+  for (auto* b : {&reg_small, &reg_large}) {
+    if (b->empty()) continue;
+    Work w;
+    w.cls = "pchol";
+    for (auto& x : *b) {
+      w.flops += (double)x.r * x.r * x.r / 3.0;
+      w.bytes += 16.0 * x.r * x.r;
+    }
+    const PcholTask* dt = upload(*b);
+    const int n = (int)b->size();
+    const bool small_kind = b == &reg_small;
+    int rmax = 1;
+    for (auto& x : *b) rmax = std::max(rmax, x.r);
+    submit([=](hipStream_t s) { launch_pchol_reg(dt, n, rmax, tol, small_kind, s); }, w);
   }
   if ((size_t)max_r * (sizeof(double) + sizeof(int)) > kLdsBudget)
     throw Failure(ST_NOT_SUPPORTED, "stack too wide for the pivoted Cholesky kernel");

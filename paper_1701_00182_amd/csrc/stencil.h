@@ -9,6 +9,7 @@ namespace acr {
 
 struct Grid {
   int nx, ny, nz;
+  int ns = 7;   // stencil slots: 7, or 27 (slot 9 (dz+1) + 3 (dy+1) + (dx+1) for the offset (dx, dy, dz))
   __host__ __device__ int64_t M() const { return (int64_t)nx * ny; }
   __host__ __device__ int64_t N() const { return M() * nz; }
 };
@@ -17,6 +18,10 @@ struct Grid {
 struct LeafEnt { int leaf, a, b, n, slot, nat; };
 // Entry coupling two sibling clusters (the exact low-rank cut couplings).
 struct CutEnt { int r, c, slot, nat; };
+// Entry of a 9-point plane operator coupling two sibling clusters, in the
+// exact factors U (rows x k, a selection) and V (cols x k, the couplings):
+// column j of block `blk` selects row r and holds the coupling to column c.
+struct Cut9Ent { int blk, j, r, c, slot, nat; };
 
 void launch_validate(Grid g, const double* coef, int* flags, hipStream_t s);
 template <class T>
@@ -29,6 +34,12 @@ void launch_cut_fill(Grid g, const double* coef, const CutEnt* ents, const int* 
                      T* const* uptr, T* const* vptr, const int* rows, const int* cols, hipStream_t s);
 template <class T>
 void launch_diag(Grid g, const double* coef, int slot, const int* perm, T* out, hipStream_t s);
+// exact factors of the cut couplings of 9-point plane operators: for every
+// plane k and entry e, U[k][blk][r + j rows] = 1, V[k][blk][c + j cols] = coef
+// (U, V zeroed before; null pointers are skipped)
+template <class T>
+void launch_cut9_fill(Grid g, const double* coef, const Cut9Ent* ents, int nent, int nblk, T* const* uptr,
+                      T* const* vptr, const int* rows, const int* cols, hipStream_t s);
 // W[k][c][pos] = b[k*M + perm[pos] + c*ldb]  (and the inverse)
 template <class T>
 void launch_perm_in(Grid g, int nrhs, const double* b, int64_t ldb, const int* perm, T* W, hipStream_t s);

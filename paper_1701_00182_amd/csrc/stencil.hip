@@ -33,6 +33,25 @@ __global__ void k_validate(Grid g, const double* __restrict__ coef, int* flags) 
   }
 }
 
+// 27-point validation: entries reaching outside the grid must be zero
+__global__ void k_validate27(Grid g, const double* __restrict__ coef, int* flags) {
+  const int64_t N = g.N();
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
+    int i, j, k;
+    grid_ijk(g, r, i, j, k);
+    bool nonfinite = false, invalid = false;
+    for (int s = 0; s < 27; ++s) {
+      const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+      const bool out = i + dx < 0 || i + dx >= g.nx || j + dy < 0 || j + dy >= g.ny || k + dz < 0 || k + dz >= g.nz;
+      const double v = coef[s * N + r];
+      if (!isfinite(v)) nonfinite = true;
+      if (out && v != 0.0) invalid = true;
+    }
+    if (nonfinite) atomicOr(&flags[FLAG_NONFINITE], 1);
+    if (invalid) atomicOr(&flags[FLAG_INVALID], 1);
+  }
+}
+
 template <class T>
 __global__ void k_conv_leaves(Grid g, const double* __restrict__ coef, const LeafEnt* __restrict__ ents, int nent,
                               T* const* __restrict__ leafptr, int nleaf) {
@@ -40,8 +59,26 @@ __global__ void k_conv_leaves(Grid g, const double* __restrict__ coef, const Lea
   const int k = blockIdx.y;
   if (e >= nent) return;
   const LeafEnt en = ents[e];
+  T* lp = leafptr[(int64_t)k * nleaf + en.leaf];
+  if (!lp) return;   // absent block of this plane
   const double v = coef[en.slot * g.N() + (int64_t)k * g.M() + en.nat];
-  leafptr[(int64_t)k * nleaf + en.leaf][en.a + (int64_t)en.b * en.n] = T(v);
+  lp[en.a + (int64_t)en.b * en.n] = T(v);
+}
+
+template <class T>
+__global__ void k_cut9_fill(Grid g, const double* __restrict__ coef, const Cut9Ent* __restrict__ ents, int nent,
+                            int nblk, T* const* __restrict__ uptr, T* const* __restrict__ vptr,
+                            const int* __restrict__ rows, const int* __restrict__ cols) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (e >= nent) return;
+  const Cut9Ent en = ents[e];
+  T* U = uptr[(int64_t)k * nblk + en.blk];
+  T* V = vptr[(int64_t)k * nblk + en.blk];
+  if (!U || !V) return;
+  // entries sharing a column select the same row: equal writes
+  U[en.r + (int64_t)en.j * rows[en.blk]] = T(1);
+  V[en.c + (int64_t)en.j * cols[en.blk]] = T(coef[en.slot * g.N() + (int64_t)k * g.M() + en.nat]);
 }
 
 __global__ void k_cut_rank(Grid g, const double* __restrict__ coef, const CutEnt* __restrict__ ents,
@@ -131,6 +168,26 @@ __global__ void k_residual(Grid g, const double* __restrict__ coef, const double
       if (!in[s]) continue;
       const int64_t nb = e + off[s];
       const double a = transpose ? coef[tslot[s] * N + nb] : coef[s * N + e];
+      acc += a * x[nb];
+    }
+    r[e] = b[e] - acc;
+  }
+}
+
+// r = b - A x for a 27-point stencil; the transpose reads, for the neighbour
+// q = r + o(s), the slot of q whose offset points back to r (26 - s)
+__global__ void k_residual27(Grid g, const double* __restrict__ coef, const double* __restrict__ x,
+                             const double* __restrict__ b, double* r, int transpose) {
+  const int64_t N = g.N(), M = g.M();
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += (int64_t)gridDim.x * blockDim.x) {
+    int i, j, k;
+    grid_ijk(g, e, i, j, k);
+    double acc = 0.0;
+    for (int s = 0; s < 27; ++s) {
+      const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+      if (i + dx < 0 || i + dx >= g.nx || j + dy < 0 || j + dy >= g.ny || k + dz < 0 || k + dz >= g.nz) continue;
+      const int64_t nb = e + dx + (int64_t)dy * g.nx + (int64_t)dz * M;
+      const double a = transpose ? coef[(26 - s) * N + nb] : coef[s * N + e];
       acc += a * x[nb];
     }
     r[e] = b[e] - acc;
@@ -250,7 +307,18 @@ inline int nblocks_for(int64_t n) {
 }  // namespace
 
 void launch_validate(Grid g, const double* coef, int* flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_validate, dim3(nblocks_for(g.N())), dim3(256), 0, s, g, coef, flags);
+  if (g.ns == 27)
+    hipLaunchKernelGGL(k_validate27, dim3(nblocks_for(g.N())), dim3(256), 0, s, g, coef, flags);
+  else
+    hipLaunchKernelGGL(k_validate, dim3(nblocks_for(g.N())), dim3(256), 0, s, g, coef, flags);
+}
+
+template <class T>
+void launch_cut9_fill(Grid g, const double* coef, const Cut9Ent* ents, int nent, int nblk, T* const* uptr,
+                      T* const* vptr, const int* rows, const int* cols, hipStream_t s) {
+  if (nent == 0) return;
+  hipLaunchKernelGGL(k_cut9_fill<T>, dim3((nent + 255) / 256, g.nz), dim3(256), 0, s, g, coef, ents, nent, nblk,
+                     uptr, vptr, rows, cols);
 }
 
 template <class T>
@@ -292,7 +360,10 @@ void launch_perm_out(Grid g, int nrhs, const T* W, const int* perm, double* x, i
 
 void launch_residual(Grid g, const double* coef, const double* x, const double* b, double* r, int transpose,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(nblocks_for(g.N())), dim3(256), 0, s, g, coef, x, b, r, transpose);
+  if (g.ns == 27)
+    hipLaunchKernelGGL(k_residual27, dim3(nblocks_for(g.N())), dim3(256), 0, s, g, coef, x, b, r, transpose);
+  else
+    hipLaunchKernelGGL(k_residual, dim3(nblocks_for(g.N())), dim3(256), 0, s, g, coef, x, b, r, transpose);
 }
 
 void launch_multidot(int64_t n, int nvec, const double* X, int64_t ldx, const double* y, double* part, int nblocks,
@@ -333,6 +404,8 @@ void launch_kappa_grad(Grid g, const double* kappa, const double* u, const doubl
   template void launch_cut_fill<T>(Grid, const double*, const CutEnt*, const int*, int, double, T* const*,      \
                                    T* const*, const int*, const int*, hipStream_t);                            \
   template void launch_diag<T>(Grid, const double*, int, const int*, T*, hipStream_t);                          \
+  template void launch_cut9_fill<T>(Grid, const double*, const Cut9Ent*, int, int, T* const*, T* const*,        \
+                                    const int*, const int*, hipStream_t);                                       \
   template void launch_perm_in<T>(Grid, int, const double*, int64_t, const int*, T*, hipStream_t);             \
   template void launch_perm_out<T>(Grid, int, const T*, const int*, double*, int64_t, hipStream_t);
 ACR_ST_INST(float)

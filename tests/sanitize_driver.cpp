@@ -50,7 +50,10 @@ int main() {
   o = base(); o.eps = nan; EXPECT(!options_valid(&o));
   o = base(); o.eps = inf; EXPECT(!options_valid(&o));
   o = base(); o.max_rank = -1; EXPECT(!options_valid(&o));
-  o = base(); o.precision = 4; EXPECT(!options_valid(&o));
+  o = base(); o.precision = 6; EXPECT(!options_valid(&o));
+  o = base(); o.precision = 5; EXPECT(options_valid(&o));
+  o = base(); o.stencil_points = 9; EXPECT(!options_valid(&o));
+  o = base(); o.stencil_points = 27; EXPECT(options_valid(&o));
   o = base(); o.precision = -1; EXPECT(!options_valid(&o));
   o = base(); o.inner_eps_ratio = nan; EXPECT(!options_valid(&o));
   o = base(); o.inner_eps_ratio = -1.0; EXPECT(!options_valid(&o));

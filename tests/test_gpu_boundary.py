@@ -203,3 +203,40 @@ def test_factor_and_solve_bitwise_deterministic(precision, eps):
     assert torch.equal(out[0][1], out[1][1])
     for k in ("max_rank", "avg_rank", "factor_bytes", "flops_gemm", "flops_svd"):
         assert out[0][2][k] == out[1][2][k], k
+
+
+def test_narrow_gemm_tiles_bitwise_equal(monkeypatch):
+    """FP32 products with outputs at most 32 columns wide run in 128 x 32 tiles;
+    the K loop accumulates in the same order as the 64 x 64 tiles, so the
+    factorisation and its solve are bitwise equal with the narrow kernel
+    switched off (ACR_GEMM_NARROW=0)."""
+    n, leaf = 24, 128
+    coef = torch.from_numpy(problem("convdiff", n)).to(DEV)
+    b = torch.from_numpy(rhs_normal(n ** 3)).to(DEV)
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("ACR_GEMM_NARROW", flag)
+        fac = acr.Factor(coef, eps=1e-2, leaf=leaf, precision="fp32")
+        out.append((fac.solve(b), fac.stats()))
+        fac.free()
+    torch.cuda.synchronize()
+    assert torch.equal(out[0][0], out[1][0])
+    assert out[0][1]["max_rank"] == out[1][1]["max_rank"]
+
+
+@pytest.mark.parametrize("n,leaf,eps", [(24, 128, 1e-2), (32, 64, 1e-4), (16, 32, 1e-3)])
+def test_register_pchol_bitwise_equals_lds_kernel(n, leaf, eps, monkeypatch):
+    """The register-tiled pivoted Cholesky (no swaps) takes the same pivots and
+    does the same arithmetic per element as the right-looking LDS kernel
+    (ACR_PCHOL_LDS=1), so the factorisation and its solve are bitwise equal."""
+    coef = torch.from_numpy(problem("convdiff", n)).to(DEV)
+    b = torch.from_numpy(rhs_normal(n ** 3)).to(DEV)
+    out = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("ACR_PCHOL_LDS", flag)
+        fac = acr.Factor(coef, eps=eps, leaf=leaf, precision="fp32")
+        out.append((fac.solve(b), fac.stats()))
+        fac.free()
+    torch.cuda.synchronize()
+    assert out[0][1]["max_rank"] == out[1][1]["max_rank"]
+    assert torch.equal(out[0][0], out[1][0])

@@ -202,3 +202,79 @@ def test_helmholtz_vs_oracle(n):
     assert rg <= 1.5 * ro
     _check_truncated(c, x, fac, f"helmholtz n={n} eps=1e-3")
     fac.free()
+
+
+@pytest.mark.parametrize("precision", ["fp32_bf16", "fp32_fp16"])
+@pytest.mark.parametrize("eps", [1e-2, 1e-4])
+def test_16bit_products_vs_oracle(precision, eps):
+    """Every block product of the factorisation on 16-bit matrix-core inputs
+    (per-K-block power-of-two scaling, FP32 accumulation): convection-diffusion
+    n = 24, leaf 128.  The 16-bit rounding (unit roundoff u = 2^-8 for BF16,
+    2^-11 for FP16) adds to the truncation error, so the bounds of the FP32
+    test are widened by u: every plane within 4 (E_o + u max|x*|) of the
+    oracle, the unrefined residual within 2 (relres_oracle + u), and FP64
+    GMRES still reaches 1e-10."""
+    u = 2.0 ** -8 if precision == "fp32_bf16" else 2.0 ** -11
+    print(f"case 16-bit products {precision} eps={eps}", flush=True)
+    c = _case("convdiff", 24, 128, eps)
+    fac = _gpu(c.coef, eps=eps, leaf=128, precision=precision, svd_fused_lds=-1)
+    x = _solve(fac, c.f)
+    dp = _plane_maxabs(x - c.xo, c.n)
+    rg, ro = float(relres(c.A, x, c.f)), float(relres(c.A, c.xo, c.f))
+    print(f"{precision} eps={eps}: max plane |x-xo| / (E_o + u max|x*|) = "
+          f"{dp.max() / (c.E_o + u * np.abs(c.xs).max()):.3f}; relres gpu {rg:.3e} oracle {ro:.3e}", flush=True)
+    assert np.all(dp <= C_PLANE * (c.E_o + u * np.abs(c.xs).max()))
+    assert rg <= 2.0 * (ro + u)
+    b = torch.from_numpy(c.f).to(DEV)
+    xr, info = fac.solve_refined(b, tol=1e-10, method="gmres", maxit=300)
+    assert info["converged"] and float(relres(c.A, xr.cpu().numpy(), c.f)) <= 1.01e-10
+    fac.free()
+
+
+@pytest.mark.parametrize("path", ["blocked", "unblocked"])
+@pytest.mark.parametrize("n,leaf,precision", [(16, 256, "fp64"), (12, 144, "fp64"), (12, 144, "fp32"),
+                                              (16, 32, "fp64"), (10, 100, "fp32"), (9, 81, "fp64")])
+def test_inverse_paths_exact_mode(n, leaf, precision, path, monkeypatch):
+    """Exact mode (eps = 0) with large leaves, so that the dense leaf inverses
+    take every Gauss-Jordan path: blocked with the matrix in LDS (FP32 up to
+    183, FP64 up to 133 rows), blocked with the matrix in global memory (a
+    256 x 256 or 144 x 144 FP64 leaf), and the unblocked kernel
+    (ACR_INVERSE_UNBLOCKED=1).  FP64: every plane within 1e-10 max|x| of the
+    oracle; FP32: the 2-norm difference within 10 kappa(A) 2^-24."""
+    print(f"case inverse {path} n={n} leaf={leaf} {precision}", flush=True)
+    if path == "unblocked":
+        monkeypatch.setenv("ACR_INVERSE_UNBLOCKED", "1")
+    coef = problem("convdiff", n)
+    f = rhs_normal(n ** 3, nrhs=2)
+    fac = _gpu(coef, eps=0.0, leaf=leaf, precision=precision)
+    x = _solve(fac, f)
+    xo = OracleACR(coef, leaf, 0.0).solve(f)
+    if precision == "fp64":
+        for j in range(2):
+            dp = _plane_maxabs(x[:, j] - xo[:, j], n)
+            assert np.all(dp <= 1e-10 * np.abs(xo[:, j]).max()), dp.max()
+    else:
+        kappa = np.linalg.cond(operator_from_coef(coef).toarray())
+        assert np.linalg.norm(x - xo) <= 10 * kappa * 2.0 ** -24 * np.linalg.norm(xo)
+    fac.free()
+
+
+@pytest.mark.parametrize("n,leaf", [(12, 144), (16, 32), (24, 128)])
+def test_blocked_inverse_fp32_as_accurate_as_unblocked(n, leaf, monkeypatch):
+    """FP32 factors in exact mode: the blocked Gauss-Jordan inverse is held to
+    the unblocked kernel's accuracy, ||x_blocked - x*|| <= 2 ||x_unblocked - x*||
+    with x* from a sparse LU.  (Forming the panel rows of the deferred update
+    as C + (T_P - I) C cancels nearly all of C when the pivots are large; that
+    form measured 40x the unblocked error on a 128-point leaf.)"""
+    print(f"case blocked vs unblocked fp32 n={n} leaf={leaf}", flush=True)
+    coef = problem("convdiff", n)
+    f = rhs_normal(n ** 3)
+    xs = spla.splu(operator_from_coef(coef).tocsc()).solve(f)
+    err = {}
+    for path in ("blocked", "unblocked"):
+        monkeypatch.setenv("ACR_INVERSE_UNBLOCKED", "1" if path == "unblocked" else "0")
+        fac = _gpu(coef, eps=0.0, leaf=leaf, precision="fp32")
+        err[path] = np.linalg.norm(_solve(fac, f) - xs) / np.linalg.norm(xs)
+        fac.free()
+    print(f"relative error blocked {err['blocked']:.3e} unblocked {err['unblocked']:.3e}", flush=True)
+    assert err["blocked"] <= 2.0 * err["unblocked"]
