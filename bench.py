@@ -198,7 +198,7 @@ def run_form(acr, coef_d, b, args, precision, timed_steps, warmup):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         fac = acr.Factor(coef_d, eps=args.eps, leaf=args.leaf, precision=precision,
-                         svd_fused_lds=args.svd_fused_lds)
+                         svd_fused_lds=args.svd_fused_lds, gemm_tiles=args.gemm_tiles)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         x, info = fac.solve_refined(b, tol=args.tol, method="gmres", restart=30, maxit=300)
@@ -276,8 +276,9 @@ def headline(args, torch, acr):
         tune = acr.autotune(coef_d, eps=args.eps, precision=args.precision, leaf=args.leaf,
                             sample_planes=args.tune_planes)
         tune["tuning_s"] = time.perf_counter() - t0
-        args.leaf, args.svd_fused_lds = tune["leaf"], tune["svd_fused_lds"]
-        log(f"autotune: leaf {args.leaf}, svd_fused_lds {args.svd_fused_lds} ({tune['tuning_s']:.1f} s)")
+        args.leaf, args.svd_fused_lds, args.gemm_tiles = tune["leaf"], tune["svd_fused_lds"], tune["gemm_tiles"]
+        log(f"autotune: leaf {args.leaf}, svd_fused_lds {args.svd_fused_lds}, gemm_tiles {args.gemm_tiles} "
+            f"({tune['tuning_s']:.1f} s)")
     log("warmup")
     run_form(acr, coef_d, b, args, args.precision, 0, args.warmup)
     # timed steps; the factorisation kernels carry HIP events on their stream
@@ -304,6 +305,7 @@ def headline(args, torch, acr):
                                f"velocity at cell Peclet 1, eps={args.eps}, HODLR leaf {args.leaf}, "
                                f"{args.precision.upper()} factors + FP64 GMRES(30) to {args.tol:g}",
                    "n": n, "N": N, "eps": args.eps, "leaf": args.leaf, "svd_fused_lds": args.svd_fused_lds,
+                   "gemm_tiles": args.gemm_tiles,
                    "autotune": tune, "precision": args.precision, "refinement": "fp64 gmres(30)",
                    "tol": args.tol},
         "value_definition": "N / (t_factor + t_solve) for one step (whole job, inputs resident)",
@@ -788,6 +790,8 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--leaf", type=int, default=128, help="leaf size (also one of the autotuner's candidates)")
     ap.add_argument("--svd-fused-lds", type=int, default=-1, help="core-SVD dispatch (acr_options_t.svd_fused_lds)")
+    ap.add_argument("--gemm-tiles", type=int, default=0, help="acr_options_t.gemm_tiles (0: 128 x 32 tiles for "
+                                                              "narrow outputs, 1: 64 x 64 only)")
     ap.add_argument("--autotune", action="store_true", help="pick --leaf / --svd-fused-lds with acr_autotune")
     ap.add_argument("--no-autotune", action="store_true", help="use --leaf / --svd-fused-lds as given (default)")
     ap.add_argument("--summarize-pmc", metavar="DIR",

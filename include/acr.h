@@ -86,6 +86,9 @@ typedef struct {
                              /* workgroup; 0 = default (none), < 0 = never; capped at the     */
                              /* LDS budget.  Tuned by acr_autotune.                            */
   int32_t stencil_points;    /* layout of coef: 7 (0 -> 7) or 27, see acr_factor              */
+  int32_t gemm_tiles;        /* matrix-core tiles of FP32 products whose output is at most 32 */
+                             /* columns wide: 0 = 128 x 32 tiles, 1 = 64 x 64 tiles (as wider */
+                             /* outputs).  Tuned by acr_autotune.                              */
 } acr_options_t;
 
 /* Fills defaults: eps 1e-6, leaf 64, FP64, no rank cap, no allocator, default SVD
@@ -284,6 +287,8 @@ acr_status_t acr_get_structure(acr_handle_t h, acr_structure_t* info, int32_t* p
  * (the cost of a refined solve), and returns the fastest pair, trying them in
  * the order listed: a later pair replaces the current choice only when at
  * least 3% faster, so timing noise does not flip between equivalent ones.
+ * At the chosen pair it then times gemm_tiles = 1 against 0 (the matrix-core
+ * tile shape of narrow products) under the same 3% rule.
  * All other
  * options are taken from opt.  coef: DEVICE, as for acr_factor (read only).
  * cache_path (may be NULL): a text file of one result per line keyed by
@@ -299,6 +304,7 @@ typedef struct {
   double seconds;          /* sample factorisation + 16 solves with that choice  */
   int32_t tried;           /* candidates measured (0 when read from the cache)   */
   int32_t from_cache;      /* 1 if the result came from cache_path                */
+  int32_t gemm_tiles;      /* chosen acr_options_t.gemm_tiles                      */
 } acr_tune_result_t;
 acr_status_t acr_autotune(const acr_options_t* opt, const double* coef, int32_t sample_planes,
                           const char* cache_path, hipStream_t stream, acr_tune_result_t* out);

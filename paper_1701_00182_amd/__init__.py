@@ -35,12 +35,13 @@ class Options(ctypes.Structure):
                 ("eps", ctypes.c_double), ("leaf", ctypes.c_int32), ("max_rank", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_eps_ratio", ctypes.c_double),
                 ("alloc", ctypes.c_void_p), ("release", ctypes.c_void_p), ("alloc_ctx", ctypes.c_void_p),
-                ("svd_fused_lds", ctypes.c_int32), ("stencil_points", ctypes.c_int32)]
+                ("svd_fused_lds", ctypes.c_int32), ("stencil_points", ctypes.c_int32),
+                ("gemm_tiles", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int32), ("svd_fused_lds", ctypes.c_int32), ("seconds", ctypes.c_double),
-                ("tried", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
+                ("tried", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("gemm_tiles", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -176,7 +177,7 @@ class Factor:
     27-point one given as coef[27, nz, ny, nx] (FP64, CUDA)."""
 
     def __init__(self, coef, eps=1e-6, leaf=64, precision="fp64", max_rank=0, inner_eps_ratio=1.0,
-                 svd_fused_lds=0):
+                 svd_fused_lds=0, gemm_tiles=0):
         L = lib()
         if coef.dim() != 4 or coef.shape[0] not in (7, 27):
             raise ValueError("coef must be shaped (7, nz, ny, nx) or (27, nz, ny, nx)")
@@ -190,6 +191,7 @@ class Factor:
         o.inner_eps_ratio = float(inner_eps_ratio)
         o.svd_fused_lds = int(svd_fused_lds)
         o.stencil_points = ns
+        o.gemm_tiles = int(gemm_tiles)
         h = ctypes.c_void_p()
         _check(L.acr_factor(ctypes.byref(o), ctypes.c_void_p(coef.data_ptr()), _stream(), ctypes.byref(h)),
                "acr_factor")
@@ -312,7 +314,7 @@ def autotune(coef, eps=1e-6, precision="fp64", leaf=64, sample_planes=16, cache=
     _check(L.acr_autotune(ctypes.byref(o), ctypes.c_void_p(coef.data_ptr()), int(sample_planes), path, _stream(),
                           ctypes.byref(r)), "acr_autotune")
     return {"leaf": r.leaf, "svd_fused_lds": r.svd_fused_lds, "seconds": r.seconds, "tried": r.tried,
-            "from_cache": bool(r.from_cache)}
+            "from_cache": bool(r.from_cache), "gemm_tiles": r.gemm_tiles}
 
 
 class ACRSolve(torch.autograd.Function):

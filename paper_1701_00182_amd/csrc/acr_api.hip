@@ -914,6 +914,8 @@ FactorBase* make_factor(const acr_options_t* o, const double* coef_in, hipStream
   al.ctx = o->alloc_ctx;
   f->ex.init(s, al);
   f->ex.leaf_lowp = o->precision == ACR_PREC_FP32_BF16LEAF ? 1 : (o->precision == ACR_PREC_FP32_FP16LEAF ? 2 : 0);
+  // matrix-core tile shape for narrow FP32 outputs: the option, overridden by ACR_GEMM_NARROW when set
+  if (!std::getenv("ACR_GEMM_NARROW")) f->ex.gemm_narrow = o->gemm_tiles != 1;
   f->prod_lowp = o->precision == ACR_PREC_FP32_BF16 ? 1 : (o->precision == ACR_PREC_FP32_FP16 ? 2 : 0);
   if (f->prod_lowp) f->ex.leaf_lowp = f->prod_lowp;
   // core-SVD dispatch: the option, overridden by ACR_FUSED_LDS (bytes) when set
@@ -1182,12 +1184,14 @@ bool tune_cache_read(const char* path, const std::string& key, acr_tune_result_t
   while (std::fgets(line, sizeof(line), fh)) {
     const char* bar = std::strchr(line, '|');
     if (!bar || std::string(line, bar - line) != key) continue;
-    int leaf = 0, fl = 0;
+    int leaf = 0, fl = 0, gt = 0;
     double sec = 0;
-    if (std::sscanf(bar + 1, " leaf=%d svd_fused_lds=%d seconds=%lf", &leaf, &fl, &sec) == 3 && leaf > 0) {
+    if (std::sscanf(bar + 1, " leaf=%d svd_fused_lds=%d seconds=%lf gemm_tiles=%d", &leaf, &fl, &sec, &gt) == 4 &&
+        leaf > 0) {
       out->leaf = leaf;
       out->svd_fused_lds = fl;
       out->seconds = sec;
+      out->gemm_tiles = gt;
       found = true;   // the last matching line wins
     }
   }
@@ -1199,8 +1203,8 @@ void tune_cache_append(const char* path, const std::string& key, const acr_tune_
   if (!path) return;
   std::FILE* fh = std::fopen(path, "a");
   if (!fh) return;
-  std::fprintf(fh, "%s| leaf=%d svd_fused_lds=%d seconds=%.6f\n", key.c_str(), r->leaf, r->svd_fused_lds,
-               r->seconds);
+  std::fprintf(fh, "%s| leaf=%d svd_fused_lds=%d seconds=%.6f gemm_tiles=%d\n", key.c_str(), r->leaf,
+               r->svd_fused_lds, r->seconds, r->gemm_tiles);
   std::fclose(fh);
 }
 
@@ -1242,9 +1246,10 @@ acr_status_t autotune_impl(const acr_options_t* opt, const double* coef, int sam
   const int fused[] = {-1, 64 * 1024, (int)kLdsBudget};
   acr_options_t o = *opt;
   o.nplanes = sp;
-  auto trial = [&](int leaf, int fl) -> double {
+  auto trial = [&](int leaf, int fl, int gt) -> double {
     o.leaf = leaf;
     o.svd_fused_lds = fl;
+    o.gemm_tiles = gt;
     hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
     const auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<FactorBase> f(o.precision == ACR_PREC_FP64 ? make_factor<double>(&o, dcoef, stream)
@@ -1264,10 +1269,10 @@ acr_status_t autotune_impl(const acr_options_t* opt, const double* coef, int sam
     for (int fl : fused) {
       try {
         if (!warm) {
-          (void)trial(leaf, fl);   // first-use costs (code objects, LDS attributes) out of the timing
+          (void)trial(leaf, fl, 0);   // first-use costs (code objects, LDS attributes) out of the timing
           warm = true;
         }
-        const double t = trial(leaf, fl);
+        const double t = trial(leaf, fl, 0);
         ++out->tried;
         // a later candidate has to be at least 3% faster: timing noise does
         // not flip between equivalent configurations
@@ -1283,6 +1288,18 @@ acr_status_t autotune_impl(const acr_options_t* opt, const double* coef, int sam
       }
     }
   if (out->leaf == 0) return last;
+  // the matrix-core tile shape for narrow outputs at the chosen pair: the
+  // 64 x 64 tiles replace the 128 x 32 ones only when at least 3% faster
+  try {
+    const double t = trial(out->leaf, out->svd_fused_lds, 1);
+    ++out->tried;
+    if (t < 0.97 * best) {
+      out->gemm_tiles = 1;
+      out->seconds = t;
+    }
+  } catch (const Failure& e) {
+    g_last_error = e.what();
+  }
   tune_cache_append(cache_path, key, out);
   return ACR_SUCCESS;
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <functional>
 #include <stdexcept>
 #include <string>
@@ -116,6 +117,22 @@ class Exec {
   const void* upload_bytes(const void* src, size_t bytes);
   template <class Task> const Task* upload(const std::vector<Task>& v) {
     return static_cast<const Task*>(upload_bytes(v.data(), v.size() * sizeof(Task)));
+  }
+  // One upload of a launch's task array and its two index arrays (one copy
+  // dispatch instead of three); each array starts on a 16-byte boundary.
+  template <class Task>
+  void upload3(const std::vector<Task>& a, const std::vector<int>& b, const std::vector<int>& c, const Task** da,
+               const int** db, const int** dc) {
+    const size_t ob = (a.size() * sizeof(Task) + 15) & ~size_t(15);
+    const size_t oc = ob + ((b.size() * sizeof(int) + 15) & ~size_t(15));
+    std::vector<char> buf(oc + c.size() * sizeof(int));
+    std::memcpy(buf.data(), a.data(), a.size() * sizeof(Task));
+    std::memcpy(buf.data() + ob, b.data(), b.size() * sizeof(int));
+    std::memcpy(buf.data() + oc, c.data(), c.size() * sizeof(int));
+    const char* d = static_cast<const char*>(upload_bytes(buf.data(), buf.size()));
+    *da = reinterpret_cast<const Task*>(d);
+    *db = reinterpret_cast<const int*>(d + ob);
+    *dc = reinterpret_cast<const int*>(d + oc);
   }
   void submit(std::function<void(hipStream_t)> f, const Work& w = Work{});
   // Eager replay of recorded launches on `s`, each timed like a submitted one

@@ -83,6 +83,7 @@ bool options_valid(const acr_options_t* o) {
   if ((o->alloc == nullptr) != (o->release == nullptr)) return false;
   if (!(o->inner_eps_ratio >= 0.0) || !std::isfinite(o->inner_eps_ratio)) return false;
   if (o->stencil_points != 0 && o->stencil_points != 7 && o->stencil_points != 27) return false;
+  if (o->gemm_tiles < 0 || o->gemm_tiles > 1) return false;
   if ((int64_t)o->nx * o->ny > (int64_t)1 << 28) return false;
   if ((int64_t)o->nx * o->ny * o->nplanes > (int64_t)1 << 34) return false;
   return true;

@@ -508,9 +508,9 @@ template <class T> void Exec::gemm(const std::vector<GemmTask>& t) {
       w.flops += 2.0 * x.m * x.n * (double)x.k;
       w.bytes += sizeof(T) * ((double)x.m * x.k + (double)x.k * x.n + (double)x.m * x.n * (x.beta != 0.0 ? 2 : 1));
     }
-    const GemmTask* dt = upload(sel);
-    const int* dtt = upload(tile_task);
-    const int* dft = upload(first);
+    const GemmTask* dt;
+    const int *dtt, *dft;
+    upload3(sel, tile_task, first, &dt, &dtt, &dft);
     if (mode == 3)
       submit([=](hipStream_t s) { launch_gemm_narrow(dt, dtt, dft, nt, s); }, w);
     else
@@ -551,9 +551,9 @@ template <class T> void Exec::seg_gemm(const std::vector<SegGemmTask>& t) {
   }
   flops_gemm += w.flops;
   if (nt == 0) return;
-  const SegGemmTask* dt = upload(t);
-  const int* dtt = upload(tile_task);
-  const int* dft = upload(first);
+  const SegGemmTask* dt;
+  const int *dtt, *dft;
+  upload3(t, tile_task, first, &dt, &dtt, &dft);
   submit([=](hipStream_t s) { launch_seg_gemm<T>(dt, dtt, dft, nt, s); }, w);
 }
 
@@ -883,9 +883,9 @@ template <class T> void Exec::gram(const std::vector<GramTask>& t) {
     w.flops += (double)x.m * x.r * (x.r + 1);
     w.bytes += sizeof(T) * (double)x.m * x.r + 8.0 * x.r * x.r * ((x.m + x.rows_per_chunk - 1) / x.rows_per_chunk);
   }
-  const GramTask* dt = upload(t);
-  const int* dtt = upload(tile_task);
-  const int* dft = upload(first);
+  const GramTask* dt;
+  const int *dtt, *dft;
+  upload3(t, tile_task, first, &dt, &dtt, &dft);
   const int n = (int)t.size();
   submit([=](hipStream_t s) { launch_gram<T>(dt, n, dtt, dft, nt, s); }, w);
 }
@@ -1030,9 +1030,9 @@ template <class T> void Exec::inner(const std::vector<InnerTask>& t) {
   bool vec = true;
   for (auto& x : t)
     vec = vec && x.rows % VW == 0 && x.ldv % VW == 0 && x.ldx % VW == 0 && al(x.V) && al(x.x);
-  const InnerTask* dt = upload(t);
-  const int* dwt = upload(wave_task);
-  const int* dfw = upload(first);
+  const InnerTask* dt;
+  const int *dwt, *dfw;
+  upload3(t, wave_task, first, &dt, &dwt, &dfw);
   submit([=](hipStream_t s) { launch_inner<T>(dt, dwt, dfw, nw, vec, s); }, w);
 }
 

@@ -39,7 +39,8 @@ def _opts(**kw):
 
 @pytest.mark.parametrize("kw", [dict(nx=0), dict(ny=-1), dict(nplanes=0), dict(leaf=0), dict(eps=-1.0),
                                 dict(eps=float("nan")), dict(max_rank=-2), dict(precision=9),
-                                dict(stencil_points=9), dict(stencil_points=-1)])
+                                dict(stencil_points=9), dict(stencil_points=-1), dict(gemm_tiles=2),
+                                dict(gemm_tiles=-1)])
 def test_invalid_options_rejected_before_device_work(kw):
     L = acr.lib()
     h = ctypes.c_void_p(123)
