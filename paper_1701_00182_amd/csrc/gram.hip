@@ -288,7 +288,6 @@ __global__ __launch_bounds__(NT) void k_pchol_lds(const PcholTask* __restrict__ 
 // The columns collect in LDS and go to global memory every kPcholChunk steps:
 // a workgroup barrier waits for the thread's outstanding global stores, so a
 // store per step would put a memory round trip into every step.
-constexpr int kPcholChunk = 32;
 template <int NT, int TB>
 __global__ __launch_bounds__(NT) void k_pchol_reg(const PcholTask* __restrict__ tasks, double tol) {
   extern __shared__ double spr[];
@@ -568,9 +567,7 @@ void launch_pchol(const PcholTask* d_tasks, int ntasks, int max_r, double tol, s
 
 void launch_pchol_reg(const PcholTask* d_tasks, int ntasks, int max_r, double tol, bool small, hipStream_t s) {
   if (ntasks <= 0) return;
-  // LDS: the scaled column, the pivot diagonals and kPcholChunk columns of L
-  // (doubles), perm, posof, alive (ints)
-  const size_t lds = (size_t)max_r * ((2 + kPcholChunk) * sizeof(double) + 3 * sizeof(int));
+  const size_t lds = lds_bytes_pchol_reg(max_r);
   if (lds > 64 * 1024) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol_reg<256, 4>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -171,6 +171,7 @@ class Exec {
   bool inverse_unblocked = false;  // ACR_INVERSE_UNBLOCKED=1: unblocked Gauss-Jordan for every inverse
   bool pchol_lds = false;      // ACR_PCHOL_LDS=1: the right-looking LDS kernel instead of the register-tiled one
   bool gemm_narrow = true;     // ACR_GEMM_NARROW=0: FP32 outputs <= 32 columns wide in 64 x 64 tiles too
+  int merge_cus = 0;           // compute units for merging LDS size classes into one launch (ACR_NO_MERGE=1: 0, off)
   int leaf_lowp = 0;           // leaf x leaf products with 16-bit inputs: 1 = BF16, 2 = FP16 (FP32 data)
   int prod_lowp = 0;           // every factorisation product without its own choice, as leaf_lowp
   const char* trace_tag = "";

@@ -52,12 +52,13 @@ template <class T> struct CJob {
   T* Vs;   // n x r stack (destroyed)
   int m, n, r;
   LR<T>* out;
+  Arena* arena = nullptr;   // where the truncated factors go (set by compress)
+  int max_rank = 0;         // rank cap of this block (0: none)
 };
 
 // Householder path: QR of both stacks, Jacobi SVD of the core, Q [Z; 0].
 template <class T>
-void compress_householder(Exec& ex, std::vector<CJob<T>*>& live, double eps, int max_rank, Arena& out,
-                          Arena& tmp) {
+void compress_householder(Exec& ex, std::vector<CJob<T>*>& live, double eps, Arena& tmp) {
   if (live.empty()) return;
   const auto mk = tmp.mark();
   const int nj = (int)live.size();
@@ -84,7 +85,7 @@ void compress_householder(Exec& ex, std::vector<CJob<T>*>& live, double eps, int
     s.p = p; s.q = q; s.r = j.r;
     s.C = Cw[i]; s.Y = Yw[i]; s.sig = sig;
     s.rank_out = d_rank + i;
-    s.max_rank = max_rank;
+    s.max_rank = j.max_rank;
     s.mode = 0;
     s.perm = tmp.get_n<int>(q);
     s.t_out = d_tv + i;
@@ -105,8 +106,8 @@ void compress_householder(Exec& ex, std::vector<CJob<T>*>& live, double eps, int
     LR<T> o;
     o.k = k;
     if (k > 0) {
-      o.U = out.get_n<T>((size_t)j.m * k);
-      o.V = out.get_n<T>((size_t)j.n * k);
+      o.U = j.arena->template get_n<T>((size_t)j.m * k);
+      o.V = j.arena->template get_n<T>((size_t)j.n * k);
       ApplyQTask a;
       a.Aq = j.Us; a.tau = tau_u[i]; a.Z = Cw[i] + (size_t)p * q; a.out = o.U;
       a.lda = j.m; a.ldz = p; a.ldo = j.m; a.m = j.m; a.p = p; a.k = k;
@@ -124,7 +125,7 @@ void compress_householder(Exec& ex, std::vector<CJob<T>*>& live, double eps, int
 
 // Gram path for stacks too large for one workgroup (see gram.hip).
 template <class T>
-void compress_gram(Exec& ex, std::vector<CJob<T>*>& live, double eps, int max_rank, Arena& out, Arena& tmp) {
+void compress_gram(Exec& ex, std::vector<CJob<T>*>& live, double eps, Arena& tmp) {
   if (live.empty()) return;
   const auto mk = tmp.mark();
   const int nj = (int)live.size();
@@ -189,7 +190,7 @@ void compress_gram(Exec& ex, std::vector<CJob<T>*>& live, double eps, int max_ra
     s.p = p; s.q = q; s.r = live[i]->r;
     s.C = Cw[i]; s.Y = Yw[i]; s.sig = tmp.get_n<double>(q);
     s.rank_out = d_rank + i;
-    s.max_rank = max_rank;
+    s.max_rank = live[i]->max_rank;
     s.mode = 1;
     s.perm = tmp.get_n<int>(q);
     s.t_out = d_tv + st.size();
@@ -222,8 +223,8 @@ void compress_gram(Exec& ex, std::vector<CJob<T>*>& live, double eps, int max_ra
       Wv[i] = tmp.get_n<T>((size_t)r * k);
       wt.push_back(WtTask{pu.L, pu.perm, Cw[i] + (size_t)p * q, p, Wu[i], r, p, k});
       wt.push_back(WtTask{pv.L, pv.perm, Yw[i] + (size_t)q * q, q, Wv[i], r, q, k});
-      o.U = out.get_n<T>((size_t)j.m * k);
-      o.V = out.get_n<T>((size_t)j.n * k);
+      o.U = j.arena->template get_n<T>((size_t)j.m * k);
+      o.V = j.arena->template get_n<T>((size_t)j.n * k);
       // the truncated factors are rebuilt in FP32 in every precision variant
       gg.push_back(gt<T>(j.Us, j.m, 0, Wu[i], r, 0, o.U, j.m, j.m, k, r, 1.0, 0.0));
       gg.back().lowp = -1;
@@ -245,6 +246,10 @@ template <class T>
 void compress(Exec& ex, std::vector<CJob<T>>& jobs, double eps, int max_rank, Arena& out, Arena& tmp) {
   std::vector<CJob<T>*> hh, gr;
   for (auto& j : jobs) {
+    if (!j.arena) {
+      j.arena = &out;
+      j.max_rank = max_rank;
+    }
     if (j.r == 0 || j.m == 0 || j.n == 0) {
       *j.out = LR<T>{};
       continue;
@@ -262,8 +267,34 @@ void compress(Exec& ex, std::vector<CJob<T>>& jobs, double eps, int max_rank, Ar
     std::fprintf(stderr, "[acr] compress %s n=%zu hh=%zu gram=%zu max_m=%d max_r=%d work=%.3g\n", ex.trace_tag,
                  jobs.size(), hh.size(), gr.size(), mm, mr, w);
   }
-  compress_householder<T>(ex, hh, eps, max_rank, out, tmp);
-  compress_gram<T>(ex, gr, eps, max_rank, out, tmp);
+  compress_householder<T>(ex, hh, eps, tmp);
+  compress_gram<T>(ex, gr, eps, tmp);
+}
+
+// Two independent sets of blocks (outputs to their own arenas, rank caps of
+// their own): one compression batch when their tolerances agree, so that the
+// pair costs one chain of launches and host round trips instead of two.
+template <class T>
+void compress2(Exec& ex, std::vector<CJob<T>>& a, double eps_a, int max_rank_a, Arena& out_a,
+               std::vector<CJob<T>>& b, double eps_b, int max_rank_b, Arena& out_b, Arena& tmp) {
+  if (eps_a != eps_b || a.empty() || b.empty()) {
+    compress<T>(ex, a, eps_a, max_rank_a, out_a, tmp);
+    compress<T>(ex, b, eps_b, max_rank_b, out_b, tmp);
+    return;
+  }
+  std::vector<CJob<T>> all;
+  all.reserve(a.size() + b.size());
+  for (auto j : a) {
+    j.arena = &out_a;
+    j.max_rank = max_rank_a;
+    all.push_back(j);
+  }
+  for (auto j : b) {
+    j.arena = &out_b;
+    j.max_rank = max_rank_b;
+    all.push_back(j);
+  }
+  compress<T>(ex, all, eps_a, 0, tmp, tmp);
 }
 
 inline int nseg(int d) { return 1 << d; }
@@ -628,8 +659,8 @@ void hodlr_inverse(Exec& ex, const Tree& tr, const std::vector<const HMat<T>*>& 
     ex.copy<T>(sc);
     ex.gemm<T>(leafupd);
     // depth-0 blocks are final; deeper ones are intermediate until the push-down
-    compress<T>(ex, gj, d == 0 ? tc.eps : tc.eps_inner, d == 0 ? tc.max_rank : 0, d == 0 ? out : work, tmp);
-    compress<T>(ex, cj, tc.eps_inner, 0, work, tmp);
+    compress2<T>(ex, gj, d == 0 ? tc.eps : tc.eps_inner, d == 0 ? tc.max_rank : 0, d == 0 ? out : work, cj,
+                 tc.eps_inner, 0, work, tmp);
     for (int p = 0; p < np; ++p)
       for (int s = 0; s < nseg(d + 1); ++s) cur[p].blk[Tree::bid(d, s)] = g[p][Tree::bid(d, s)];
     tmp.release(tm);
@@ -696,8 +727,7 @@ void hodlr_inverse(Exec& ex, const Tree& tr, const std::vector<const HMat<T>*>& 
     }
     ex.copy<T>(sc);
     ex.gemm<T>(leafupd);
-    compress<T>(ex, bj, tc.eps, tc.max_rank, out, tmp);
-    compress<T>(ex, aj, tc.eps_inner, 0, work, tmp);
+    compress2<T>(ex, bj, tc.eps, tc.max_rank, out, aj, tc.eps_inner, 0, work, tmp);
     // the new accumulators live in `work`, so only the stacks are released
     tmp.release(tm);
     if (d + 1 < L) acc = std::move(nacc);
@@ -891,8 +921,7 @@ void hodlr_product(Exec& ex, const Tree& tr, const std::vector<ProdJob<T>>& jobs
     ex.gemm<T>(zg);
     ex.copy<T>(sc);
     ex.gemm<T>(leafupd);
-    compress<T>(ex, bj, tc.eps, tc.max_rank, out, tmp);
-    compress<T>(ex, aj, tc.eps_inner, 0, work, tmp);
+    compress2<T>(ex, bj, tc.eps, tc.max_rank, out, aj, tc.eps_inner, 0, work, tmp);
     tmp.release(tm);
     if (d + 1 < L) acc = std::move(nacc);
   }

@@ -234,10 +234,15 @@ template <class T> void launch_inner(const InnerTask* d_tasks, const int* d_wave
                                     int nwaves, bool vec, hipStream_t s);
 template <class T> void launch_apply_leaf(const LeafTask* d_tasks, int ntasks, bool vec, hipStream_t s);
 constexpr size_t kLdsBudget = 156 * 1024;
+constexpr size_t kLdsPerCu = 160 * 1024;   // LDS of one compute unit
 constexpr size_t kSmallLds = 32 * 1024;   // LDS-resident tasks up to this size use 256-thread workgroups
 inline size_t lds_bytes_qr(const QrTask& t, size_t w) { return (size_t)t.m * t.r * w; }
 inline size_t lds_bytes_jacobi(const SvdTask& t) { return (size_t)t.q * t.tc * 8; }
 inline size_t lds_bytes_pchol_packed(int r) { return (size_t)r * (r + 1) / 2 * 8 + (size_t)r * 4; }
+// register-tiled pivoted Cholesky: the scaled column, the pivot diagonals and
+// kPcholChunk buffered columns of L (doubles), perm, posof, alive (ints)
+constexpr int kPcholChunk = 32;
+inline size_t lds_bytes_pchol_reg(int r) { return (size_t)r * ((2 + kPcholChunk) * 8 + 3 * 4); }
 constexpr int kSvdWave = 64;
 inline bool svd_wave_ok(const SvdTask& t) {
   return t.mode == 0 && t.p <= kSvdWave && t.q <= kSvdWave && t.r <= kSvdWave;

@@ -282,6 +282,11 @@ void Exec::init(hipStream_t s, const Allocator& a) {
   inverse_unblocked = iu && iu[0] == '1';
   const char* gn = std::getenv("ACR_GEMM_NARROW");
   gemm_narrow = !(gn && gn[0] == '0');
+  const char* nm = std::getenv("ACR_NO_MERGE");
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+    merge_cus = (nm && nm[0] == '1') ? 0 : cus;
   stream = s;
   al = a;
   ring_bytes_ = size_t(64) << 20;
@@ -450,24 +455,47 @@ void Exec::read_flags(int out[NFLAGS]) {
 
 // Splits tasks by the local memory they need: one launch per size class of the
 // LDS-resident kernel (so small problems are not limited by the occupancy of
-// large ones), one launch of the global-memory kernel for the rest.
+// large ones), one launch of the global-memory kernel for the rest.  Classes
+// whose tasks all fit on the chip at once at the occupancy of the largest one
+// (cus compute units, `threads` per workgroup; 0: 256 up to kSmallLds, else
+// 1024) share a launch: their workgroups would not have waited for each
+// other, and a second launch of a few long tasks would serialise behind the
+// first.
+inline int wg_per_cu(size_t lds, int threads) {
+  const int by_lds = lds > 0 ? (int)(kLdsPerCu / lds) : 64;
+  const int by_threads = 2048 / threads;
+  return std::max(1, std::min(by_lds, by_threads));
+}
+
 template <class Task, class Need, class Launch>
-void bucketed(const std::vector<Task>& t, Need need, Launch launch) {
+void bucketed(const std::vector<Task>& t, Need need, Launch launch, int cus = 0, int threads = 0) {
   static const size_t cls[] = {16 * 1024, 32 * 1024, 64 * 1024, 96 * 1024, kLdsBudget};
   std::vector<Task> b[6];
+  size_t mx[5] = {0, 0, 0, 0, 0};
   for (const Task& x : t) {
     const size_t n = need(x);
     int c = 5;
     for (int i = 0; i < 5; ++i)
       if (n <= cls[i]) { c = i; break; }
     b[c].push_back(x);
+    if (c < 5) mx[c] = std::max(mx[c], n);
   }
-  for (int i = 0; i < 5; ++i)
-    if (!b[i].empty()) {
-      size_t mx = 0;
-      for (const Task& x : b[i]) mx = std::max(mx, need(x));
-      launch(b[i], std::max<size_t>(mx, 16));
+  for (int i = 4; i >= 0; --i) {
+    if (b[i].empty()) continue;
+    size_t lds = std::max<size_t>(mx[i], 16);
+    std::vector<Task> group = std::move(b[i]);
+    while (cus > 0) {
+      int j = i - 1;
+      while (j >= 0 && b[j].empty()) --j;
+      if (j < 0) break;
+      const int nt = threads ? threads : (lds <= kSmallLds ? 256 : 1024);
+      if ((long)(group.size() + b[j].size()) > (long)cus * wg_per_cu(lds, nt)) break;
+      group.insert(group.end(), b[j].begin(), b[j].end());
+      b[j].clear();
+      i = j;
     }
+    launch(group, lds);
+  }
   if (!b[5].empty()) launch(b[5], 0);
 }
 
@@ -631,7 +659,8 @@ template <class T> void Exec::qr(const std::vector<QrTask>& t) {
              const QrTask* dt = upload(b);
              const int n = (int)b.size();
              submit([=](hipStream_t s) { launch_qr_lds<T>(dt, n, lds, s); }, w);
-           });
+           },
+           merge_cus);
 }
 
 template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tvals) {
@@ -788,24 +817,24 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
   }
   // main stream: pivoted QR of the LDS cores first (their ranks come back
   // early), then the one-workgroup cores
-  bucketed(two[0], [](const SvdTask& x) { return lds_bytes_qrcp(x); }, qrcp_batch);
+  bucketed(two[0], [](const SvdTask& x) { return lds_bytes_qrcp(x); }, qrcp_batch, merge_cus);
   if (!two[0].empty()) read_ranks(0);
   bucketed(small, [](const SvdTask& x) { return lds_bytes_svd_wave(x, sizeof(T)); },
-           [&](const std::vector<SvdTask>& b, size_t lds) { fused(b, lds, true); });
+           [&](const std::vector<SvdTask>& b, size_t lds) { fused(b, lds, true); }, merge_cus, 64);
   bucketed(mid, [](const SvdTask& x) { return lds_bytes_svd_block(x); },
-           [&](const std::vector<SvdTask>& b, size_t lds) { fused(b, lds, false); });
+           [&](const std::vector<SvdTask>& b, size_t lds) { fused(b, lds, false); }, merge_cus);
   small.insert(small.end(), mid.begin(), mid.end());
   left(small);
   if (!two[0].empty()) {
     rank_stage(0);
-    bucketed(two[0], [](const SvdTask& x) { return lds_bytes_jacobi(x); }, jacobi_batch);
+    bucketed(two[0], [](const SvdTask& x) { return lds_bytes_jacobi(x); }, jacobi_batch, merge_cus);
     left(two[0]);
   }
   if (split) {
     rank_stage(1);
     std::swap(stream, side_);
     if (svd_global) jacobi_batch(two[1], 0);
-    else bucketed(two[1], [](const SvdTask& x) { return lds_bytes_jacobi(x); }, jacobi_batch);
+    else bucketed(two[1], [](const SvdTask& x) { return lds_bytes_jacobi(x); }, jacobi_batch, merge_cus);
     left(two[1]);
     hip_check(hipEventRecord(ev_[2], stream), "hipEventRecord");
     std::swap(stream, side_);
@@ -852,7 +881,8 @@ template <class T> void Exec::applyq(const std::vector<ApplyQTask>& t) {
              const ApplyQTask* dt = upload(b);
              const int n = (int)b.size();
              submit([=](hipStream_t s) { launch_applyq_lds<T>(dt, n, lds, s); }, w);
-           });
+           },
+           merge_cus);
 }
 
 template <class T> void Exec::gram(const std::vector<GramTask>& t) {
@@ -916,6 +946,14 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
       wide.push_back(x);
       max_r = std::max(max_r, x.r);
     }
+  }
+  // both kinds in one launch of the wide-tile kernel when it holds them all at
+  // once (a second launch of a few long tasks would wait for the first)
+  if (merge_cus > 0 && !reg_small.empty() && !reg_large.empty() &&
+      (long)(reg_small.size() + reg_large.size()) <=
+          (long)merge_cus * wg_per_cu(lds_bytes_pchol_reg(kPcholReg), 1024)) {
+    reg_large.insert(reg_large.end(), reg_small.begin(), reg_small.end());
+    reg_small.clear();
   }
   for (auto* b : {&reg_small, &reg_large}) {
     if (b->empty()) continue;
