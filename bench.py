@@ -656,6 +656,7 @@ PMC_CLASSES = [
     ("k_gram", "gram", ["paper_1701_00182_amd/csrc/gemm_mfma.hip", "paper_1701_00182_amd/csrc/gram.hip"]),
     ("k_wtilde<float>", "wtilde", ["paper_1701_00182_amd/csrc/gram.hip"]),
     ("k_inverse<float", "inverse", ["paper_1701_00182_amd/csrc/la_kernels.hip"]),
+    ("k_inverse_blk<float", "inverse", ["paper_1701_00182_amd/csrc/la_kernels.hip"]),
     ("k_copy<float>", "copy", ["paper_1701_00182_amd/csrc/la_kernels.hip"]),
     ("k_apply_leaf_vec<float>", "solve_leaf", ["paper_1701_00182_amd/csrc/solve_kernels.hip"]),
     ("k_inner_vec<float>", "solve_inner", ["paper_1701_00182_amd/csrc/solve_kernels.hip"]),
