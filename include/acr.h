@@ -332,6 +332,19 @@ typedef struct {
 void acr_set_kernel_timing(int32_t level);
 int32_t acr_get_kernel_times(acr_kernel_time_t* out, int32_t cap);
 
+/*
+ * Cached device memory.  With the default allocator (acr_options_t.alloc
+ * NULL), device buffers that the library releases (a freed handle's arenas,
+ * executor buffers) are kept per device and size and handed to later requests
+ * of the same size instead of going back through hipFree / hipMalloc, which
+ * synchronise the device.  acr_release_cached_memory() frees every cached
+ * buffer (all devices) and returns the bytes released; an allocation that
+ * fails does the same once before reporting ACR_ERROR_HIP.  Environment
+ * ACR_NO_POOL=1 disables the cache.  Callers with their own allocator
+ * callbacks are not affected.  Thread-safe.
+ */
+size_t acr_release_cached_memory(void);
+
 /* Text of the last failure on the calling host thread ("" if none); valid until the next call. */
 const char* acr_last_error_message(void);
 

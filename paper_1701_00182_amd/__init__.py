@@ -71,7 +71,8 @@ class RefineResult(ctypes.Structure):
 
 EXPORTS = ("acr_options_default", "acr_factor", "acr_solve", "acr_solve_transpose", "acr_solve_noalloc", "acr_free",
            "acr_get_stats", "acr_solve_refined", "acr_residual", "acr_assemble_diffusion",
-           "acr_kappa_gradient", "acr_status_string", "acr_plan_structure", "acr_get_structure")
+           "acr_kappa_gradient", "acr_status_string", "acr_plan_structure", "acr_get_structure",
+           "acr_release_cached_memory")
 
 
 def lib():
@@ -114,6 +115,8 @@ def lib():
         L.acr_get_structure.restype = ctypes.c_int
         L.acr_last_error_message.argtypes = []
         L.acr_last_error_message.restype = ctypes.c_char_p
+        L.acr_release_cached_memory.argtypes = []
+        L.acr_release_cached_memory.restype = ctypes.c_size_t
         _LIB = L
     return _LIB
 
@@ -135,6 +138,12 @@ def _structure(call, where):
         pos += m
     return {"M": info.M, "depth": info.depth, "perm": perm[:info.M], "node_offset": noff[:info.nodes],
             "node_size": nsz[:info.nodes], "schedule": sched, "last_plane": info.last_plane}
+
+
+def release_cached_memory():
+    """acr_release_cached_memory: free the device buffers the library keeps for
+    reuse; returns the bytes released."""
+    return int(lib().acr_release_cached_memory())
 
 
 def plan_structure(nx, ny, nplanes, leaf):

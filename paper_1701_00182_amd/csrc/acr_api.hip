@@ -1457,6 +1457,8 @@ const char* acr_last_error_message(void) { return g_last_error.c_str(); }
 
 void acr_set_kernel_timing(int32_t level) { acr::timing_enable(level); }
 
+size_t acr_release_cached_memory(void) { return acr::release_cached_memory(); }
+
 int32_t acr_get_kernel_times(acr_kernel_time_t* out, int32_t cap) {
   return acr::timing_report(out, cap < 0 ? 0 : cap);
 }

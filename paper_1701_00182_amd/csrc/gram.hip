@@ -565,17 +565,21 @@ void launch_pchol(const PcholTask* d_tasks, int ntasks, int max_r, double tol, s
   hipLaunchKernelGGL(k_pchol<1024>, dim3(ntasks), dim3(1024), lds, s, d_tasks, tol);
 }
 
-void launch_pchol_reg(const PcholTask* d_tasks, int ntasks, int max_r, double tol, bool small, hipStream_t s) {
+void launch_pchol_reg(const PcholTask* d_tasks, int ntasks, int max_r, double tol, int kind, hipStream_t s) {
   if (ntasks <= 0) return;
   const size_t lds = lds_bytes_pchol_reg(max_r);
   if (lds > 64 * 1024) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol_reg<256, 4>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol_reg<512, 8>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol_reg<1024, 5>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
-  if (small)
+  if (kind == 0)
     hipLaunchKernelGGL((k_pchol_reg<256, 4>), dim3(ntasks), dim3(256), lds, s, d_tasks, tol);
+  else if (kind == 1)
+    hipLaunchKernelGGL((k_pchol_reg<512, 8>), dim3(ntasks), dim3(512), lds, s, d_tasks, tol);
   else
     hipLaunchKernelGGL((k_pchol_reg<1024, 5>), dim3(ntasks), dim3(1024), lds, s, d_tasks, tol);
 }

@@ -80,6 +80,9 @@ struct Work {
   double flops_per_count = 0, bytes_per_count = 0;
 };
 
+// Frees the device buffers kept for reuse (default allocator); returns bytes.
+size_t release_cached_memory();
+
 // Process-wide switch and table of per-kernel-class event timings.
 void timing_enable(int level);   // 0 off, 1 factorisation launches, 2 also solve replays
 bool timing_enabled();
@@ -170,6 +173,7 @@ class Exec {
   bool pchol_global = false;   // ACR_PCHOL_GLOBAL=1: every Gram takes the left-looking global-memory kernel
   bool inverse_unblocked = false;  // ACR_INVERSE_UNBLOCKED=1: unblocked Gauss-Jordan for every inverse
   bool pchol_lds = false;      // ACR_PCHOL_LDS=1: the right-looking LDS kernel instead of the register-tiled one
+  bool pchol_512 = false;      // ACR_PCHOL_TILES=512: 512-thread 8 x 8 tiles for the whole large register-tiled kind
   bool gemm_narrow = true;     // ACR_GEMM_NARROW=0: FP32 outputs <= 32 columns wide in 64 x 64 tiles too
   int merge_cus = 0;           // compute units for merging LDS size classes into one launch (ACR_NO_MERGE=1: 0, off)
   int leaf_lowp = 0;           // leaf x leaf products with 16-bit inputs: 1 = BF16, 2 = FP16 (FP32 data)

@@ -194,11 +194,59 @@ void reg_add(void* p, size_t bytes) {
   std::lock_guard<std::mutex> lk(g_reg_mu);
   registry()[(uintptr_t)p] = bytes;
 }
-void reg_del(void* p) {
+size_t reg_del(void* p) {
   std::lock_guard<std::mutex> lk(g_reg_mu);
-  registry().erase((uintptr_t)p);
+  auto it = registry().find((uintptr_t)p);
+  if (it == registry().end()) return 0;
+  const size_t b = it->second;
+  registry().erase(it);
+  return b;
+}
+
+// Device buffers the library released (default allocator only), kept per
+// (device, size) for reuse by later requests of the same size: a factorisation
+// allocates its arenas in equal chunks, and hipMalloc / hipFree of such chunks
+// synchronise the device and, after many factorisations in one process, took
+// up to 0.3 s each.  acr_release_cached_memory() returns them to the runtime;
+// an allocation that fails does the same and tries once more.
+std::mutex g_pool_mu;
+std::map<std::pair<int, size_t>, std::vector<void*>>& chunk_pool() {
+  static std::map<std::pair<int, size_t>, std::vector<void*>> p;
+  return p;
+}
+bool pool_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("ACR_NO_POOL");
+    return !(e && e[0] == '1');
+  }();
+  return on;
+}
+void* pool_take(int dev, size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  auto it = chunk_pool().find({dev, bytes});
+  if (it == chunk_pool().end() || it->second.empty()) return nullptr;
+  void* p = it->second.back();
+  it->second.pop_back();
+  return p;
+}
+void pool_put(int dev, void* p, size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  chunk_pool()[{dev, bytes}].push_back(p);
+}
+size_t pool_release() {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  size_t n = 0;
+  for (auto& kv : chunk_pool())
+    for (void* p : kv.second) {
+      (void)hipFree(p);
+      n += kv.first.second;
+    }
+  chunk_pool().clear();
+  return n;
 }
 }  // namespace
+
+size_t release_cached_memory() { return pool_release(); }
 
 namespace {
 struct DeviceScratch {
@@ -282,6 +330,8 @@ void Exec::init(hipStream_t s, const Allocator& a) {
   inverse_unblocked = iu && iu[0] == '1';
   const char* gn = std::getenv("ACR_GEMM_NARROW");
   gemm_narrow = !(gn && gn[0] == '0');
+  const char* pt = std::getenv("ACR_PCHOL_TILES");
+  pchol_512 = pt && std::strcmp(pt, "512") == 0;
   const char* nm = std::getenv("ACR_NO_MERGE");
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) == hipSuccess &&
@@ -340,7 +390,17 @@ void* Exec::dev_alloc(size_t bytes) {
     p = al.alloc(bytes, al.ctx, stream);
     if (!p) throw Failure(ST_OOM, "allocator callback returned NULL");
   } else {
-    hip_check(hipMalloc(&p, bytes), "hipMalloc");
+    const int dev = current_device();
+    if (pool_enabled()) p = pool_take(dev, bytes);
+    if (!p) {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e == hipErrorOutOfMemory && pool_enabled()) {
+        (void)hipGetLastError();
+        pool_release();
+        e = hipMalloc(&p, bytes);
+      }
+      hip_check(e, "hipMalloc");
+    }
   }
   reg_add(p, bytes);
   return p;
@@ -348,9 +408,18 @@ void* Exec::dev_alloc(size_t bytes) {
 
 void Exec::dev_free(void* p) {
   if (!p) return;
-  reg_del(p);
+  const size_t bytes = reg_del(p);
   if (al.release) {
     al.release(p, al.ctx, stream);
+    return;
+  }
+  if (pool_enabled() && bytes > 0) {
+    // the executor's streams are the only users of its buffers (solve streams
+    // are synchronised before a handle's memory is released): once they are
+    // idle the buffer can serve any later request
+    (void)hipStreamSynchronize(stream);
+    if (side_) (void)hipStreamSynchronize(side_);
+    pool_put(current_device(), p, bytes);
     return;
   }
   (void)hipFree(p);  // hipFree waits for the device to finish with the memory
@@ -934,28 +1003,32 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
   // (ACR_PCHOL_LDS=1: those whose packed lower triangle fits in LDS take the
   // right-looking LDS kernel instead), wider ones the left-looking one with L
   // in global memory; two launches at most per kind (finer size buckets
-  // serialise the batch)
-  std::vector<PcholTask> packed, wide, reg_small, reg_large;
+  // serialise the batch).  Orders up to kPcholReg1024 take 5 x 5 tiles on
+  // 1024 threads (at n = 128 the class took 287 ms per factorisation against
+  // 333 ms with 8 x 8 tiles on 512 threads), orders up to kPcholReg 8 x 8
+  // tiles (they went to the left-looking kernel before); ACR_PCHOL_TILES=512
+  // takes 8 x 8 tiles for every order above kPcholRegSmall.
+  std::vector<PcholTask> packed, wide, reg_small, reg_large, reg_big;
   int max_r = 1;
   for (auto& x : t) {
     if (!pchol_global && pchol_lds && lds_bytes_pchol_packed(x.r) <= kLdsBudget) {
       packed.push_back(x);
     } else if (!pchol_global && x.r <= kPcholReg) {
-      (x.r <= kPcholRegSmall ? reg_small : reg_large).push_back(x);
+      (x.r <= kPcholRegSmall ? reg_small : x.r <= kPcholReg1024 && !pchol_512 ? reg_large : reg_big).push_back(x);
     } else {
       wide.push_back(x);
       max_r = std::max(max_r, x.r);
     }
   }
-  // both kinds in one launch of the wide-tile kernel when it holds them all at
+  // the small kind joins the 1024-thread launch when that holds them all at
   // once (a second launch of a few long tasks would wait for the first)
   if (merge_cus > 0 && !reg_small.empty() && !reg_large.empty() &&
       (long)(reg_small.size() + reg_large.size()) <=
-          (long)merge_cus * wg_per_cu(lds_bytes_pchol_reg(kPcholReg), 1024)) {
+          (long)merge_cus * wg_per_cu(lds_bytes_pchol_reg(kPcholReg1024), 1024)) {
     reg_large.insert(reg_large.end(), reg_small.begin(), reg_small.end());
     reg_small.clear();
   }
-  for (auto* b : {&reg_small, &reg_large}) {
+  for (auto* b : {&reg_small, &reg_large, &reg_big}) {
     if (b->empty()) continue;
     Work w;
     w.cls = "pchol";
@@ -965,10 +1038,10 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
     }
     const PcholTask* dt = upload(*b);
     const int n = (int)b->size();
-    const bool small_kind = b == &reg_small;
+    const int kind = b == &reg_small ? 0 : b == &reg_large ? 2 : 1;
     int rmax = 1;
     for (auto& x : *b) rmax = std::max(rmax, x.r);
-    submit([=](hipStream_t s) { launch_pchol_reg(dt, n, rmax, tol, small_kind, s); }, w);
+    submit([=](hipStream_t s) { launch_pchol_reg(dt, n, rmax, tol, kind, s); }, w);
   }
   if ((size_t)max_r * (sizeof(double) + sizeof(int)) > kLdsBudget)
     throw Failure(ST_NOT_SUPPORTED, "stack too wide for the pivoted Cholesky kernel");

@@ -511,8 +511,10 @@ __device__ __forceinline__ int jacobi_sweeps(double* V, int64_t vs, int64_t es, 
 // and written once per round instead of once per column pair.  The stopping
 // rule is the scalar one, evaluated on the fresh Gram matrices.
 constexpr int kJB = 8;
-constexpr int kJBScratch = 16 * 16 * 2 + 16 * 3;   // doubles of LDS per wavefront: G, V, rotation table
+// doubles of LDS per wavefront: G, V, rotation table, two 16 x 16 transpose tiles
+constexpr int kJBScratch = 16 * 16 * 2 + 16 * 3 + 2 * 256;
 constexpr int kJBInner = 1;                        // inner sweeps per block-pair visit
+constexpr int kJBRegRows = 256;                    // longest vectors of the register-resident visit
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -520,70 +522,39 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One block pair: columns cb[0..7] = bi*kJB.., cb[8..15] = bj*kJB.. (those >= n
-// are zero).  Returns whether Y changed; cmax2 takes the largest squared |cos|
-// of its column pairs before the step.
-__device__ inline bool jacobi_block_pair(double* X, int64_t vs, int n, int len, int bi, int bj, double tol,
-                                         double* g, double& cmax2) {
+// The Gram matrix of a block pair from its accumulators (v holds
+// G[kr + 4v][kc]) into LDS, V = I, and the pair's largest squared |cos| into
+// cmax2.
+__device__ inline void block_gram_store(double* g, const dbl4& acc0, const dbl4& acc1, double& cmax2) {
+  const int lane = threadIdx.x & 63;
+  const int kc = lane & 15, kr = lane >> 4;
+  double* vm = g + 256;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) g[(kr + 4 * v) * 16 + kc] = acc0[v] + acc1[v];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int e = lane + 64 * v;
+    vm[e] = (e >> 4) == (e & 15) ? 1.0 : 0.0;
+  }
+  wave_sync();
+  double c2 = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int a = kr + 4 * v;
+    if (a < kc) c2 = fmax(c2, pair_cos2(g[a * 17], g[kc * 17], g[a * 16 + kc]));
+  }
+  for (int off = 32; off > 0; off >>= 1) c2 = fmax(c2, __shfl_xor(c2, off, 64));
+  cmax2 = fmax(cmax2, c2);
+}
+
+// Inner cyclic Jacobi on the 16 x 16 Gram matrix G in LDS, rotations
+// accumulated in V; returns whether any rotation was applied.
+__device__ inline bool block_inner_jacobi(double* g, double tol) {
   const int lane = threadIdx.x & 63;
   double* vm = g + 256;
   double* cself = vm + 256;
   double* cpart = cself + 16;
   int* part = reinterpret_cast<int*>(cpart + 16);
-  auto colof = [&](int k) { return k < kJB ? bi * kJB + k : bj * kJB + (k - kJB); };
-  // Gram matrix: lane l feeds Y[r0 + l/16][slot l%16] as both operands; rows
-  // come in batches of 32 (8 loads per lane, issued together), the next batch
-  // loaded while the current one is multiplied; rows past len load a clamped
-  // address and contribute zero
-  {
-    const int kc = lane & 15, kr = lane >> 4;
-    const int col = colof(kc);
-    const bool ok = col < n;
-    const double* xc = X + (int64_t)(ok ? col : 0) * vs;
-    auto batch = [&](double (&y)[8], int r0) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int row = r0 + 4 * i + kr;
-        const double v = xc[row < len ? row : len - 1];
-        y[i] = (ok && row < len) ? v : 0.0;
-      }
-    };
-    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    double ya[8], yb[8];
-    batch(ya, 0);
-    for (int r0 = 0; r0 < len; r0 += 64) {
-      batch(yb, r0 + 32);
-#pragma unroll
-      for (int i = 0; i < 8; i += 2) {
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[i], ya[i], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[i + 1], ya[i + 1], acc1, 0, 0, 0);
-      }
-      batch(ya, r0 + 64);
-#pragma unroll
-      for (int i = 0; i < 8; i += 2) {
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[i], yb[i], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[i + 1], yb[i + 1], acc1, 0, 0, 0);
-      }
-    }
-    // accumulator v holds G[kr + 4v][kc]
-#pragma unroll
-    for (int v = 0; v < 4; ++v) g[(kr + 4 * v) * 16 + kc] = acc0[v] + acc1[v];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int e = lane + 64 * v;
-      vm[e] = (e >> 4) == (e & 15) ? 1.0 : 0.0;
-    }
-    wave_sync();
-    double c2 = 0.0;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int a = kr + 4 * v;
-      if (a < kc) c2 = fmax(c2, pair_cos2(g[a * 17], g[kc * 17], g[a * 16 + kc]));
-    }
-    for (int off = 32; off > 0; off >>= 1) c2 = fmax(c2, __shfl_xor(c2, off, 64));
-    cmax2 = fmax(cmax2, c2);
-  }
-  // inner cyclic Jacobi on G, rotations accumulated in V
   bool changed = false;
   const int a = lane >> 2, b0 = (lane & 3) * 4;
   for (int is = 0; is < kJBInner; ++is) {
@@ -632,7 +603,55 @@ __device__ inline bool jacobi_block_pair(double* X, int64_t vs, int n, int len, 
     if (!swept) break;
     changed = true;
   }
-  if (!changed) return false;
+  return changed;
+}
+
+// One block pair: columns cb[0..7] = bi*kJB.., cb[8..15] = bj*kJB.. (those >= n
+// are zero).  Returns whether Y changed; cmax2 takes the largest squared |cos|
+// of its column pairs before the step.  The vectors are streamed twice (Gram,
+// then update), 32 rows at a time.
+__device__ inline bool jacobi_block_pair(double* X, int64_t vs, int n, int len, int bi, int bj, double tol,
+                                         double* g, double& cmax2) {
+  const int lane = threadIdx.x & 63;
+  double* vm = g + 256;
+  auto colof = [&](int k) { return k < kJB ? bi * kJB + k : bj * kJB + (k - kJB); };
+  // Gram matrix: lane l feeds Y[r0 + l/16][slot l%16] as both operands; rows
+  // come in batches of 32 (8 loads per lane, issued together), the next batch
+  // loaded while the current one is multiplied; rows past len load a clamped
+  // address and contribute zero
+  {
+    const int kc = lane & 15, kr = lane >> 4;
+    const int col = colof(kc);
+    const bool ok = col < n;
+    const double* xc = X + (int64_t)(ok ? col : 0) * vs;
+    auto batch = [&](double (&y)[8], int r0) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int row = r0 + 4 * i + kr;
+        const double v = xc[row < len ? row : len - 1];
+        y[i] = (ok && row < len) ? v : 0.0;
+      }
+    };
+    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    double ya[8], yb[8];
+    batch(ya, 0);
+    for (int r0 = 0; r0 < len; r0 += 64) {
+      batch(yb, r0 + 32);
+#pragma unroll
+      for (int i = 0; i < 8; i += 2) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[i], ya[i], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[i + 1], ya[i + 1], acc1, 0, 0, 0);
+      }
+      batch(ya, r0 + 64);
+#pragma unroll
+      for (int i = 0; i < 8; i += 2) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[i], yb[i], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[i + 1], yb[i + 1], acc1, 0, 0, 0);
+      }
+    }
+    block_gram_store(g, acc0, acc1, cmax2);
+  }
+  if (!block_inner_jacobi(g, tol)) return false;
   // Y <- Y V, 16 rows at a time: lane l feeds Y[r0 + l%16][slot 4kk + l/16] and
   // V[4kk + l/16][l%16]; accumulator v is the new Y[r0 + l/16 + 4v][slot l%16]
   const int ir = lane & 15, ik = lane >> 4;
@@ -687,12 +706,78 @@ __device__ inline bool jacobi_block_pair(double* X, int64_t vs, int n, int len, 
   return true;
 }
 
+// The same visit for vectors of at most 32 NB elements with the block pair
+// held in registers: every lane loads its share of the 16 columns in one burst
+// (lane l: rows 4i + l/16 of column slot l%16), the Gram matrix and, after the
+// inner sweep, the rotated columns come from the same registers, so each
+// column is read once and written once per visit.  The update needs the rows
+// of each 16-row chunk across the lanes (the transposed layout): the chunk
+// goes through one of two 16 x 16 LDS tiles of the wavefront.
+template <int NB>
+__device__ inline bool jacobi_block_pair_reg(double* X, int64_t vs, int n, int len, int bi, int bj, double tol,
+                                             double* g, double& cmax2) {
+  const int lane = threadIdx.x & 63;
+  const int kc = lane & 15, kr = lane >> 4;
+  double* vm = g + 256;
+  double* tile = g + 16 * 16 * 2 + 16 * 3;
+  auto colof = [&](int k) { return k < kJB ? bi * kJB + k : bj * kJB + (k - kJB); };
+  const int col = colof(kc);
+  const bool ok = col < n;
+  // one base address per lane and constant offsets; rows past len are not read
+  const double* xc = X + (int64_t)(ok ? col : 0) * vs + kr;
+  double y[NB][8];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) y[b][i] = (ok && 32 * b + 4 * i + kr < len) ? xc[32 * b + 4 * i] : 0.0;
+  {
+    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int i = 0; i < 8; i += 2) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(y[b][i], y[b][i], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(y[b][i + 1], y[b][i + 1], acc1, 0, 0, 0);
+      }
+    block_gram_store(g, acc0, acc1, cmax2);
+  }
+  if (!block_inner_jacobi(g, tol)) return false;
+  // chunk (b, c): rows 32 b + 16 c + 4 i' + kr of slot kc in y[b][4 c + i'];
+  // transposed, lane l holds rows 16 (2 b + c) + l%16 of slots 4 kk + l/16
+  double bv[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) bv[kk] = vm[(kk * 4 + kr) * 16 + kc];
+  double* xo = X + (int64_t)(ok ? col : 0) * vs + kr;
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (32 * b + 16 * c >= len) continue;
+      double* tl = tile + 256 * c;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tl[(4 * u + kr) * 16 + kc] = y[b][4 * c + u];
+      wave_sync();
+      double a[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) a[kk] = tl[kc * 16 + 4 * kk + kr];
+      dbl4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) d = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], bv[kk], d, 0, 0, 0);
+      if (ok) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (32 * b + 16 * c + kr + 4 * v < len) xo[32 * b + 16 * c + 4 * v] = d[v];
+      }
+    }
+  return true;
+}
+
 // Sweeps of the blocked one-sided Jacobi over n columns of length len (column
 // stride vs, element stride 1); scratch holds kJBScratch doubles of LDS per
 // wavefront.  Returns the number of sweeps run and adds the flops done to
 // `work`: the 16 x 16 Gram matrix of every block-pair visit (512 len) and the
 // update Y V of the pairs that changed (512 len).
-template <int NT>
+template <int NT, int NB = 0>
 __device__ __forceinline__ int jacobi_block_sweeps(double* X, int64_t vs, int n, int len, double tol,
                                                    double* scratch, double* red, int* redi, double& work) {
   const int nblk = (n + kJB - 1) / kJB;
@@ -712,7 +797,12 @@ __device__ __forceinline__ int jacobi_block_sweeps(double* X, int64_t vs, int n,
         int bi, bj;
         tournament_pair(pi, round, nb, bi, bj);
         visits += lead;
-        if (jacobi_block_pair(X, vs, n, len, bi, bj, tol, g, cmax2)) {
+        bool ch;
+        if constexpr (NB > 0)
+          ch = jacobi_block_pair_reg<NB>(X, vs, n, len, bi, bj, tol, g, cmax2);
+        else
+          ch = jacobi_block_pair(X, vs, n, len, bi, bj, tol, g, cmax2);
+        if (ch) {
           rot = 1;
           visits += lead;
         }
@@ -765,8 +855,17 @@ __device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int
   const int gi = threadIdx.x / G, gl = threadIdx.x % G;
   const int nu = (len + G - 1) / G;
   if constexpr (BLOCKED) {
-    // contiguous vectors (es == 1) and kJBScratch doubles per wavefront
-    sweeps = jacobi_block_sweeps<NT>(V, vs, n, len, tol, bscratch, red, redi, work);
+    // contiguous vectors (es == 1) and kJBScratch doubles per wavefront; block
+    // pairs of vectors up to kJBRegRows long stay in registers during a visit
+    // (workgroups of at most 512 threads leave them the registers)
+    const int nbr = NT > 512 ? 0 : len <= 64 ? 2 : len <= 128 ? 4 : len <= 192 ? 6 : len <= kJBRegRows ? 8 : 0;
+    switch (nbr) {
+      case 2: sweeps = jacobi_block_sweeps<NT, 2>(V, vs, n, len, tol, bscratch, red, redi, work); break;
+      case 4: sweeps = jacobi_block_sweeps<NT, 4>(V, vs, n, len, tol, bscratch, red, redi, work); break;
+      case 6: sweeps = jacobi_block_sweeps<NT, 6>(V, vs, n, len, tol, bscratch, red, redi, work); break;
+      case 8: sweeps = jacobi_block_sweeps<NT, 8>(V, vs, n, len, tol, bscratch, red, redi, work); break;
+      default: sweeps = jacobi_block_sweeps<NT, 0>(V, vs, n, len, tol, bscratch, red, redi, work); break;
+    }
   } else switch (nu <= kCap ? nu : 0) {
 #define ACR_JAC_NU(k) \
   case k: sweeps = jacobi_sweeps<NT, (k <= kCap ? k : 0)>(V, vs, es, n, len, G, tol, red, redi, work); break;
@@ -1169,9 +1268,11 @@ template <class T>
 void launch_jacobi(const SvdTask* d_tasks, int ntasks, double eps, int* d_flags, size_t lds, hipStream_t s) {
   if (ntasks <= 0) return;
   if (lds == 0) {
-    const size_t scratch = (size_t)(1024 / 64) * kJBScratch * sizeof(double);
-    allow(k_jacobi<T, false, 1024>, scratch);
-    hipLaunchKernelGGL((k_jacobi<T, false, 1024>), dim3(ntasks), dim3(1024), scratch, s, d_tasks, eps, d_flags);
+    // blocked sweeps: 512 threads leave a wavefront the registers to hold a
+    // block pair of vectors up to kJBRegRows long
+    const size_t scratch = (size_t)(512 / 64) * kJBScratch * sizeof(double);
+    allow(k_jacobi<T, false, 512>, scratch);
+    hipLaunchKernelGGL((k_jacobi<T, false, 512>), dim3(ntasks), dim3(512), scratch, s, d_tasks, eps, d_flags);
     return;
   }
   if (lds <= kSmallLds) {

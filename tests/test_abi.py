@@ -48,6 +48,11 @@ def test_invalid_options_rejected_before_device_work(kw):
     assert code == 1 and not h.value
 
 
+def test_release_cached_memory_without_device_work():
+    # nothing was allocated in this process: the cache is empty
+    assert acr.release_cached_memory() == 0
+
+
 def test_null_arguments_rejected():
     L = acr.lib()
     h = ctypes.c_void_p()

@@ -226,17 +226,41 @@ def test_narrow_gemm_tiles_bitwise_equal(monkeypatch):
 
 @pytest.mark.parametrize("n,leaf,eps", [(24, 128, 1e-2), (32, 64, 1e-4), (16, 32, 1e-3)])
 def test_register_pchol_bitwise_equals_lds_kernel(n, leaf, eps, monkeypatch):
-    """The register-tiled pivoted Cholesky (no swaps) takes the same pivots and
-    does the same arithmetic per element as the right-looking LDS kernel
+    """The register-tiled pivoted Cholesky (no swaps; 5 x 5 tiles on 1024
+    threads, or 8 x 8 on 512 with ACR_PCHOL_TILES=512) takes the same pivots
+    and does the same arithmetic per element as the right-looking LDS kernel
     (ACR_PCHOL_LDS=1), so the factorisation and its solve are bitwise equal."""
     coef = torch.from_numpy(problem("convdiff", n)).to(DEV)
     b = torch.from_numpy(rhs_normal(n ** 3)).to(DEV)
     out = []
-    for flag in ("0", "1"):
-        monkeypatch.setenv("ACR_PCHOL_LDS", flag)
+    for lds, tiles in (("0", ""), ("0", "512"), ("1", "")):
+        monkeypatch.setenv("ACR_PCHOL_LDS", lds)
+        monkeypatch.setenv("ACR_PCHOL_TILES", tiles)
         fac = acr.Factor(coef, eps=eps, leaf=leaf, precision="fp32")
         out.append((fac.solve(b), fac.stats()))
         fac.free()
     torch.cuda.synchronize()
-    assert out[0][1]["max_rank"] == out[1][1]["max_rank"]
-    assert torch.equal(out[0][0], out[1][0])
+    for o in out[1:]:
+        assert out[0][1]["max_rank"] == o[1]["max_rank"]
+        assert torch.equal(out[0][0], o[0])
+
+
+def test_cached_device_memory_reused_and_released():
+    """Freed handles leave their device buffers in the library's cache; the
+    next factorisation of the same operator takes them over and gives bitwise
+    the same factors and solution; acr_release_cached_memory empties the
+    cache."""
+    n, leaf = 16, 32
+    coef = torch.from_numpy(problem("convdiff", n)).to(DEV)
+    b = torch.from_numpy(rhs_normal(n ** 3)).to(DEV)
+    acr.release_cached_memory()
+    out = []
+    for _ in range(3):
+        fac = acr.Factor(coef, eps=1e-2, leaf=leaf, precision="fp32")
+        out.append((fac.solve(b), fac.stats()["factor_bytes"]))
+        fac.free()
+    torch.cuda.synchronize()
+    for o in out[1:]:
+        assert torch.equal(out[0][0], o[0]) and o[1] == out[0][1]
+    assert acr.release_cached_memory() > 0
+    assert acr.release_cached_memory() == 0
