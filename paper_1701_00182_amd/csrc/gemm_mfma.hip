@@ -51,6 +51,25 @@ __device__ inline void tile_of(const GemmTask& t, int local, int& row0, int& col
   col0 = (local % ntn) * 64;
 }
 
+// A wavefront's 32 x 32 FP32 accumulator, computed transposed (D[v] holds
+// row r = lane row, column c0 + 8 (v / 4) + 4 (l / 32) + v % 4): C = alpha acc
+// + beta C with one row pointer per lane.
+__device__ inline void store_acc32(const GemmTask& t, int r, int c0, const f32x16& acc) {
+  const int lane = threadIdx.x & 63;
+  if (r >= t.m) return;
+  float* base = static_cast<float*>(t.C) + r;
+  const float al = (float)t.alpha, be = (float)t.beta;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int c = c0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    if (c >= t.n) continue;
+    float* p = base + (int64_t)c * t.ldc;
+    float x = al * acc[v];
+    if (t.beta != 0.0) x += be * *p;
+    *p = x;
+  }
+}
+
 // C(i, j) of the tile = alpha * v + beta * C(i, j)
 template <class T>
 __device__ inline void store_tile(const GemmTask& t, int row0, int col0, int i, int j, T v) {
@@ -91,10 +110,11 @@ template <class T, int KB, int P = 64> struct Stage {
 #pragma unroll
         for (int u = 0; u < VEC; ++u) v[s][u] = x[u];
       } else {
+        // element u sits at ptr + u along the contiguous dimension
 #pragma unroll
         for (int u = 0; u < VEC; ++u) {
           const int qp = pc ? gp + u : gp, qk = pc ? gk : gk + u;
-          v[s][u] = (qp < np && qk < K) ? base[qp * sp + qk * sk] : T(0);
+          v[s][u] = (qp < np && qk < K) ? ptr[u] : T(0);
         }
       }
     }
@@ -165,9 +185,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const GemmTask* __restrict__ t
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int v = 0; v < 16; ++v)
-    store_tile<float>(t, row0, col0, wr + (lane & 31), wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), acc[v]);
+  store_acc32(t, row0 + wr + (lane & 31), col0 + wc, acc);
 }
 
 // FP32 data, FP32 matrix cores, for outputs at most 32 columns wide (the
@@ -215,9 +233,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32_n32(const GemmTask* __restrict
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int v = 0; v < 16; ++v)
-    store_tile<float>(t, row0, 0, wr + (lane & 31), 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), acc[v]);
+  store_acc32(t, row0 + wr + (lane & 31), 0, acc);
 }
 
 // FP64 data, FP64 matrix cores.
@@ -387,9 +403,7 @@ __global__ __launch_bounds__(256) void k_gemm_lowp(const GemmTask* __restrict__ 
     for (int v = 0; v < 16; ++v) acc[v] += ldexpf(blk[v], ea + eb);
     __syncthreads();
   }
-#pragma unroll
-  for (int v = 0; v < 16; ++v)
-    store_tile<float>(t, row0, col0, wr + (lane & 31), wc + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), acc[v]);
+  store_acc32(t, row0 + wr + (lane & 31), col0 + wc, acc);
 }
 
 // Segmented GEMM: the inner dimension runs over the task's (A_s, B_s) pairs,
