@@ -155,6 +155,7 @@ class Exec {
   // d_tvals: device array of the tasks' t_out values (contiguous, in task order)
   template <class T> void svd(std::vector<SvdTask>& t, double eps, int* d_tvals);
   template <class T> void applyq(const std::vector<ApplyQTask>& t);
+  void tri_copy(const std::vector<TriCopyTask>& t);
   template <class T> void gram(const std::vector<GramTask>& t);
   void pchol(const std::vector<PcholTask>& t, double tol);
   void materialize_r(const std::vector<PcholTask>& t);
@@ -175,6 +176,7 @@ class Exec {
   bool pchol_lds = false;      // ACR_PCHOL_LDS=1: the right-looking LDS kernel instead of the register-tiled one
   bool pchol_512 = false;      // ACR_PCHOL_TILES=512: 512-thread 8 x 8 tiles for the whole large register-tiled kind
   bool gemm_narrow = true;     // ACR_GEMM_NARROW=0: FP32 outputs <= 32 columns wide in 64 x 64 tiles too
+  bool svd_lq = true;          // ACR_SVD_LQ=0: cores too large for LDS keep W^T in the blocked global sweeps
   int merge_cus = 0;           // compute units for merging LDS size classes into one launch (ACR_NO_MERGE=1: 0, off)
   int leaf_lowp = 0;           // leaf x leaf products with 16-bit inputs: 1 = BF16, 2 = FP16 (FP32 data)
   int prod_lowp = 0;           // every factorisation product without its own choice, as leaf_lowp

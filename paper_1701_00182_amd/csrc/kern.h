@@ -93,6 +93,16 @@ struct SvdTask {
   unsigned long long* flop_ctr;   // += flops counted on the device (sweeps, small cores, left factor)
 };
 
+// dst (n x n, ld n) = upper triangle of src (ld lds), zeros below; the next
+// n x n doubles of dst are cleared
+struct TriCopyTask {
+  const double* src;
+  double* dst;
+  int64_t lds;
+  int n;
+};
+void launch_tri_copy(const TriCopyTask* d_tasks, int ntasks, hipStream_t s);
+
 // out (m x k) = Q * [Z; 0] with Q the product of the panel's reflectors
 struct ApplyQTask {
   const void* Aq;   // reflectors (panel after QR)

@@ -330,6 +330,8 @@ void Exec::init(hipStream_t s, const Allocator& a) {
   inverse_unblocked = iu && iu[0] == '1';
   const char* gn = std::getenv("ACR_GEMM_NARROW");
   gemm_narrow = !(gn && gn[0] == '0');
+  const char* lq = std::getenv("ACR_SVD_LQ");
+  svd_lq = !(lq && lq[0] == '0');
   const char* pt = std::getenv("ACR_PCHOL_TILES");
   pchol_512 = pt && std::strcmp(pt, "512") == 0;
   const char* nm = std::getenv("ACR_NO_MERGE");
@@ -902,8 +904,44 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
   if (split) {
     rank_stage(1);
     std::swap(stream, side_);
-    if (svd_global) jacobi_batch(two[1], 0);
-    else bucketed(two[1], [](const SvdTask& x) { return lds_bytes_jacobi(x); }, jacobi_batch, merge_cus);
+    // Cores whose W^T (q x t) exceeds LDS but whose t x t triangle fits, with
+    // q > t: W^T = Q2 R2 (Householder QR in place), the scalar LDS sweeps on
+    // the columns of R2 (R2 J = Zr Sigma with the rotations J and values of
+    // W^T's sweeps), then Z = Q2 [Zr; 0].  The workspace C of the core (free
+    // once the pivoted QR has written W^T) holds R2, Zr and the reflector
+    // scales: 2 t^2 + t <= 2 p q doubles as p >= t and q > t.
+    std::vector<SvdTask> glob, red, redj;
+    std::vector<QrTask> rq;
+    std::vector<TriCopyTask> rc;
+    std::vector<ApplyQTask> ra;
+    for (auto& x : two[1]) {
+      const int tt = x.tc;
+      if (svd_lq && tt > 0 && x.q > tt && (size_t)tt * tt * 8 <= kLdsBudget) {
+        double* buf = x.C;
+        double* tau = x.C + 2 * (size_t)tt * tt;
+        rq.push_back(QrTask{x.Y, tau, x.q, x.q, tt});
+        rc.push_back(TriCopyTask{x.Y, buf, x.q, tt});
+        SvdTask r = x;
+        r.q = tt;
+        r.Y = buf;
+        redj.push_back(r);
+        ApplyQTask aq;
+        aq.Aq = x.Y; aq.tau = tau; aq.Z = buf + (size_t)tt * tt; aq.out = x.Y + (size_t)x.q * x.q;
+        aq.lda = x.q; aq.ldz = tt; aq.ldo = x.q; aq.m = x.q; aq.p = tt; aq.k = tt;
+        ra.push_back(aq);
+        red.push_back(x);
+      } else {
+        glob.push_back(x);
+      }
+    }
+    if (!redj.empty()) {
+      qr<double>(rq);
+      tri_copy(rc);
+      bucketed(redj, [](const SvdTask& x) { return lds_bytes_jacobi(x); }, jacobi_batch, merge_cus);
+      applyq<double>(ra);
+    }
+    if (svd_global) jacobi_batch(glob, 0);
+    else bucketed(glob, [](const SvdTask& x) { return lds_bytes_jacobi(x); }, jacobi_batch, merge_cus);
     left(two[1]);
     hip_check(hipEventRecord(ev_[2], stream), "hipEventRecord");
     std::swap(stream, side_);
@@ -1073,6 +1111,17 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
   if (!small.empty()) launch(small, lds_small);
   if (!large.empty()) launch(large, lds_large);
   if (!wide.empty()) launch(wide, 0);
+}
+
+void Exec::tri_copy(const std::vector<TriCopyTask>& t) {
+  if (t.empty()) return;
+  for (auto& x : t) {
+    check_range(x.src, sizeof(double) * ext(x.n, x.n, x.lds), "tri_copy source");
+    check_range(x.dst, sizeof(double) * 2 * (size_t)x.n * x.n, "tri_copy destination");
+  }
+  const TriCopyTask* dt = upload(t);
+  const int n = (int)t.size();
+  submit([=](hipStream_t s) { launch_tri_copy(dt, n, s); });
 }
 
 void Exec::materialize_r(const std::vector<PcholTask>& t) {

@@ -1236,6 +1236,20 @@ __global__ __launch_bounds__(256) void k_core_left(const SvdTask* __restrict__ t
   }
 }
 
+__global__ __launch_bounds__(256) void k_tri_copy(const TriCopyTask* __restrict__ tasks) {
+  const TriCopyTask t = tasks[blockIdx.x];
+  const int n = t.n;
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t e = threadIdx.x + (int64_t)blockIdx.y * 256; e < 2 * nn; e += 256 * (int64_t)gridDim.y) {
+    double v = 0.0;
+    if (e < nn) {
+      const int i = (int)(e % n), j = (int)(e / n);
+      if (i <= j) v = t.src[i + (int64_t)j * t.lds];
+    }
+    t.dst[e] = v;
+  }
+}
+
 template <class K> void allow(K kernel, size_t bytes) {
   if (bytes > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1314,6 +1328,11 @@ void launch_core_left(const SvdTask* d_tasks, int ntasks, int kc, int nchunks, s
   if (ntasks <= 0 || nchunks <= 0) return;
   allow(k_core_left<T>, lds);
   hipLaunchKernelGGL(k_core_left<T>, dim3(ntasks, nchunks), dim3(256), lds, s, d_tasks, kc, ctr);
+}
+
+void launch_tri_copy(const TriCopyTask* d_tasks, int ntasks, hipStream_t s) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_tri_copy, dim3(ntasks, 8), dim3(256), 0, s, d_tasks);
 }
 
 #define ACR_SVD_INST(T)                                                                                     \

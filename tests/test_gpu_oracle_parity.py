@@ -111,20 +111,24 @@ def _check_truncated(c, x, fac, tag):
     assert st["avg_rank"] <= 2 * max(oavg, 1.0)
 
 
-@pytest.mark.parametrize("path", ["default", "pchol_global", "svd_global"])
+@pytest.mark.parametrize("path", ["default", "pchol_global", "svd_global", "svd_global_blocked"])
 @pytest.mark.parametrize("eps", [1e-2, 1e-4])
 def test_fp32_headline_paths_vs_oracle(eps, path, monkeypatch):
     """Convection-diffusion n = 24, leaf 128, FP32 factors: the headline's Gram
     compression (FP64 Gram on matrix cores, pivoted Cholesky, two-kernel core
     SVD); `pchol_global` forces the left-looking pivoted Cholesky with L in
-    global memory for every stack, `svd_global` the global-memory pivoted QR
-    and blocked Jacobi sweeps for every core."""
+    global memory for every stack; `svd_global` the global-memory pivoted QR
+    for every core, then for cores with q > t the QR of W^T and LDS sweeps on
+    its triangle, blocked sweeps on W^T for the others; `svd_global_blocked`
+    blocked sweeps on W^T for every core (ACR_SVD_LQ=0)."""
     print(f"case fp32 headline path={path} eps={eps}", flush=True)
     c = _case("convdiff", 24, 128, eps)
     if path == "pchol_global":
         monkeypatch.setenv("ACR_PCHOL_GLOBAL", "1")
-    if path == "svd_global":
+    if path.startswith("svd_global"):
         monkeypatch.setenv("ACR_SVD_GLOBAL", "1")
+    if path == "svd_global_blocked":
+        monkeypatch.setenv("ACR_SVD_LQ", "0")
     fac = _gpu(c.coef, eps=eps, leaf=128, precision="fp32", svd_fused_lds=-1)
     x = _solve(fac, c.f)
     _check_truncated(c, x, fac, f"fp32 n=24 leaf128 eps={eps} {path}")
