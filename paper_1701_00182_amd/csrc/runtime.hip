@@ -909,7 +909,9 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
     // the columns of R2 (R2 J = Zr Sigma with the rotations J and values of
     // W^T's sweeps), then Z = Q2 [Zr; 0].  The workspace C of the core (free
     // once the pivoted QR has written W^T) holds R2, Zr and the reflector
-    // scales: 2 t^2 + t <= 2 p q doubles as p >= t and q > t.
+    // scales: 2 t^2 + t <= 2 p q doubles as p >= t and q > t.  (Blocked
+    // sweeps on R2 for triangles beyond LDS measured slower than on W^T: the
+    // QR and the reflector application lengthen the side stream.)
     std::vector<SvdTask> glob, red, redj;
     std::vector<QrTask> rq;
     std::vector<TriCopyTask> rc;
