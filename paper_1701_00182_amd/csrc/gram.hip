@@ -573,6 +573,8 @@ void launch_pchol_reg(const PcholTask* d_tasks, int ntasks, int max_r, double to
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol_reg<512, 8>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol_reg<512, 5>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_pchol_reg<1024, 5>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
@@ -580,6 +582,8 @@ void launch_pchol_reg(const PcholTask* d_tasks, int ntasks, int max_r, double to
     hipLaunchKernelGGL((k_pchol_reg<256, 4>), dim3(ntasks), dim3(256), lds, s, d_tasks, tol);
   else if (kind == 1)
     hipLaunchKernelGGL((k_pchol_reg<512, 8>), dim3(ntasks), dim3(512), lds, s, d_tasks, tol);
+  else if (kind == 3)
+    hipLaunchKernelGGL((k_pchol_reg<512, 5>), dim3(ntasks), dim3(512), lds, s, d_tasks, tol);
   else
     hipLaunchKernelGGL((k_pchol_reg<1024, 5>), dim3(ntasks), dim3(1024), lds, s, d_tasks, tol);
 }

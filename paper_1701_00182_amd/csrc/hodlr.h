@@ -175,6 +175,7 @@ class Exec {
   bool inverse_unblocked = false;  // ACR_INVERSE_UNBLOCKED=1: unblocked Gauss-Jordan for every inverse
   bool pchol_lds = false;      // ACR_PCHOL_LDS=1: the right-looking LDS kernel instead of the register-tiled one
   bool pchol_512 = false;      // ACR_PCHOL_TILES=512: 512-thread 8 x 8 tiles for the whole large register-tiled kind
+  bool pchol_mid = true;       // ACR_PCHOL_TILES=1024: orders 89-155 on 1024 threads too (else 512 threads, 5 x 5 tiles)
   bool gemm_narrow = true;     // ACR_GEMM_NARROW=0: FP32 outputs <= 32 columns wide in 64 x 64 tiles too
   bool svd_lq = true;          // ACR_SVD_LQ=0: cores too large for LDS keep W^T in the blocked global sweeps
   int merge_cus = 0;           // compute units for merging LDS size classes into one launch (ACR_NO_MERGE=1: 0, off)

@@ -229,11 +229,13 @@ template <class T> void launch_gram_mfma(const GramTask* d_tasks, const int* d_t
 // global memory (max_r bounds the tasks' orders)
 void launch_pchol(const PcholTask* d_tasks, int ntasks, int max_r, double tol, size_t lds_packed, hipStream_t s);
 // register-tiled pivoted Cholesky (no swaps): kind 0 for orders up to
-// kPcholRegSmall (256-thread workgroups, 4 x 4 tiles), kind 2 up to
-// kPcholReg1024 (1024 threads, 5 x 5 tiles), kind 1 up to kPcholReg (512
-// threads, 8 x 8 tiles: the same arithmetic with fewer, larger tiles);
-// overwrites the tasks' Gram buffers (the columns of L in original row order)
+// kPcholRegSmall (256-thread workgroups, 4 x 4 tiles), kind 3 up to
+// kPcholRegMid (512 threads, 5 x 5 tiles), kind 2 up to kPcholReg1024 (1024
+// threads, 5 x 5 tiles), kind 1 up to kPcholReg (512 threads, 8 x 8 tiles):
+// the same arithmetic per entry whatever the tiling; overwrites the tasks'
+// Gram buffers (the columns of L in original row order)
 constexpr int kPcholRegSmall = 88;
+constexpr int kPcholRegMid = 155;
 constexpr int kPcholReg1024 = 220;
 constexpr int kPcholReg = 248;
 void launch_pchol_reg(const PcholTask* d_tasks, int ntasks, int max_r, double tol, int kind, hipStream_t s);

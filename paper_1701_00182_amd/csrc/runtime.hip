@@ -334,6 +334,7 @@ void Exec::init(hipStream_t s, const Allocator& a) {
   svd_lq = !(lq && lq[0] == '0');
   const char* pt = std::getenv("ACR_PCHOL_TILES");
   pchol_512 = pt && std::strcmp(pt, "512") == 0;
+  pchol_mid = !(pt && std::strcmp(pt, "1024") == 0);
   const char* nm = std::getenv("ACR_NO_MERGE");
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) == hipSuccess &&
@@ -1043,18 +1044,26 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
   // (ACR_PCHOL_LDS=1: those whose packed lower triangle fits in LDS take the
   // right-looking LDS kernel instead), wider ones the left-looking one with L
   // in global memory; two launches at most per kind (finer size buckets
-  // serialise the batch).  Orders up to kPcholReg1024 take 5 x 5 tiles on
+  // serialise the batch).  Orders up to kPcholRegMid take 5 x 5 tiles on 512
+  // threads (their at most 465 tiles would leave over half of a 1024-thread
+  // workgroup idle in every step), orders up to kPcholReg1024 5 x 5 tiles on
   // 1024 threads (at n = 128 the class took 287 ms per factorisation against
   // 333 ms with 8 x 8 tiles on 512 threads), orders up to kPcholReg 8 x 8
-  // tiles (they went to the left-looking kernel before); ACR_PCHOL_TILES=512
-  // takes 8 x 8 tiles for every order above kPcholRegSmall.
-  std::vector<PcholTask> packed, wide, reg_small, reg_large, reg_big;
+  // tiles (they went to the left-looking kernel before).  ACR_PCHOL_TILES=512
+  // takes 8 x 8 tiles for every order above kPcholRegSmall, =1024 keeps the
+  // orders up to kPcholRegMid on 1024 threads.
+  std::vector<PcholTask> packed, wide, reg_small, reg_mid, reg_large, reg_big;
   int max_r = 1;
   for (auto& x : t) {
     if (!pchol_global && pchol_lds && lds_bytes_pchol_packed(x.r) <= kLdsBudget) {
       packed.push_back(x);
     } else if (!pchol_global && x.r <= kPcholReg) {
-      (x.r <= kPcholRegSmall ? reg_small : x.r <= kPcholReg1024 && !pchol_512 ? reg_large : reg_big).push_back(x);
+      (x.r <= kPcholRegSmall                   ? reg_small
+       : pchol_512                             ? reg_big
+       : x.r <= kPcholRegMid && pchol_mid      ? reg_mid
+       : x.r <= kPcholReg1024                  ? reg_large
+                                               : reg_big)
+          .push_back(x);
     } else {
       wide.push_back(x);
       max_r = std::max(max_r, x.r);
@@ -1068,7 +1077,7 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
     reg_large.insert(reg_large.end(), reg_small.begin(), reg_small.end());
     reg_small.clear();
   }
-  for (auto* b : {&reg_small, &reg_large, &reg_big}) {
+  for (auto* b : {&reg_small, &reg_mid, &reg_large, &reg_big}) {
     if (b->empty()) continue;
     Work w;
     w.cls = "pchol";
@@ -1078,7 +1087,7 @@ void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
     }
     const PcholTask* dt = upload(*b);
     const int n = (int)b->size();
-    const int kind = b == &reg_small ? 0 : b == &reg_large ? 2 : 1;
+    const int kind = b == &reg_small ? 0 : b == &reg_mid ? 3 : b == &reg_large ? 2 : 1;
     int rmax = 1;
     for (auto& x : *b) rmax = std::max(rmax, x.r);
     submit([=](hipStream_t s) { launch_pchol_reg(dt, n, rmax, tol, kind, s); }, w);

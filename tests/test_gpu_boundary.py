@@ -226,14 +226,15 @@ def test_narrow_gemm_tiles_bitwise_equal(monkeypatch):
 
 @pytest.mark.parametrize("n,leaf,eps", [(24, 128, 1e-2), (32, 64, 1e-4), (16, 32, 1e-3)])
 def test_register_pchol_bitwise_equals_lds_kernel(n, leaf, eps, monkeypatch):
-    """The register-tiled pivoted Cholesky (no swaps; 5 x 5 tiles on 1024
-    threads, or 8 x 8 on 512 with ACR_PCHOL_TILES=512) takes the same pivots
+    """The register-tiled pivoted Cholesky (no swaps; 5 x 5 tiles on 512 or
+    1024 threads by order, 8 x 8 on 512 with ACR_PCHOL_TILES=512, 5 x 5 on
+    1024 for every mid order with ACR_PCHOL_TILES=1024) takes the same pivots
     and does the same arithmetic per element as the right-looking LDS kernel
     (ACR_PCHOL_LDS=1), so the factorisation and its solve are bitwise equal."""
     coef = torch.from_numpy(problem("convdiff", n)).to(DEV)
     b = torch.from_numpy(rhs_normal(n ** 3)).to(DEV)
     out = []
-    for lds, tiles in (("0", ""), ("0", "512"), ("1", "")):
+    for lds, tiles in (("0", ""), ("0", "512"), ("0", "1024"), ("1", "")):
         monkeypatch.setenv("ACR_PCHOL_LDS", lds)
         monkeypatch.setenv("ACR_PCHOL_TILES", tiles)
         fac = acr.Factor(coef, eps=eps, leaf=leaf, precision="fp32")
