@@ -205,8 +205,13 @@ template <class T> void launch_inverse(const InvTask* d_tasks, int ntasks, int m
 // LDS-resident variants; `lds` is the dynamic shared memory per workgroup
 template <class T> void launch_qr_lds(const QrTask* d_tasks, int ntasks, size_t lds, hipStream_t s);
 template <class T> void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, hipStream_t s);
+// threads: the workgroup size that gives every core of the launch one pass
+// per round of its LDS-resident sweeps (rounded up to 256, 512 or 1024); for
+// the blocked sweeps in global memory (lds = 0), above 512 when a vector is
+// longer than kJBRegRows
+constexpr int kJBRegRows = 256;   // longest vectors of the register-resident blocked visit
 template <class T> void launch_jacobi(const SvdTask* d_tasks, int ntasks, double eps, int* d_flags, size_t lds,
-                                      hipStream_t s);
+                                      int threads, hipStream_t s);
 // Cores whose C fits in LDS: the pivoted QR, the sweeps and the right vectors
 // in one workgroup per core (one wavefront when p, q, r <= kSvdWave), with no
 // host round trip; larger cores: launch_qrcp, then launch_jacobi
@@ -251,7 +256,15 @@ constexpr size_t kLdsBudget = 156 * 1024;
 constexpr size_t kLdsPerCu = 160 * 1024;   // LDS of one compute unit
 constexpr size_t kSmallLds = 32 * 1024;   // LDS-resident tasks up to this size use 256-thread workgroups
 inline size_t lds_bytes_qr(const QrTask& t, size_t w) { return (size_t)t.m * t.r * w; }
-inline size_t lds_bytes_jacobi(const SvdTask& t) { return (size_t)t.q * t.tc * 8; }
+// Row stride of W^T (q x t) in LDS for the scalar sweeps: q rounded up to 8
+// modulo 16 doubles, so that the vectors that the 8-lane groups of a
+// wavefront read together start in different LDS banks (q itself where the
+// padding would not fit)
+__host__ __device__ inline int jacobi_ld(int q, int t) {
+  const int ld = q + ((8 - q) % 16 + 16) % 16;
+  return (size_t)ld * t * 8 <= kLdsBudget ? ld : q;
+}
+inline size_t lds_bytes_jacobi(const SvdTask& t) { return (size_t)jacobi_ld(t.q, t.tc) * t.tc * 8; }
 inline size_t lds_bytes_pchol_packed(int r) { return (size_t)r * (r + 1) / 2 * 8 + (size_t)r * 4; }
 // register-tiled pivoted Cholesky: the scaled column, the pivot diagonals and
 // kPcholChunk buffered columns of L (doubles), perm, posof, alive (ints)

@@ -851,9 +851,31 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
     }
     w.counter = ctr;
     w.flops_per_count = 1.0;
+    if (trace) {
+      // vectors (rows q) and columns (rank t) of the launch, by quartile
+      std::vector<int> qs, ts;
+      for (auto& x : bb) {
+        qs.push_back(x.q);
+        ts.push_back(x.tc);
+      }
+      std::sort(qs.begin(), qs.end());
+      std::sort(ts.begin(), ts.end());
+      const size_t m = qs.size();
+      std::fprintf(stderr, "[acr] jacobi lds=%zu cores=%zu q %d/%d/%d/%d t %d/%d/%d/%d\n", lds, m, qs[0],
+                   qs[m / 4], qs[m / 2], qs[m - 1], ts[0], ts[m / 4], ts[m / 2], ts[m - 1]);
+    }
+    // threads for one pass per round over every core's column pairs: 8 lanes
+    // per pair for vectors up to 128 long, 16 for longer ones (the blocked
+    // sweeps in global memory: 1024 threads once a vector exceeds the
+    // register-resident visit)
+    int threads = 0;
+    for (auto& x : bb) {
+      const int need = lds == 0 ? (x.q > kJBRegRows ? 1024 : 512) : (x.q <= 128 ? 8 : 16) * ((x.tc + 1) / 2);
+      threads = std::max(threads, need);
+    }
     const SvdTask* dt = upload(bb);
     const int n = (int)bb.size();
-    submit([=](hipStream_t s) { launch_jacobi<T>(dt, n, eps, fl, lds, s); }, w);
+    submit([=](hipStream_t s) { launch_jacobi<T>(dt, n, eps, fl, lds, threads, s); }, w);
   };
   // numerical ranks found by the pivoted QR, read back per stream
   std::vector<int> tv[2];

@@ -500,6 +500,147 @@ __device__ __forceinline__ int jacobi_sweeps(double* V, int64_t vs, int64_t es, 
   return sweeps;
 }
 
+// Block bounds [lo, hi) of block k at level l of the recursive halving of
+// [0, n) (first half = ceil): the bits of k, most significant first, pick the
+// half at each of the l splits.
+__device__ inline void rec_block(int n, int l, int k, int& lo, int& hi) {
+  lo = 0;
+  hi = n;
+  for (int d = l - 1; d >= 0; --d) {
+    const int mid = lo + (hi - lo + 1) / 2;
+    if ((k >> d) & 1) lo = mid;
+    else hi = mid;
+  }
+}
+
+// The sweeps of jacobi_svd for NU > 0 elements per lane in the recursive
+// pairing order: at level l = 0, 1, ... the columns are cut into 2^l blocks
+// by repeated halving, and in every block the first half S1 meets every
+// vector of the second half S2 in |S1| rounds (round r pairs S1[g] with
+// S2[(g + r) mod |S1|]).  Every pair is visited once per sweep, in n - 1 to
+// about n + log2(n) rounds.  While a level's groups fit the workgroup, each
+// group keeps its S1 vector in registers for the whole level and only the S2
+// vectors go through memory: one vector loaded and stored per pair and round
+// instead of two.  (Measured on pivoted-QR-preconditioned cores the order
+// also converges in fewer sweeps than the round-robin tournament.)  Returns
+// the number of sweeps and adds the flops to `work` as jacobi_sweeps does.
+template <int NT, int NU>
+__device__ __forceinline__ int jacobi_sweeps_rec(double* V, int64_t vs, int64_t es, int n, int len, int G,
+                                                 double tol, double* red, int* redi, double& work) {
+  const int groups = NT / G;
+  const int gi0 = threadIdx.x / G, gl = threadIdx.x % G;
+  const int st = (int)es;
+  const int il = gl + (NU - 1) * G;
+  const bool tail_ok = il < len;
+  auto load = [&](const double* x, double (&r)[NU]) {
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      if (u + 1 < NU) {
+        r[u] = x[(gl + u * G) * st];
+      } else {
+        const double v = x[(tail_ok ? il : len - 1) * st];
+        r[u] = tail_ok ? v : 0.0;
+      }
+    }
+  };
+  auto store = [&](double* x, const double (&r)[NU]) {
+#pragma unroll
+    for (int u = 0; u + 1 < NU; ++u) x[(gl + u * G) * st] = r[u];
+    if (tail_ok) x[il * st] = r[NU - 1];
+  };
+  // one pair step on register slices xr, yr; true when rotated
+  auto step = [&](double (&xr)[NU], double (&yr)[NU], double& cmax2) {
+    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      al = fma(xr[u], xr[u], al);
+      be = fma(yr[u], yr[u], be);
+      ga = fma(xr[u], yr[u], ga);
+    }
+    gsum3_dpp(al, be, ga, G);
+    cmax2 = fmax(cmax2, pair_cos2(al, be, ga));
+    double cs, sn;
+    if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const double x = xr[u], y = yr[u];
+      xr[u] = cs * x - sn * y;
+      yr[u] = sn * x + cs * y;
+    }
+    return true;
+  };
+  int sweeps = 0;
+  double nrot = 0.0;
+  double xr[NU], yr[NU];
+  for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
+    ++sweeps;
+    int rot = 0;
+    double cmax2 = 0.0;
+    for (int l = 0;; ++l) {
+      const int smax = (n + (1 << l) - 1) >> l;   // largest block at level l
+      if (smax <= 1) break;
+      const int m = (smax + 1) / 2, ng = (1 << l) * m;
+      if (ng <= groups) {
+        int lo = 0, hi = 0, g = gi0 % m;
+        bool act = gi0 < ng;
+        if (act) rec_block(n, l, gi0 / m, lo, hi);
+        const int mid = lo + (hi - lo + 1) / 2;
+        act = act && hi - lo > 1 && lo + g < mid;
+        if (act) load(V + (lo + g) * vs, xr);
+        for (int r = 0; r < m; ++r) {
+          if (act && r < mid - lo) {
+            const int j = (g + r) % (mid - lo);
+            if (mid + j < hi) {
+              double* yb = V + (mid + j) * vs;
+              load(yb, yr);
+              if (step(xr, yr, cmax2)) {
+                store(yb, yr);
+                rot = 1;
+                nrot += gl == 0 ? 1.0 : 0.0;
+              }
+            }
+          }
+          __syncthreads();
+        }
+        if (act) store(V + (lo + g) * vs, xr);
+        __syncthreads();
+      } else {
+        // more groups than the workgroup holds (the last levels, a round or
+        // two each): both vectors of a pair through memory
+        for (int r = 0; r < m; ++r) {
+          for (int gi = gi0; gi < ng; gi += groups) {
+            int lo, hi;
+            const int g = gi % m;
+            rec_block(n, l, gi / m, lo, hi);
+            const int mid = lo + (hi - lo + 1) / 2;
+            if (hi - lo <= 1 || lo + g >= mid || r >= mid - lo) continue;
+            const int j = (g + r) % (mid - lo);
+            if (mid + j >= hi) continue;
+            double* xb = V + (lo + g) * vs;
+            double* yb = V + (mid + j) * vs;
+            load(xb, xr);
+            load(yb, yr);
+            if (step(xr, yr, cmax2)) {
+              store(xb, xr);
+              store(yb, yr);
+              rot = 1;
+              nrot += gl == 0 ? 1.0 : 0.0;
+            }
+          }
+          __syncthreads();
+        }
+      }
+    }
+    if (!__syncthreads_or(rot)) break;
+    int dummy = 0;
+    block_argmax<NT>(cmax2, dummy, red, redi);
+    if (cmax2 <= tol) break;
+  }
+  const double rots = block_sum<NT>(nrot, red);
+  work += 6.0 * (double)len * ((double)sweeps * 0.5 * (double)n * (double)(n - 1) + rots);
+  return sweeps;
+}
+
 // ---- Blocked one-sided Jacobi for vectors in global memory ----------------
 //
 // The n columns are cut into blocks of kJB; each round of a cyclic tournament
@@ -514,7 +655,6 @@ constexpr int kJB = 8;
 // doubles of LDS per wavefront: G, V, rotation table, two 16 x 16 transpose tiles
 constexpr int kJBScratch = 16 * 16 * 2 + 16 * 3 + 2 * 256;
 constexpr int kJBInner = 1;                        // inner sweeps per block-pair visit
-constexpr int kJBRegRows = 256;                    // longest vectors of the register-resident visit
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -827,7 +967,7 @@ __device__ __forceinline__ int jacobi_block_sweeps(double* X, int64_t vs, int n,
 // is n ints of scratch, red / redi one slot per wavefront.  Groups have at
 // least min_g lanes (16 keeps global-memory vectors coalesced).  Returns k;
 // all threads call it.
-template <int NT, int min_g = 1, bool BLOCKED = false>
+template <int NT, int min_g = 1, bool BLOCKED = false, int CAP = 0>
 __device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int n, int len, const int* perm,
                                           double* sig, int* ord, double eps, const SvdTask& t, int* flags,
                                           double* red, int* redi, int& sweeps, double& work,
@@ -849,7 +989,7 @@ __device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int
   // 256 or more threads (at most 128 registers, so that several workgroups
   // share a compute unit), 16 in a single wavefront; wider groups (a second
   // pass per round) rather than streamed vectors when a slice would exceed it
-  constexpr int kCap = NT >= 256 ? 12 : 16;
+  constexpr int kCap = CAP > 0 ? CAP : NT >= 256 ? 12 : 16;
   while (G < 16 && (len + G - 1) / G > kCap) G <<= 1;
   const int groups = NT / G;
   const int gi = threadIdx.x / G, gl = threadIdx.x % G;
@@ -868,10 +1008,12 @@ __device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int
     }
   } else switch (nu <= kCap ? nu : 0) {
 #define ACR_JAC_NU(k) \
-  case k: sweeps = jacobi_sweeps<NT, (k <= kCap ? k : 0)>(V, vs, es, n, len, G, tol, red, redi, work); break;
+  case k: sweeps = jacobi_sweeps_rec<NT, (k <= kCap ? k : 1)>(V, vs, es, n, len, G, tol, red, redi, work); break;
     ACR_JAC_NU(1) ACR_JAC_NU(2) ACR_JAC_NU(3) ACR_JAC_NU(4) ACR_JAC_NU(5) ACR_JAC_NU(6) ACR_JAC_NU(7)
     ACR_JAC_NU(8) ACR_JAC_NU(9) ACR_JAC_NU(10) ACR_JAC_NU(11) ACR_JAC_NU(12) ACR_JAC_NU(13) ACR_JAC_NU(14)
-    ACR_JAC_NU(15) ACR_JAC_NU(16)
+    ACR_JAC_NU(15) ACR_JAC_NU(16) ACR_JAC_NU(17) ACR_JAC_NU(18) ACR_JAC_NU(19) ACR_JAC_NU(20) ACR_JAC_NU(21)
+    ACR_JAC_NU(22) ACR_JAC_NU(23) ACR_JAC_NU(24) ACR_JAC_NU(25) ACR_JAC_NU(26) ACR_JAC_NU(27) ACR_JAC_NU(28)
+    ACR_JAC_NU(29) ACR_JAC_NU(30) ACR_JAC_NU(31) ACR_JAC_NU(32)
 #undef ACR_JAC_NU
     default: sweeps = jacobi_sweeps<NT, 0>(V, vs, es, n, len, G, tol, red, redi, work); break;
   }
@@ -927,7 +1069,7 @@ __device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int
 // Jacobi stage of the cores whose pivoted QR ran in global memory: W^T
 // (q x t, from k_qrcp) in LDS when it fits (scalar sweeps), else in place in
 // global memory (blocked sweeps).
-template <class T, bool LDS, int NT>
+template <class T, bool LDS, int NT, int CAP = 0>
 __global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks, double eps, int* flags) {
   extern __shared__ double smj[];
   const SvdTask t = tasks[blockIdx.x];
@@ -940,8 +1082,10 @@ __global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks
   double* A = LDS ? smj : t.Y;
   __shared__ double red[NT / 64];
   __shared__ int redi[NT / 64];
+  const int ld = LDS ? jacobi_ld(rows, n) : rows;
   if (LDS)
-    staged_copy<NT>((int64_t)rows * n, [&](int64_t e) { return t.Y[e]; }, [&](int64_t e, double v) { A[e] = v; });
+    staged_copy<NT>((int64_t)rows * n, [&](int64_t e) { return t.Y[e]; },
+                    [&](int64_t e, double v) { A[(e / rows) * ld + e % rows] = v; });
   __syncthreads();
   int sweeps = 0;
   double work = 0.0;
@@ -949,8 +1093,8 @@ __global__ __launch_bounds__(NT) void k_jacobi(const SvdTask* __restrict__ tasks
   // Vectors in global memory take the blocked sweeps (LDS holds their
   // per-wavefront Gram and rotation matrices); the counters record the flops
   // the sweeps did.
-  const int k = jacobi_svd<NT, LDS ? 1 : 16, !LDS>(A, rows, 1, n, rows, nullptr, t.sig, t.perm, eps, t, flags,
-                                                   red, redi, sweeps, work, LDS ? nullptr : smj);
+  const int k = jacobi_svd<NT, LDS ? 1 : 16, !LDS, CAP>(A, ld, 1, n, rows, nullptr, t.sig, t.perm, eps, t, flags,
+                                                        red, redi, sweeps, work, LDS ? nullptr : smj);
   if (threadIdx.x == 0) {
     *t.rank_out = k;
     const unsigned long long f = (unsigned long long)work;
@@ -1258,10 +1402,10 @@ template <class K> void allow(K kernel, size_t bytes) {
 
 }  // namespace
 
-// Large-core stages run with 1024 threads when their LDS working set exceeds
-// kSmallLds (it already limits them to one or two workgroups per compute
-// unit; the extra wavefronts hide latency and shorten each core's critical
-// path), with 256 threads otherwise.
+// The pivoted QR of large cores runs with 1024 threads when its LDS working
+// set exceeds kSmallLds (it already limits them to one or two workgroups per
+// compute unit; the extra wavefronts hide latency and shorten each core's
+// critical path), with 256 threads otherwise.
 template <class T>
 void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, hipStream_t s) {
   if (ntasks <= 0) return;
@@ -1279,11 +1423,19 @@ void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, h
 }
 
 template <class T>
-void launch_jacobi(const SvdTask* d_tasks, int ntasks, double eps, int* d_flags, size_t lds, hipStream_t s) {
+void launch_jacobi(const SvdTask* d_tasks, int ntasks, double eps, int* d_flags, size_t lds, int threads,
+                   hipStream_t s) {
   if (ntasks <= 0) return;
   if (lds == 0) {
     // blocked sweeps: 512 threads leave a wavefront the registers to hold a
-    // block pair of vectors up to kJBRegRows long
+    // block pair of vectors up to kJBRegRows long; launches with longer
+    // vectors stream them, with a block pair per wavefront of 1024 threads
+    if (threads > 512) {
+      const size_t scratch = (size_t)(1024 / 64) * kJBScratch * sizeof(double);
+      allow(k_jacobi<T, false, 1024>, scratch);
+      hipLaunchKernelGGL((k_jacobi<T, false, 1024>), dim3(ntasks), dim3(1024), scratch, s, d_tasks, eps, d_flags);
+      return;
+    }
     const size_t scratch = (size_t)(512 / 64) * kJBScratch * sizeof(double);
     allow(k_jacobi<T, false, 512>, scratch);
     hipLaunchKernelGGL((k_jacobi<T, false, 512>), dim3(ntasks), dim3(512), scratch, s, d_tasks, eps, d_flags);
@@ -1294,8 +1446,21 @@ void launch_jacobi(const SvdTask* d_tasks, int ntasks, double eps, int* d_flags,
     hipLaunchKernelGGL((k_jacobi<T, true, 256>), dim3(ntasks), dim3(256), lds, s, d_tasks, eps, d_flags);
     return;
   }
-  allow(k_jacobi<T, true, 1024>, lds);
-  hipLaunchKernelGGL((k_jacobi<T, true, 1024>), dim3(ntasks), dim3(1024), lds, s, d_tasks, eps, d_flags);
+  // larger cores: the smallest workgroup that takes every column pair of a
+  // round at once, with 8 lanes per pair for vectors up to 128 long (16
+  // elements per lane) so that the per-pair work (sums across the lanes, the
+  // rotation) is shared by 8 pairs per wavefront; 1024 threads allow at most
+  // 12 elements per lane
+  if (threads <= 256) {
+    allow(k_jacobi<T, true, 256, 16>, lds);
+    hipLaunchKernelGGL((k_jacobi<T, true, 256, 16>), dim3(ntasks), dim3(256), lds, s, d_tasks, eps, d_flags);
+  } else if (threads <= 512) {
+    allow(k_jacobi<T, true, 512, 16>, lds);
+    hipLaunchKernelGGL((k_jacobi<T, true, 512, 16>), dim3(ntasks), dim3(512), lds, s, d_tasks, eps, d_flags);
+  } else {
+    allow(k_jacobi<T, true, 1024>, lds);
+    hipLaunchKernelGGL((k_jacobi<T, true, 1024>), dim3(ntasks), dim3(1024), lds, s, d_tasks, eps, d_flags);
+  }
 }
 
 // Cores whose LDS working set exceeds kSmallLds use 1024 threads (their LDS
@@ -1337,7 +1502,7 @@ void launch_tri_copy(const TriCopyTask* d_tasks, int ntasks, hipStream_t s) {
 
 #define ACR_SVD_INST(T)                                                                                     \
   template void launch_qrcp<T>(const SvdTask*, int, double, size_t, hipStream_t);                           \
-  template void launch_jacobi<T>(const SvdTask*, int, double, int*, size_t, hipStream_t);                   \
+  template void launch_jacobi<T>(const SvdTask*, int, double, int*, size_t, int, hipStream_t);                   \
   template void launch_svd_block<T>(const SvdTask*, int, double, double, int*, size_t, hipStream_t);        \
   template void launch_svd_wave<T>(const SvdTask*, int, double, double, int*, size_t, hipStream_t);         \
   template void launch_core_left<T>(const SvdTask*, int, int, int, size_t, unsigned long long*, hipStream_t);
