@@ -980,11 +980,12 @@ __device__ __forceinline__ int jacobi_svd(double* V, int64_t vs, int64_t es, int
   while (G > min_g && G * npairs > NT) G >>= 1;
   while (G > 1 && G > 2 * len) G >>= 1;
   // a pair counts as orthogonal once |<x, y>| <= tol |x| |y|: rounding level
-  // for exact factorisations, else 1e-4 eps (at most 1e-8) -- the vectors then
-  // carry errors of order tol and the values of order tol^2, far below the
-  // truncation at eps sigma_1, and the last sweep of the quadratic
-  // convergence is not needed
-  const double tol = fmax(fmax(1e-15, 2.3e-16 * (double)len), eps > 0.0 ? fmin(1e-8, 1e-4 * eps) : 0.0);
+  // for exact factorisations, else 1e-4 eps (at most 1e-6) -- the vectors then
+  // carry errors of order tol and the values of order tol^2, four orders of
+  // magnitude or more below the truncation at eps sigma_1, and the last
+  // sweeps of the quadratic convergence are not needed (at eps = 1e-2 the
+  // headline's ranks and GMRES iterations are the same as with 1e-8)
+  const double tol = fmax(fmax(1e-15, 2.3e-16 * (double)len), eps > 0.0 ? fmin(1e-6, 1e-4 * eps) : 0.0);
   // register-resident slices of up to 12 elements per lane in workgroups of
   // 256 or more threads (at most 128 registers, so that several workgroups
   // share a compute unit), 16 in a single wavefront; wider groups (a second
