@@ -751,7 +751,11 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
       if (x.ldu < x.p || x.ldv < x.q) throw Failure(ST_HIP, "bounds check: svd ld");
       if (x.r < x.p || x.r < x.q) throw Failure(ST_HIP, "bounds check: svd core shape");
     }
-  const double delta = eps > 0.0 ? 0.01 * eps : 0.0;
+  // the pivoted QR drops a trailing block of Frobenius norm at most delta
+  // times the core's largest column norm (<= sigma_1): with delta = eps / 10
+  // the compression error stays within 1.1 eps sigma_1, and only values within
+  // eps sigma_1 / 10 of the threshold can change their side of it
+  const double delta = eps > 0.0 ? 0.1 * eps : 0.0;
   int* fl = d_flags;
   for (auto& x : t) x.flop_ctr = d_svd_flops;
   std::vector<SvdTask> small, mid, big;
