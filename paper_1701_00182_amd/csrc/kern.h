@@ -197,7 +197,18 @@ void launch_gemm_narrow(const GemmTask* d_tasks, const int* d_tile_task, const i
                         hipStream_t s);
 template <class T> void launch_seg_gemm(const SegGemmTask* d_tasks, const int* d_tile_task, const int* d_first_tile,
                                         int ntiles, hipStream_t s);
-// units: workgroups per task (each takes (column, 2048-row chunk) units in turn)
+// Work units of a copy: columns of at most kCopyUnit elements go whole, as
+// many as fit in kCopyUnit elements per unit; longer columns in kCopyUnit-row
+// chunks.
+constexpr int kCopyUnit = 2048;
+__host__ __device__ inline int copy_cols_per_unit(int m) { return m >= kCopyUnit || m <= 0 ? 1 : kCopyUnit / m; }
+__host__ __device__ inline int64_t copy_units(int m, int n) {
+  if (m <= 0 || n <= 0) return 0;
+  if (m > kCopyUnit) return (int64_t)n * ((m + kCopyUnit - 1) / kCopyUnit);
+  const int cpu = copy_cols_per_unit(m);
+  return (n + cpu - 1) / cpu;
+}
+// units: workgroups per task (each takes the task's units in turn)
 template <class T> void launch_copy(const CopyTask* d_tasks, int ntasks, int units, hipStream_t s);
 // unblocked = true forces the unblocked Gauss-Jordan kernel
 template <class T> void launch_inverse(const InvTask* d_tasks, int ntasks, int max_s,

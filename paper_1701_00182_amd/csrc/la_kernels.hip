@@ -40,49 +40,96 @@ __global__ __launch_bounds__(256) void k_copy(const CopyTask* __restrict__ tasks
   const T* rs = static_cast<const T*>(t.rs);
   const T* cs = static_cast<const T*>(t.cs);
   const T alpha = T(t.alpha);
-  // units of (column, 2048-row chunk): one division per unit, none per element
-  const int ich = (t.m + 2047) / 2048;
-  const int64_t units = (int64_t)t.n * ich;
-  for (int64_t u = blockIdx.y; u < units; u += gridDim.y) {
-    const int j = (int)(u / ich), i0 = (int)(u % ich) * 2048;
-    const int i1 = t.m < i0 + 2048 ? t.m : i0 + 2048;
-    const T csj = cs ? cs[j] : T(1);
-    const T* sc = src ? src + (int64_t)j * t.lds : nullptr;
-    T* dc = dst + (int64_t)j * t.ldd;
-    int i = i0 + threadIdx.x;
-    // 16-byte vectors when every column pointer is aligned at the chunk start
-    if (sc && aligned16(sc + i0) && aligned16(dc + i0) && (!rs || aligned16(rs + i0))) {
-      const int nv = (i1 - i0) / VN;
-      for (int e = threadIdx.x; e < nv; e += 256) {
-        const int ib = i0 + e * VN;
-        V x = *reinterpret_cast<const V*>(sc + ib);
-        T* xv = reinterpret_cast<T*>(&x);
-        V rv;
-        if (rs) rv = *reinterpret_cast<const V*>(rs + ib);
-        const T* rsv = reinterpret_cast<const T*>(&rv);
-        V y;
-        if (t.accumulate) y = *reinterpret_cast<const V*>(dc + ib);
-        T* yv = reinterpret_cast<T*>(&y);
-        V o;
-        T* ov = reinterpret_cast<T*>(&o);
+  const int64_t units = copy_units(t.m, t.n);
+  const int ich = (t.m + kCopyUnit - 1) / kCopyUnit;
+  const int cpu = copy_cols_per_unit(t.m);
+  // one VN-element slot: rows i .. i + nv - 1 of column j, 16-byte accesses
+  // when the whole slot is there and aligned
+  struct Slot {
+    T x[VN], r[VN], y[VN];
+    T* d;
+    T csj;
+    int i, j, nv;
+    bool vec;
+  };
+  auto load = [&](Slot& q) {
+    const T* sc = src ? src + (int64_t)q.j * t.lds + q.i : nullptr;
+    q.d = dst + (int64_t)q.j * t.ldd + q.i;
+    q.csj = cs ? cs[q.j] : T(1);
+    q.vec = q.nv == VN && aligned16(sc) && aligned16(q.d) && (!rs || aligned16(rs + q.i));
+    if (q.vec) {
+      if (sc) *reinterpret_cast<V*>(q.x) = *reinterpret_cast<const V*>(sc);
+      if (rs) *reinterpret_cast<V*>(q.r) = *reinterpret_cast<const V*>(rs + q.i);
+      if (t.accumulate) *reinterpret_cast<V*>(q.y) = *reinterpret_cast<const V*>(q.d);
+    } else {
+      // unrolled with a predicate per element, so the slot stays in registers
 #pragma unroll
-        for (int c = 0; c < VN; ++c) {
-          T v = alpha * xv[c];
-          if (rs) v *= rsv[c];
-          v *= csj;
-          if (t.accumulate) v += yv[c];
-          ov[c] = v;
+      for (int c = 0; c < VN; ++c) {
+        if (c < q.nv) {
+          if (sc) q.x[c] = sc[c];
+          if (rs) q.r[c] = rs[q.i + c];
+          if (t.accumulate) q.y[c] = q.d[c];
         }
-        *reinterpret_cast<V*>(dc + ib) = o;
       }
-      i = i0 + nv * VN + threadIdx.x;
     }
-    for (; i < i1; i += 256) {
-      T v = sc ? alpha * sc[i] : (i == j ? alpha : T(0));
-      if (rs) v *= rs[i];
-      v *= csj;
-      if (t.accumulate) v += dc[i];
-      dc[i] = v;
+    if (!sc)
+#pragma unroll
+      for (int c = 0; c < VN; ++c) q.x[c] = q.i + c == q.j ? T(1) : T(0);
+  };
+  auto store = [&](Slot& q) {
+    T o[VN];
+#pragma unroll
+    for (int c = 0; c < VN; ++c) {
+      T v = alpha * q.x[c];
+      if (rs) v *= q.r[c];
+      v *= q.csj;
+      if (t.accumulate) v += q.y[c];
+      o[c] = v;
+    }
+    if (q.vec) {
+      *reinterpret_cast<V*>(q.d) = *reinterpret_cast<const V*>(o);
+    } else {
+#pragma unroll
+      for (int c = 0; c < VN; ++c)
+        if (c < q.nv) q.d[c] = o[c];
+    }
+  };
+  for (int64_t u = blockIdx.y; u < units; u += gridDim.y) {
+    // the unit's columns c0 .. c1 - 1, rows r0 .. r1 - 1 of each
+    int c0, c1, r0, r1;
+    if (t.m > kCopyUnit) {
+      c0 = (int)(u / ich);
+      c1 = c0 + 1;
+      r0 = (int)(u % ich) * kCopyUnit;
+      r1 = t.m < r0 + kCopyUnit ? t.m : r0 + kCopyUnit;
+    } else {
+      c0 = (int)u * cpu;
+      c1 = t.n < c0 + cpu ? t.n : c0 + cpu;
+      r0 = 0;
+      r1 = t.m;
+    }
+    const int spc = (r1 - r0 + VN - 1) / VN;   // slots per column
+    const int cnt = (c1 - c0) * spc;
+    // two slots per thread per pass, both loaded before either is stored
+    for (int e = threadIdx.x; e < cnt; e += 512) {
+      Slot a, b;
+      const bool hb = e + 256 < cnt;
+      {
+        const int jj = e / spc, v = e - jj * spc;
+        a.j = c0 + jj;
+        a.i = r0 + v * VN;
+        a.nv = r1 - a.i < VN ? r1 - a.i : VN;
+      }
+      if (hb) {
+        const int e2 = e + 256, jj = e2 / spc, v = e2 - jj * spc;
+        b.j = c0 + jj;
+        b.i = r0 + v * VN;
+        b.nv = r1 - b.i < VN ? r1 - b.i : VN;
+      }
+      load(a);
+      if (hb) load(b);
+      store(a);
+      if (hb) store(b);
     }
   }
 }

@@ -671,13 +671,21 @@ template <class T> void Exec::copy(const std::vector<CopyTask>& t) {
   Work w;
   w.cls = "copy";
   for (auto& x : t) w.bytes += sizeof(T) * (double)x.m * x.n * ((x.src ? 1 : 0) + 1 + (x.accumulate ? 1 : 0));
-  int64_t units = 1;
-  for (auto& x : t) units = std::max<int64_t>(units, (int64_t)x.n * ((x.m + 2047) / 2048));
-  // workgroups per task along y: at least 64, and enough that a launch of few
-  // tasks still spreads over the whole chip (about 4096 workgroups; a single
-  // large copy on 64 workgroups ran one column chunk after another)
+  // workgroups per task along y: enough that the launch has about 8192
+  // workgroups (a single large copy spreads over the chip) and that no
+  // workgroup takes more than 32 units of the largest task, at most that
+  // task's units (short columns share a unit, so a launch of many small
+  // blocks does not pay for idle workgroups)
+  int64_t units = 1, total = 0;
+  for (auto& x : t) {
+    const int64_t u = copy_units(x.m, x.n);
+    units = std::max<int64_t>(units, u);
+    total += u;
+  }
   const int n = (int)t.size();
-  const int gy = (int)std::min<int64_t>(units, std::max<int64_t>(64, (4096 + n - 1) / n));
+  const int64_t per = (total + n - 1) / n;   // mean units per task
+  const int64_t want = std::max<int64_t>({(8192 + n - 1) / n, (units + 31) / 32, std::min<int64_t>(per, 4)});
+  const int gy = (int)std::min<int64_t>({units, want, 65535});
   const CopyTask* dt = upload(t);
   submit([=](hipStream_t s) { launch_copy<T>(dt, n, gy, s); }, w);
 }
