@@ -19,18 +19,50 @@ namespace acr {
 namespace {
 
 __global__ __launch_bounds__(256) void k_gram_reduce(const GramTask* __restrict__ tasks) {
+  __shared__ double tile[32][33];
   const GramTask t = tasks[blockIdx.x];
+  const int r = t.r;
   const int nchunk = (t.m + t.rows_per_chunk - 1) / t.rows_per_chunk;
-  // r^2 fits 32 bits (the host rejects wider stacks): 32-bit division for the
-  // element index, not the much longer 64-bit one
-  const int rr = t.r * t.r;
-  for (int e = threadIdx.x + blockIdx.y * 256; e < rr; e += gridDim.y * 256) {
-    const int i = e % t.r, j = e / t.r;
-    if (i > j) continue;
-    double s = 0.0;
-    for (int c = 0; c < nchunk; ++c) s += t.part[(int64_t)c * rr + e];
-    t.G[i + (int64_t)j * t.r] = s;
-    t.G[j + (int64_t)i * t.r] = s;
+  // r^2 fits 32 bits (the host rejects wider stacks)
+  const int rr = r * r;
+  const int nb = (r + 31) / 32, ntile = nb * (nb + 1) / 2;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // 32 x 32 tiles (bi, bj), bi <= bj, of the upper triangle, column by
+  // column: the sums of the chunk partials in chunk order for the entries
+  // i <= j, stored in place and, through the LDS tile, at the mirrored
+  // position, both with consecutive lanes on consecutive rows
+  for (int tt = blockIdx.y; tt < ntile; tt += gridDim.y) {
+    int bj = (int)((sqrtf(8.0f * (float)tt + 1.0f) - 1.0f) * 0.5f);
+    while (bj > 0 && bj * (bj + 1) / 2 > tt) --bj;
+    while ((bj + 1) * (bj + 2) / 2 <= tt) ++bj;
+    const int bi = tt - bj * (bj + 1) / 2;
+    const int i = bi * 32 + tx;
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < r) {
+      const double* p = t.part + i;
+#pragma unroll 4
+      for (int c = 0; c < nchunk; ++c) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int j = bj * 32 + ty + 8 * k;
+          if (j < r) sum[k] += p[(int64_t)c * rr + (int64_t)j * r];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = bj * 32 + ty + 8 * k;
+      if (i < r && j < r && (bi < bj || i <= j)) t.G[i + (int64_t)j * r] = sum[k];
+      tile[ty + 8 * k][tx] = sum[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      // entry (row, col) = (bj * 32 + tx, bi * 32 + ty + 8 k) mirrors (col, row)
+      const int row = bj * 32 + tx, col = bi * 32 + ty + 8 * k;
+      if (row < r && col < r && (bi < bj || col < row)) t.G[row + (int64_t)col * r] = tile[tx][ty + 8 * k];
+    }
+    __syncthreads();
   }
 }
 
@@ -538,10 +570,10 @@ __global__ __launch_bounds__(256) void k_wtilde(const WtTask* __restrict__ tasks
 
 template <class T>
 void launch_gram(const GramTask* d_tasks, int ntasks, const int* d_tile_task, const int* d_first_tile, int ntiles,
-                 hipStream_t s) {
+                 int reduce_wgs, hipStream_t s) {
   if (ntasks <= 0) return;
   launch_gram_mfma<T>(d_tasks, d_tile_task, d_first_tile, ntiles, s);
-  hipLaunchKernelGGL(k_gram_reduce, dim3(ntasks, 16), dim3(256), 0, s, d_tasks);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(ntasks, reduce_wgs), dim3(256), 0, s, d_tasks);
 }
 
 void launch_pchol(const PcholTask* d_tasks, int ntasks, int max_r, double tol, size_t lds_packed, hipStream_t s) {
@@ -602,8 +634,8 @@ void launch_wtilde(const WtTask* d_tasks, int ntasks, int kc, int nchunks, size_
   hipLaunchKernelGGL(k_wtilde<T>, dim3(ntasks, nchunks), dim3(256), lds, s, d_tasks, kc);
 }
 
-template void launch_gram<float>(const GramTask*, int, const int*, const int*, int, hipStream_t);
-template void launch_gram<double>(const GramTask*, int, const int*, const int*, int, hipStream_t);
+template void launch_gram<float>(const GramTask*, int, const int*, const int*, int, int, hipStream_t);
+template void launch_gram<double>(const GramTask*, int, const int*, const int*, int, int, hipStream_t);
 template void launch_wtilde<float>(const WtTask*, int, int, int, size_t, hipStream_t);
 template void launch_wtilde<double>(const WtTask*, int, int, int, size_t, hipStream_t);
 

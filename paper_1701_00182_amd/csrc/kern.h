@@ -234,8 +234,10 @@ template <class T> void launch_svd_block(const SvdTask* d_tasks, int ntasks, dou
 template <class T> void launch_core_left(const SvdTask* d_tasks, int ntasks, int kc, int nchunks, size_t lds,
                                          unsigned long long* ctr, hipStream_t s);
 template <class T> void launch_applyq_lds(const ApplyQTask* d_tasks, int ntasks, size_t lds, hipStream_t s);
+// reduce_wgs: workgroups per task of the ordered sum of the chunk partials
+// (each takes 32 x 32 tiles of the upper triangle in turn)
 template <class T> void launch_gram(const GramTask* d_tasks, int ntasks, const int* d_tile_task,
-                                   const int* d_first_tile, int ntiles, hipStream_t s);
+                                   const int* d_first_tile, int ntiles, int reduce_wgs, hipStream_t s);
 // chunk partials of the Gram on the matrix cores (workgroup map: four
 // wavefronts per workgroup, one per row chunk x upper pair of 32-column blocks)
 template <class T> void launch_gram_mfma(const GramTask* d_tasks, const int* d_tile_task, const int* d_first_tile,

@@ -1061,7 +1061,15 @@ template <class T> void Exec::gram(const std::vector<GramTask>& t) {
   const int *dtt, *dft;
   upload3(t, tile_task, first, &dt, &dtt, &dft);
   const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_gram<T>(dt, n, dtt, dft, nt, s); }, w);
+  // reduction: about 4096 workgroups per launch, at most 16 upper-triangle
+  // tiles of the widest stack per workgroup
+  int max_tiles = 1;
+  for (auto& x : t) {
+    const int nb = (x.r + 31) / 32;
+    max_tiles = std::max(max_tiles, nb * (nb + 1) / 2);
+  }
+  const int rw = std::min({max_tiles, std::max((4096 + n - 1) / n, (max_tiles + 15) / 16), 65535});
+  submit([=](hipStream_t s) { launch_gram<T>(dt, n, dtt, dft, nt, rw, s); }, w);
 }
 
 void Exec::pchol(const std::vector<PcholTask>& t, double tol) {
