@@ -488,11 +488,27 @@ __global__ __launch_bounds__(NT) void k_pchol_reg(const PcholTask* __restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_materialize_r(const PcholTask* __restrict__ tasks) {
+  __shared__ double tile[32][33];
   const PcholTask t = tasks[blockIdx.x];
   const int r = t.r, r1 = t.r1;
-  for (int e = threadIdx.x + blockIdx.y * 256; e < r1 * r; e += gridDim.y * 256) {
-    const int a = e % r1, i = e / r1;
-    t.R[a + (int64_t)t.perm[i] * r1] = i >= a ? t.L[i + (int64_t)a * r] : 0.0;
+  const int nba = (r1 + 31) / 32, nbi = (r + 31) / 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // 32 x 32 tiles of R (rows a, pivot positions i): L read with consecutive
+  // lanes on consecutive i, R written with consecutive lanes on consecutive a
+  for (int tt = blockIdx.y; tt < nba * nbi; tt += gridDim.y) {
+    const int ba = tt % nba, bi = tt / nba;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = bi * 32 + tx, a = ba * 32 + ty + 8 * k;
+      tile[ty + 8 * k][tx] = (i < r && a < r1 && i >= a) ? t.L[i + (int64_t)a * r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int a = ba * 32 + tx, i = bi * 32 + ty + 8 * k;
+      if (a < r1 && i < r) t.R[a + (int64_t)t.perm[i] * r1] = tile[tx][ty + 8 * k];
+    }
+    __syncthreads();
   }
 }
 
@@ -620,9 +636,9 @@ void launch_pchol_reg(const PcholTask* d_tasks, int ntasks, int max_r, double to
     hipLaunchKernelGGL((k_pchol_reg<1024, 5>), dim3(ntasks), dim3(1024), lds, s, d_tasks, tol);
 }
 
-void launch_materialize_r(const PcholTask* d_tasks, int ntasks, hipStream_t s) {
+void launch_materialize_r(const PcholTask* d_tasks, int ntasks, int wgs, hipStream_t s) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_materialize_r, dim3(ntasks, 8), dim3(256), 0, s, d_tasks);
+  hipLaunchKernelGGL(k_materialize_r, dim3(ntasks, wgs), dim3(256), 0, s, d_tasks);
 }
 
 template <class T>

@@ -257,7 +257,7 @@ constexpr int kPcholRegMid = 155;
 constexpr int kPcholReg1024 = 220;
 constexpr int kPcholReg = 248;
 void launch_pchol_reg(const PcholTask* d_tasks, int ntasks, int max_r, double tol, int kind, hipStream_t s);
-void launch_materialize_r(const PcholTask* d_tasks, int ntasks, hipStream_t s);
+void launch_materialize_r(const PcholTask* d_tasks, int ntasks, int wgs, hipStream_t s);
 template <class T> void launch_wtilde(const WtTask* d_tasks, int ntasks, int kc, int nchunks, size_t lds,
                                       hipStream_t s);
 // vec: the 16-byte vector kernels (every task's sizes, leading dimensions and

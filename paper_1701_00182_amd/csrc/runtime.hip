@@ -1180,9 +1180,14 @@ void Exec::tri_copy(const std::vector<TriCopyTask>& t) {
 void Exec::materialize_r(const std::vector<PcholTask>& t) {
   if (t.empty()) return;
   for (auto& x : t) check_range(x.R, sizeof(double) * (size_t)x.r1 * x.r, "materialize R");
-  const PcholTask* dt = upload(t);
+  // about 4096 workgroups per launch, at most 16 32 x 32 tiles of the largest
+  // R per workgroup
+  int max_tiles = 1;
+  for (auto& x : t) max_tiles = std::max(max_tiles, ((x.r1 + 31) / 32) * ((x.r + 31) / 32));
   const int n = (int)t.size();
-  submit([=](hipStream_t s) { launch_materialize_r(dt, n, s); });
+  const int wgs = std::min({max_tiles, std::max((4096 + n - 1) / n, (max_tiles + 15) / 16), 65535});
+  const PcholTask* dt = upload(t);
+  submit([=](hipStream_t s) { launch_materialize_r(dt, n, wgs, s); });
 }
 
 template <class T> void Exec::wtilde(const std::vector<WtTask>& t) {
