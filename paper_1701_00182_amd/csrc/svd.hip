@@ -391,6 +391,13 @@ __device__ inline double pair_cos2(double al, double be, double ga) {
   return ab > 0.0 ? ga * ga * rcp_nr(ab) : 0.0;
 }
 
+// 1 when a pair's squared |cos| exceeds tol (the stopping rule of the scalar
+// sweeps only asks whether any pair does), else 0: no division per pair.
+__device__ inline double pair_over(double al, double be, double ga, double tol) {
+  const double ab = al * be;
+  return ab > 0.0 && ga * ga > tol * ab ? 1.0 : 0.0;
+}
+
 // One Jacobi step on the vector pair (xa, xb) of length len (element i at
 // index i * st), handled by the G lanes of a group (gl = lane in group): the
 // three inner products, the rotation and its application.  With NU > 0 every
@@ -398,7 +405,8 @@ __device__ inline double pair_cos2(double al, double be, double ga) {
 // the products and the update, and the loops unroll without branches: rows of
 // lanes before the last are full, the last one loads through a clamped index
 // and stores under a mask.  NU = 0 streams the vectors twice.  Returns whether
-// a rotation was applied; cmax2 takes the pair's squared |cos| before it.
+// a rotation was applied; cmax2 becomes 1 when the pair's squared |cos| before
+// it exceeds tol.
 template <int NU>
 __device__ __forceinline__ bool jacobi_pair(double* xa, double* xb, int st, int len, int G, int gl, double tol,
                                    double& cmax2) {
@@ -411,7 +419,7 @@ __device__ __forceinline__ bool jacobi_pair(double* xa, double* xb, int st, int 
       ga += x * y;
     }
     gsum3_dpp(al, be, ga, G);
-    cmax2 = fmax(cmax2, pair_cos2(al, be, ga));
+    cmax2 = fmax(cmax2, pair_over(al, be, ga, tol));
     double cs, sn;
     if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
     for (int i = gl; i < len; i += G) {
@@ -444,7 +452,7 @@ __device__ __forceinline__ bool jacobi_pair(double* xa, double* xb, int st, int 
     ga = fma(xr[u], yr[u], ga);
   }
   gsum3_dpp(al, be, ga, G);
-  cmax2 = fmax(cmax2, pair_cos2(al, be, ga));
+  cmax2 = fmax(cmax2, pair_over(al, be, ga, tol));
   double cs, sn;
   if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
 #pragma unroll
@@ -491,9 +499,9 @@ __device__ __forceinline__ int jacobi_sweeps(double* V, int64_t vs, int64_t es, 
       __syncthreads();
     }
     if (!__syncthreads_or(rot)) break;
-    int dummy = 0;
-    block_argmax<NT>(cmax2, dummy, red, redi);
-    if (cmax2 <= tol) break;
+    // no pair of this sweep had squared |cos| above tol: quadratic convergence
+    // leaves every pair within about tol of orthogonal
+    if (!__syncthreads_or(cmax2 > 0.0)) break;
   }
   const double rots = block_sum<NT>(nrot, red);
   work += 6.0 * (double)len * ((double)sweeps * 0.5 * (double)n * (double)(n - 1) + rots);
@@ -558,7 +566,7 @@ __device__ __forceinline__ int jacobi_sweeps_rec(double* V, int64_t vs, int64_t 
       ga = fma(xr[u], yr[u], ga);
     }
     gsum3_dpp(al, be, ga, G);
-    cmax2 = fmax(cmax2, pair_cos2(al, be, ga));
+    cmax2 = fmax(cmax2, pair_over(al, be, ga, tol));
     double cs, sn;
     if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
 #pragma unroll
@@ -632,9 +640,9 @@ __device__ __forceinline__ int jacobi_sweeps_rec(double* V, int64_t vs, int64_t 
       }
     }
     if (!__syncthreads_or(rot)) break;
-    int dummy = 0;
-    block_argmax<NT>(cmax2, dummy, red, redi);
-    if (cmax2 <= tol) break;
+    // no pair of this sweep had squared |cos| above tol: quadratic convergence
+    // leaves every pair within about tol of orthogonal
+    if (!__syncthreads_or(cmax2 > 0.0)) break;
   }
   const double rots = block_sum<NT>(nrot, red);
   work += 6.0 * (double)len * ((double)sweeps * 0.5 * (double)n * (double)(n - 1) + rots);
