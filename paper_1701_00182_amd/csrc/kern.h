@@ -215,7 +215,9 @@ template <class T> void launch_inverse(const InvTask* d_tasks, int ntasks, int m
                                        int* d_flags, hipStream_t s, bool unblocked);
 // LDS-resident variants; `lds` is the dynamic shared memory per workgroup
 template <class T> void launch_qr_lds(const QrTask* d_tasks, int ntasks, size_t lds, hipStream_t s);
-template <class T> void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, hipStream_t s);
+// max_q: the widest core (the global-memory variant keeps its pivot map in LDS)
+template <class T> void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, int max_q,
+                                    hipStream_t s);
 // threads: the workgroup size that gives every core of the launch one pass
 // per round of its LDS-resident sweeps (rounded up to 256, 512 or 1024); for
 // the blocked sweeps in global memory (lds = 0), above 512 when a vector is
@@ -296,7 +298,8 @@ inline size_t lds_bytes_svd_wave(const SvdTask& t, size_t w) {
 // size (0: such cores take the two-kernel path, the faster one at the n = 128
 // benchmark shapes; acr_options_t.svd_fused_lds / acr_autotune change it)
 constexpr size_t kFusedLds = 0;
-inline size_t lds_bytes_qrcp(const SvdTask& t) { return ((size_t)(t.p | 1) * t.q + t.q) * 8 + (size_t)t.q * 4; }
+// C (ld p|1), q norms, q pivots, the q-entry position -> column map
+inline size_t lds_bytes_qrcp(const SvdTask& t) { return ((size_t)(t.p | 1) * t.q + t.q) * 8 + (size_t)t.q * 8; }
 inline size_t lds_bytes_svd_block(const SvdTask& t) {
   const size_t lc = t.p | 1;
   return (lc * t.q + t.q) * 8 + (size_t)2 * t.q * 4;

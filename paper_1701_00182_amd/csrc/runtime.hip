@@ -847,7 +847,9 @@ template <class T> void Exec::svd(std::vector<SvdTask>& t, double eps, int* d_tv
     }
     const SvdTask* dt = upload(b);
     const int n = (int)b.size();
-    submit([=](hipStream_t s) { launch_qrcp<T>(dt, n, delta, lds, s); }, w);
+    int max_q = 1;
+    for (auto& x : b) max_q = std::max(max_q, x.q);
+    submit([=](hipStream_t s) { launch_qrcp<T>(dt, n, delta, lds, max_q, s); }, w);
   };
   auto jacobi_batch = [this, eps, fl](const std::vector<SvdTask>& b, size_t lds) {
     Work w;

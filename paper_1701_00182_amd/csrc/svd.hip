@@ -140,19 +140,22 @@ __device__ __forceinline__ void core_product_mfma(const SvdTask& t, double* C, i
 }
 
 // Reflector j of the pivoted QR, v = (1, x_{j+1..} * scale) with factor tj,
-// applied to the trailing columns j+1.. of C (groups of G lanes, one column
-// per group at a time), and the squared norms of their rows j+1.. written to
-// nrm.  With NU > 0 each lane holds NU = ceil((p - j) / G) rows of v and of
+// applied to the columns in pivot positions j+1.. (column colp[c] of C, with
+// this step's exchange of positions j and pc applied; groups of G lanes, one
+// column per group at a time), and the squared norms of their rows j+1..
+// written to nrm by position.  With NU > 0 each lane holds NU = ceil((p - j) / G) rows of v and of
 // the column in registers and the loops unroll without branches: rows of
 // lanes before the last are full, the last one loads through a clamped index
 // and stores under a mask.  NU = 0 streams the rows.
 template <int NT, int NU>
 __device__ __forceinline__ void qrcp_update(double* C, int64_t lc, int p, int q, int j, const double* col,
-                                            double scale, double tj, int G, double* nrm) {
+                                            double scale, double tj, int G, double* nrm, const int* colp, int pc) {
   const int groups = NT / G, gi = threadIdx.x / G, gl = threadIdx.x % G;
+  // column at position c > j: the map before this step's pivot exchange
+  auto column = [&](int c) { return C + (int64_t)(c == pc ? colp[j] : colp[c]) * lc; };
   if (NU == 0) {
     for (int c = j + 1 + gi; c < q; c += groups) {
-      double* ac = C + c * lc;
+      double* ac = column(c);
       if (tj != 0.0) {
         double w = 0.0;
         for (int i = j + gl; i < p; i += G) w += (i == j ? 1.0 : col[i] * scale) * ac[i];
@@ -178,7 +181,7 @@ __device__ __forceinline__ void qrcp_update(double* C, int64_t lc, int p, int q,
     v[u] = (u + 1 < R || tail_ok) ? vv : 0.0;
   }
   for (int c = j + 1 + gi; c < q; c += groups) {
-    double* ac = C + c * lc;
+    double* ac = column(c);
     double a[R];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
@@ -207,13 +210,14 @@ __device__ __forceinline__ void qrcp_update(double* C, int64_t lc, int p, int q,
 // Householder QR with column pivoting of C (p x q, column stride lc), stopped
 // before step j once the trailing block (rows and columns j..) has Frobenius
 // norm at most delta times the largest column norm of C; returns the number of
-// reflectors t.  R is left in the upper
-// triangle of the first t rows (the entries below it are left unspecified).
-// All threads call it.  Column slices of up to CAP rows per lane are held in
+// reflectors t.  The columns are not moved: the column of R in pivot position
+// c is column colp[c] of C (rows a <= c of it, for a < t; the entries below
+// are left unspecified), and perm[c] is its original index.  All threads call
+// it.  Column slices of up to CAP rows per lane are held in
 // registers.
 template <int NT, int CAP>
-__device__ __forceinline__ int qrcp_body(double* C, int64_t lc, int p, int q, double* nrm, int* perm, double delta,
-                                         double* red, int* redi) {
+__device__ __forceinline__ int qrcp_body(double* C, int64_t lc, int p, int q, double* nrm, int* perm, int* colp,
+                                         double delta, double* red, int* redi) {
   const int mn = p < q ? p : q;
   double mx = 0.0;
   {
@@ -223,7 +227,7 @@ __device__ __forceinline__ int qrcp_body(double* C, int64_t lc, int p, int q, do
       double s = 0.0;
       for (int i = gl; i < p; i += G) s += C[i + c * lc] * C[i + c * lc];
       s = gsum2(s, G);
-      if (gl == 0) { nrm[c] = s; perm[c] = c; }
+      if (gl == 0) { nrm[c] = s; perm[c] = c; colp[c] = c; }
       mx = fmax(mx, s);
     }
   }
@@ -263,31 +267,22 @@ __device__ __forceinline__ int qrcp_body(double* C, int64_t lc, int p, int q, do
     bc = __builtin_amdgcn_readfirstlane(bc);
     rest = read_first_lane(rest);
     if (!(rest > thr2) || !(best > 0.0)) break;
+    // the pivot takes position j without moving data: the columns stay where
+    // they are and positions j and pc exchange their entries of the map colp
+    // (and of perm) after this step's last barrier; until then every thread
+    // reads the old map with the exchange applied.  The norms need no
+    // exchange: position pc's entry is rewritten by this step's update (its
+    // column is then the one that was at position j) and position j's is not
+    // read again.
     const int pc = bc;
-    if (pc != j) {
-      for (int i = threadIdx.x; i < p; i += NT) {
-        const double a = C[i + j * lc];
-        C[i + j * lc] = C[i + pc * lc];
-        C[i + pc * lc] = a;
-      }
-      if (threadIdx.x == 0) {
-        const double a = nrm[j];
-        nrm[j] = nrm[pc];
-        nrm[pc] = a;
-        const int b = perm[j];
-        perm[j] = perm[pc];
-        perm[pc] = b;
-      }
-      __syncthreads();
-    }
-    // Householder reflector of column j from its stored norm: nrm[j] holds the
-    // squared norm of rows j.. (recomputed exactly after the previous step), so
-    // the part below the diagonal is nrm[j] - x0^2 without another reduction.
-    // The reflector v = (1, x_{j+1..} * scale) is applied on the fly and not
-    // stored: only R is used afterwards.
-    double* col = C + j * lc;
+    // Householder reflector of the pivot column from its stored norm (best):
+    // the squared norm of rows j.. (recomputed exactly after the previous
+    // step), so the part below the diagonal is best - x0^2 without another
+    // reduction.  The reflector v = (1, x_{j+1..} * scale) is applied on the
+    // fly and not stored: only R is used afterwards.
+    double* col = C + (int64_t)colp[pc] * lc;
     const double x0 = col[j];
-    const double sigma = fmax(nrm[j] - x0 * x0, 0.0);
+    const double sigma = fmax(best - x0 * x0, 0.0);
     double tj = 0.0, scale = 0.0, beta = x0;
     if (sigma > 0.0) {
       const double nr = sqrt(x0 * x0 + sigma);
@@ -301,16 +296,28 @@ __device__ __forceinline__ int qrcp_body(double* C, int64_t lc, int p, int q, do
     const int nu = (p - j + G - 1) / G;
     switch (nu <= CAP ? nu : 0) {
 #define ACR_QRCP_NU(k) \
-  case k: qrcp_update<NT, (k <= CAP ? k : 0)>(C, lc, p, q, j, col, scale, tj, G, nrm); break;
+  case k: qrcp_update<NT, (k <= CAP ? k : 0)>(C, lc, p, q, j, col, scale, tj, G, nrm, colp, pc); break;
       ACR_QRCP_NU(1) ACR_QRCP_NU(2) ACR_QRCP_NU(3) ACR_QRCP_NU(4) ACR_QRCP_NU(5) ACR_QRCP_NU(6)
       ACR_QRCP_NU(7) ACR_QRCP_NU(8) ACR_QRCP_NU(9) ACR_QRCP_NU(10) ACR_QRCP_NU(11) ACR_QRCP_NU(12)
       ACR_QRCP_NU(13) ACR_QRCP_NU(14) ACR_QRCP_NU(15) ACR_QRCP_NU(16)
 #undef ACR_QRCP_NU
-      default: qrcp_update<NT, 0>(C, lc, p, q, j, col, scale, tj, G, nrm); break;
+      default: qrcp_update<NT, 0>(C, lc, p, q, j, col, scale, tj, G, nrm, colp, pc); break;
     }
     __syncthreads();
-    // every thread has read x0 and the column: the diagonal of R can be stored
-    if (threadIdx.x == 0) col[j] = beta;
+    // every thread has read x0, the column and the map: the diagonal of R can
+    // be stored and the exchange committed (the next reads of colp and perm
+    // follow the next step's first barrier)
+    if (threadIdx.x == 0) {
+      col[j] = beta;
+      if (pc != j) {
+        const int b = perm[j];
+        perm[j] = perm[pc];
+        perm[pc] = b;
+        const int d = colp[j];
+        colp[j] = colp[pc];
+        colp[pc] = d;
+      }
+    }
     tcount = j + 1;
   }
   __syncthreads();
@@ -333,15 +340,17 @@ __global__ __launch_bounds__(NT) void k_qrcp(const SvdTask* __restrict__ tasks, 
   double* C = LDS ? smc : t.C;
   double* nrm = LDS ? smc + (int64_t)lc * q : t.sig;
   int* perm = LDS ? reinterpret_cast<int*>(nrm + q) : t.perm;
+  // position -> column map: after perm in LDS, else all of the dynamic LDS
+  int* colp = LDS ? perm + q : reinterpret_cast<int*>(smc);
   __shared__ double red[NT / 64];
   __shared__ int redi[NT / 64];
   core_product_mfma<T, NT>(t, C, lc);
   __syncthreads();
-  const int tcount = qrcp_body<NT, LDS ? 12 : 8>(C, lc, p, q, nrm, perm, delta, red, redi);
+  const int tcount = qrcp_body<NT, LDS ? 12 : 8>(C, lc, p, q, nrm, perm, colp, delta, red, redi);
   double* Wt = t.Y;
   for (int64_t e = threadIdx.x; e < (int64_t)q * tcount; e += NT) {
     const int c = (int)(e % q), a = (int)(e / q);
-    Wt[perm[c] + (int64_t)a * q] = c >= a ? C[a + (int64_t)c * lc] : 0.0;
+    Wt[perm[c] + (int64_t)a * q] = c >= a ? C[a + (int64_t)colp[c] * lc] : 0.0;
   }
   if (threadIdx.x == 0) *t.t_out = tcount;
 }
@@ -1167,13 +1176,14 @@ __global__ __launch_bounds__(NT) void k_svd_block(const SvdTask* __restrict__ ta
   __shared__ int redi[NT / 64];
   core_product_mfma<T, NT>(t, C, lc);
   __syncthreads();
-  const int n = qrcp_body<NT, 12>(C, lc, p, q, nrm, perm, delta, red, redi);
+  // the pivot map of the QR in the sweeps' scratch
+  const int n = qrcp_body<NT, 12>(C, lc, p, q, nrm, perm, ord, delta, red, redi);
   // W^T = P R^T (q x n) through the global workspace back into the C region:
   // the sweeps then run on contiguous columns
   double* Wt = t.Y;
   for (int e = threadIdx.x; e < q * n; e += NT) {
     const int c = e % q, a = e / q;
-    Wt[perm[c] + a * q] = c >= a ? C[a + c * lc] : 0.0;
+    Wt[perm[c] + a * q] = c >= a ? C[a + ord[c] * lc] : 0.0;
   }
   __threadfence();
   __syncthreads();
@@ -1416,10 +1426,13 @@ template <class K> void allow(K kernel, size_t bytes) {
 // compute unit; the extra wavefronts hide latency and shorten each core's
 // critical path), with 256 threads otherwise.
 template <class T>
-void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, hipStream_t s) {
+void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, int max_q, hipStream_t s) {
   if (ntasks <= 0) return;
   if (lds == 0) {
-    hipLaunchKernelGGL((k_qrcp<T, false, 1024>), dim3(ntasks), dim3(1024), 0, s, d_tasks, delta);
+    // C in global memory, the position -> column map in LDS
+    const size_t map = (size_t)max_q * sizeof(int);
+    allow(k_qrcp<T, false, 1024>, map);
+    hipLaunchKernelGGL((k_qrcp<T, false, 1024>), dim3(ntasks), dim3(1024), map, s, d_tasks, delta);
     return;
   }
   if (lds <= kSmallLds) {
@@ -1510,7 +1523,7 @@ void launch_tri_copy(const TriCopyTask* d_tasks, int ntasks, hipStream_t s) {
 }
 
 #define ACR_SVD_INST(T)                                                                                     \
-  template void launch_qrcp<T>(const SvdTask*, int, double, size_t, hipStream_t);                           \
+  template void launch_qrcp<T>(const SvdTask*, int, double, size_t, int, hipStream_t);                           \
   template void launch_jacobi<T>(const SvdTask*, int, double, int*, size_t, int, hipStream_t);                   \
   template void launch_svd_block<T>(const SvdTask*, int, double, double, int*, size_t, hipStream_t);        \
   template void launch_svd_wave<T>(const SvdTask*, int, double, double, int*, size_t, hipStream_t);         \
