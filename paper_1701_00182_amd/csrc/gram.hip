@@ -514,9 +514,10 @@ __global__ __launch_bounds__(256) void k_materialize_r(const PcholTask* __restri
 
 // W = P1 L11^{-T} Z scattered into r x k (precision T): blocked back
 // substitution, one workgroup per (task, chunk of kc right-hand sides) with
-// the chunk of Z in LDS.  Each 32-row diagonal block is staged in LDS and
-// solved by the first wavefront (one lane per right-hand side), then
-// subtracted from the rows above it by the whole workgroup.  LDS:
+// the chunk of Z in LDS.  Each 32-row diagonal block is staged in LDS (with
+// the reciprocals of its diagonal) and solved by the first wavefront, one lane
+// per right-hand side with the block's 32 entries in registers, right-looking,
+// then subtracted from the rows above it by the whole workgroup.  LDS:
 // r1 * kc + 32 * 32 doubles.
 template <class T>
 __global__ __launch_bounds__(256) void k_wtilde(const WtTask* __restrict__ tasks, int kc) {
@@ -532,22 +533,39 @@ __global__ __launch_bounds__(256) void k_wtilde(const WtTask* __restrict__ tasks
       [&](int64_t e, double v) { zs[e] = v; });
   __syncthreads();
   double* Ld = zs + (int64_t)r1 * kc;   // diagonal block: Ld[i + c * 32] = L(lo + i, lo + c)
+  __shared__ double rd[32];             // 1 / L(lo + i, lo + i)
   for (int hi = r1; hi > 0; hi -= 32) {
     const int lo = hi - 32 > 0 ? hi - 32 : 0;
     const int h = hi - lo;
     for (int e = threadIdx.x; e < h * h; e += 256) {
       const int i = e % h, c = e / h;
-      if (i >= c) Ld[i + c * 32] = L[(lo + i) + (int64_t)(lo + c) * r];
+      if (i >= c) {
+        const double v = L[(lo + i) + (int64_t)(lo + c) * r];
+        Ld[i + c * 32] = v;
+        if (i == c) rd[i] = 1.0 / v;
+      }
     }
     __syncthreads();
     if (threadIdx.x < nc) {
-      double* z = zs + threadIdx.x * r1;
-      for (int a = hi - 1; a >= lo; --a) {
-        const double* la = Ld + (a - lo) * 32 - lo;   // la[b] = L(b, a), b in [a, hi)
-        double s = z[a];
-        for (int b = a + 1; b < hi; ++b) s -= la[b] * z[b];
-        z[a] = s / la[a];
+      // right-looking: once z[a] is final, its term L(a, b) z[a] leaves every
+      // row b < a of the block at once (independent updates of the block's z
+      // held in registers, instead of a dependent dot product per row)
+      double* z = zs + threadIdx.x * r1 + lo;
+      double zr[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) zr[u] = u < h ? z[u] : 0.0;
+#pragma unroll
+      for (int a = 31; a >= 0; --a) {
+        if (a < h) {
+          const double za = zr[a] * rd[a];
+          zr[a] = za;
+#pragma unroll
+          for (int b = 0; b < a; ++b) zr[b] = fma(-Ld[a + b * 32], za, zr[b]);
+        }
       }
+#pragma unroll
+      for (int u = 0; u < 32; ++u)
+        if (u < h) z[u] = zr[u];
     }
     __syncthreads();
     // z[b, c] -= sum over a in [lo, hi) of L(a, b) z[a, c] for b < lo: a thread
