@@ -270,6 +270,7 @@ template <class T> void launch_apply_leaf(const LeafTask* d_tasks, int ntasks, b
 constexpr size_t kLdsBudget = 156 * 1024;
 constexpr size_t kLdsPerCu = 160 * 1024;   // LDS of one compute unit
 constexpr size_t kSmallLds = 32 * 1024;   // LDS-resident tasks up to this size use 256-thread workgroups
+constexpr size_t kMidLds = 80 * 1024;     // pivoted QR of cores up to this size on 512-thread workgroups
 inline size_t lds_bytes_qr(const QrTask& t, size_t w) { return (size_t)t.m * t.r * w; }
 // Row stride of W^T (q x t) in LDS for the scalar sweeps: q rounded up to 8
 // modulo 16 doubles, so that the vectors that the 8-lane groups of a

@@ -1440,6 +1440,11 @@ void launch_qrcp(const SvdTask* d_tasks, int ntasks, double delta, size_t lds, i
     hipLaunchKernelGGL((k_qrcp<T, true, 256>), dim3(ntasks), dim3(256), lds, s, d_tasks, delta);
     return;
   }
+  if (lds <= kMidLds) {
+    allow(k_qrcp<T, true, 512>, lds);
+    hipLaunchKernelGGL((k_qrcp<T, true, 512>), dim3(ntasks), dim3(512), lds, s, d_tasks, delta);
+    return;
+  }
   allow(k_qrcp<T, true, 1024>, lds);
   hipLaunchKernelGGL((k_qrcp<T, true, 1024>), dim3(ntasks), dim3(1024), lds, s, d_tasks, delta);
 }
