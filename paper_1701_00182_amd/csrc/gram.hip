@@ -384,6 +384,10 @@ __global__ __launch_bounds__(NT) void k_pchol_reg(const PcholTask* __restrict__ 
   // the Gram buffer receives the columns of L in original row order
   auto* Lo = to_global(const_cast<double*>(t.G));
   unsigned dead = 0;   // this thread's diagonal entries already eliminated (bit a)
+  // the rows i0 + a and columns k0 + c of this thread's tile eliminated by
+  // earlier pivots (bit a / c): the pivot column is formed without reading
+  // the shared flags
+  unsigned rdead = 0, cdead = 0;
   int rank = 0;
   // columns j0 .. j0 + n - 1 of the LDS buffer to global memory
   auto flush = [&](int j0, int n) {
@@ -410,7 +414,7 @@ __global__ __launch_bounds__(NT) void k_pchol_reg(const PcholTask* __restrict__ 
         double x = 0.0;
 #pragma unroll
         for (int c = 0; c < TB; ++c) x = k0 + c == p ? v[a][c] : x;
-        if (i < r) lv[i] = (i == p || alive[i]) ? x * inv : 0.0;
+        if (i < r) lv[i] = (i == p || !((rdead >> a) & 1u)) ? x * inv : 0.0;
       }
     }
     if (R >= 0 && R == pb && C < R) {
@@ -421,9 +425,11 @@ __global__ __launch_bounds__(NT) void k_pchol_reg(const PcholTask* __restrict__ 
         double x = 0.0;
 #pragma unroll
         for (int a = 0; a < TB; ++a) x = i0 + a == p ? v[a][c] : x;
-        if (k < r) lv[k] = alive[k] ? x * inv : 0.0;
+        if (k < r) lv[k] = !((cdead >> c) & 1u) ? x * inv : 0.0;
       }
     }
+    if (p >= i0 && p < i0 + TB) rdead |= 1u << (p - i0);
+    if (p >= k0 && p < k0 + TB) cdead |= 1u << (p - k0);
     if (threadIdx.x == 0) {
       dpiv[p] = b;
       const int q = posof[p], pj = perm[j];
